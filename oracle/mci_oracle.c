@@ -1,0 +1,496 @@
+/*
+ * mci_oracle.c -- plain FP64 CPU oracle for FFT multichannel interpolation (MCI),
+ * Cheng & Kou, "FFT Multichannel Interpolation and Application to Image
+ * Super-resolution" (arXiv:1802.10291).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is built into liborc_mci.so and is loaded by
+ * the test-suite, the smoke check and the CPU-baseline leg of the benchmark.  The
+ * product library (paper_1802_10291_amd) never includes, links or calls it, and it
+ * shares no code, header or table with the GPU path.
+ *
+ * What it computes is the plain definition of the method, written out with no
+ * transform algorithm at all:
+ *   1. the DFT of each channel's samples, summed directly in O(N^2)   (Lemma 3.1, eq. sumformgm)
+ *   2. per residue n in I_1 the M x M system  A_n H_n = D_n, solved by Gaussian
+ *      elimination with partial pivoting                               (eq. defH, eq. matrixeqn1)
+ *   3. an output operator applied coefficient-wise (identity, circular Hilbert
+ *      transform -i sgn n, derivative (i n)^q)                          (Section 2; Ex. 3.6, 3.11; end of Section 3)
+ *   4. the trigonometric sum  sum_{n in band} a(n) e^{i n t_j}  evaluated directly at
+ *      every output point t_j = 2 pi j / n_out                          (eq. bandsignal, eq. DFTexpression)
+ * plus an independent second route, the sampling series of Theorem 3.3
+ * (eq. drictexpression) with the interpolation functions y_m of eq. ym / eq. defrm.
+ *
+ * Notation: the paper's L (samples per channel) is called N here, the band
+ * I^N = [N_1, N_2] is [n1, n1 + mu - 1] with mu = M*N, and I_1 = [n1, n1 + N - 1].
+ * Channel k (0-based) has Fourier multiplier b_k(n); H_n[j][k] = b_k(n + j N).
+ *
+ * Numbers are IEEE FP64 with round-to-nearest.  Every phase e^{+-2 pi i n p / N} is read
+ * from a table indexed by the exactly reduced integer (n p) mod N, so no large
+ * argument ever reaches sin/cos.
+ *
+ * Readings of points the paper leaves open (each is listed in the design notes):
+ *  - real mode returns Re of the reconstruction (pinned by Table 1);
+ *  - outputs on a grid coarser than the band fold by accumulation, since
+ *    e^{i n t_j} only depends on n mod n_out;
+ *  - each equation of the per-residue system is divided by its largest coefficient
+ *    before elimination (row equilibration: it does not change the solution, it keeps
+ *    derivative channels, whose rows scale like (M N)^k, from losing digits);
+ *  - a residue whose system is singular is an error unless the caller allows the
+ *    convention of Remark 3.4 (set the whole residue's coefficients to zero).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+enum { ORC_MULT_DERIV = 0, ORC_MULT_HILBERT = 1, ORC_MULT_TABLE = 2 };
+enum { ORC_OUT_IDENTITY = 0, ORC_OUT_HILBERT = 1, ORC_OUT_DERIV = 2 };
+enum { ORC_OK = 0, ORC_E_INVALID = 1, ORC_E_SINGULAR = 2, ORC_E_NOMEM = 5 };
+
+#define ORC_MAX_M 8
+
+/* A channel set: M multipliers b_k, each either (i n)^order, -i sgn n, or a table of
+ * values for n in [n1, n1 + M N) stored as interleaved (re, im) doubles. */
+typedef struct {
+  int M;
+  int64_t N, n1;
+  const int *kinds, *orders;
+  const double *tables; /* M blocks of 2*mu doubles, or NULL */
+} chanset;
+
+static double two_pi(void) { return 6.283185307179586476925286766559; }
+
+/* (i n)^q with the power of i taken exactly. */
+static cplx ipow_times(int64_t n, int q) {
+  double mag = 1.0;
+  for (int r = 0; r < q; ++r) mag *= (double)n;
+  switch (q & 3) {
+    case 0: return mag;
+    case 1: return I * mag;
+    case 2: return -mag;
+    default: return -I * mag;
+  }
+}
+
+static double sgn(int64_t n) { return n > 0 ? 1.0 : (n < 0 ? -1.0 : 0.0); }
+
+/* Fourier multiplier b_k(n) of channel k (eq. sysfunction). */
+static cplx mult(const chanset *cs, int k, int64_t n) {
+  switch (cs->kinds[k]) {
+    case ORC_MULT_DERIV: return ipow_times(n, cs->orders[k]);
+    case ORC_MULT_HILBERT: return -I * sgn(n);
+    default: {
+      int64_t mu = (int64_t)cs->M * cs->N;
+      int64_t off = n - cs->n1;
+      if (off < 0 || off >= mu) return 0.0;
+      const double *t = cs->tables + (size_t)k * 2 * mu;
+      return t[2 * off] + I * t[2 * off + 1];
+    }
+  }
+}
+
+/* Output operator o(n) applied to a reconstructed coefficient. */
+static cplx outop(int op, int order, int64_t n) {
+  switch (op) {
+    case ORC_OUT_IDENTITY: return 1.0;
+    case ORC_OUT_HILBERT: return -I * sgn(n);
+    default: return ipow_times(n, order);
+  }
+}
+
+/* Solve G x = r for an M x M complex system by Gaussian elimination with partial
+ * pivoting after dividing every equation by its largest |coefficient|.  G is row-major
+ * and overwritten.  Returns 0, or 1 if the system is singular. */
+static int gauss_solve(int M, cplx *G, cplx *r, cplx *x) {
+  for (int i = 0; i < M; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < M; ++j) s = fmax(s, cabs(G[i * M + j]));
+    if (s == 0.0) return 1;
+    for (int j = 0; j < M; ++j) G[i * M + j] /= s;
+    r[i] /= s;
+  }
+  for (int c = 0; c < M; ++c) {
+    int piv = c;
+    double best = cabs(G[c * M + c]);
+    for (int i = c + 1; i < M; ++i) {
+      double v = cabs(G[i * M + c]);
+      if (v > best) { best = v; piv = i; }
+    }
+    if (best <= 1e-13) return 1;
+    if (piv != c) {
+      for (int j = 0; j < M; ++j) {
+        cplx t = G[c * M + j]; G[c * M + j] = G[piv * M + j]; G[piv * M + j] = t;
+      }
+      cplx t = r[c]; r[c] = r[piv]; r[piv] = t;
+    }
+    for (int i = c + 1; i < M; ++i) {
+      cplx f = G[i * M + c] / G[c * M + c];
+      for (int j = c; j < M; ++j) G[i * M + j] -= f * G[c * M + j];
+      r[i] -= f * r[c];
+    }
+  }
+  for (int i = M - 1; i >= 0; --i) {
+    cplx s = r[i];
+    for (int j = i + 1; j < M; ++j) s -= G[i * M + j] * x[j];
+    x[i] = s / G[i * M + i];
+  }
+  return 0;
+}
+
+/* The per-residue system of eq. matrixeqn1 written as H_n^T A_n^T = D_n^T:
+ * equation k (channel) reads  sum_j b_k(n + jN) a(n + jN) = d_k(n). */
+static void build_system(const chanset *cs, int64_t n, cplx *G) {
+  const int M = cs->M;
+  for (int k = 0; k < M; ++k)
+    for (int j = 0; j < M; ++j) G[k * M + j] = mult(cs, k, n + (int64_t)j * cs->N);
+}
+
+/* d_m(n) for n = n1 + i, i in [0, N): (1/N) sum_p g_m[p] e^{-2 pi i n p / N}
+ * (Lemma 3.1: the samples are the inverse DFT of d_m over I_1, with the 1/L factor). */
+static void direct_dft(int64_t N, int64_t n1, const cplx *g, const cplx *W, cplx *d) {
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t n = n1 + i;
+    int64_t nm = ((n % N) + N) % N;
+    cplx s = 0.0;
+    for (int64_t p = 0; p < N; ++p) s += g[p] * W[(nm * p) % N];
+    d[i] = s / (double)N;
+  }
+}
+
+static cplx *phase_table(int64_t n, double sign) {
+  cplx *W = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+  if (!W) return NULL;
+  for (int64_t k = 0; k < n; ++k) {
+    double a = sign * two_pi() * (double)k / (double)n;
+    W[k] = cos(a) + I * sin(a);
+  }
+  return W;
+}
+
+static int check_chanset(const chanset *cs) {
+  if (cs->M < 1 || cs->M > ORC_MAX_M || cs->N < 1) return ORC_E_INVALID;
+  for (int k = 0; k < cs->M; ++k) {
+    int kd = cs->kinds[k];
+    if (kd != ORC_MULT_DERIV && kd != ORC_MULT_HILBERT && kd != ORC_MULT_TABLE) return ORC_E_INVALID;
+    if (kd == ORC_MULT_TABLE && !cs->tables) return ORC_E_INVALID;
+    if (kd == ORC_MULT_DERIV && (cs->orders[k] < 0 || cs->orders[k] > 16)) return ORC_E_INVALID;
+  }
+  return ORC_OK;
+}
+
+/* Recovered band coefficients a(n), n in [n1, n1 + mu), for one signal whose channel
+ * spectra d[M][N] are given.  Returns ORC_OK or ORC_E_SINGULAR (first bad residue in
+ * *bad). */
+static int solve_band(const chanset *cs, const cplx *d, int allow_zero, cplx *a, int64_t *bad) {
+  const int M = cs->M;
+  const int64_t N = cs->N;
+  int status = ORC_OK;
+  for (int64_t i = 0; i < N; ++i) {
+    cplx G[ORC_MAX_M * ORC_MAX_M], r[ORC_MAX_M], x[ORC_MAX_M];
+    build_system(cs, cs->n1 + i, G);
+    for (int k = 0; k < M; ++k) r[k] = d[(size_t)k * N + i];
+    if (gauss_solve(M, G, r, x)) {
+      if (!allow_zero) {
+        if (status == ORC_OK) { status = ORC_E_SINGULAR; if (bad) *bad = cs->n1 + i; }
+        for (int j = 0; j < M; ++j) x[j] = 0.0;
+      } else {
+        for (int j = 0; j < M; ++j) x[j] = 0.0; /* Remark 3.4 */
+      }
+    }
+    for (int j = 0; j < M; ++j) a[i + (int64_t)j * N] = x[j];
+  }
+  return status;
+}
+
+static void load_signal(int64_t M, int64_t N, int real_io, const double *g, cplx *out) {
+  for (int64_t q = 0; q < M * N; ++q)
+    out[q] = real_io ? g[q] : g[2 * q] + I * g[2 * q + 1];
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Exported entry points (ctypes).                                                 */
+/* ------------------------------------------------------------------------------ */
+
+/* Channel spectra d_m(n1 + i), i in [0, N), interleaved complex [batch][M][N][2]. */
+int orc_channel_dft(int M, int64_t N, int64_t n1, int real_io, int64_t batch, const double *g, double *d_out) {
+  if (M < 1 || N < 1 || batch < 0) return ORC_E_INVALID;
+  cplx *W = phase_table(N, -1.0);
+  if (!W) return ORC_E_NOMEM;
+  int rc = ORC_OK;
+#pragma omp parallel for schedule(dynamic) collapse(2)
+  for (int64_t b = 0; b < batch; ++b)
+    for (int m = 0; m < M; ++m) {
+      cplx *gs = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+      cplx *ds = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+      if (!gs || !ds) { rc = ORC_E_NOMEM; free(gs); free(ds); continue; }
+      const size_t sig = ((size_t)b * M + m) * (size_t)N;
+      load_signal(1, N, real_io, g + (real_io ? sig : 2 * sig), gs);
+      direct_dft(N, n1, gs, W, ds);
+      for (int64_t i = 0; i < N; ++i) {
+        d_out[2 * (sig + i)] = creal(ds[i]);
+        d_out[2 * (sig + i) + 1] = cimag(ds[i]);
+      }
+      free(gs); free(ds);
+    }
+  free(W);
+  return rc;
+}
+
+/* Q_n = H_n^{-1} for every residue n = n1 + i, as [N][M][M][2] (row m, column k =
+ * q_{mk}(n)).  Row m of Q_n is the solution A of A H_n = e_m, so the same elimination
+ * as the reconstruction is used.  flags[i] = 1 marks a singular residue (Q_n set to
+ * zero there). */
+int orc_inverse_tables(int M, int64_t N, int64_t n1, const int *kinds, const int *orders, const double *tables,
+                       double *q_out, int *flags) {
+  chanset cs = {M, N, n1, kinds, orders, tables};
+  if (check_chanset(&cs)) return ORC_E_INVALID;
+  for (int64_t i = 0; i < N; ++i) {
+    int sing = 0;
+    for (int m = 0; m < M && !sing; ++m) {
+      cplx G[ORC_MAX_M * ORC_MAX_M], r[ORC_MAX_M], x[ORC_MAX_M];
+      build_system(&cs, n1 + i, G);
+      for (int k = 0; k < M; ++k) r[k] = (k == m) ? 1.0 : 0.0;
+      if (gauss_solve(M, G, r, x)) { sing = 1; break; }
+      for (int k = 0; k < M; ++k) {
+        size_t o = (((size_t)i * M + m) * M + k) * 2;
+        q_out[o] = creal(x[k]);
+        q_out[o + 1] = cimag(x[k]);
+      }
+    }
+    if (sing)
+      for (int q = 0; q < M * M * 2; ++q) q_out[(size_t)i * M * M * 2 + q] = 0.0;
+    flags[i] = sing;
+  }
+  return ORC_OK;
+}
+
+/* Recovered band coefficients a(n1 + i), i in [0, mu), [batch][mu][2], before any
+ * output operator.  *bad receives the first singular residue when the result is
+ * ORC_E_SINGULAR. */
+int orc_recover_band(int M, int64_t N, int64_t n1, const int *kinds, const int *orders, const double *tables,
+                     int real_io, int allow_zero, int64_t batch, const double *g, double *a_out, int64_t *bad) {
+  chanset cs = {M, N, n1, kinds, orders, tables};
+  if (check_chanset(&cs) || batch < 0) return ORC_E_INVALID;
+  const int64_t mu = (int64_t)M * N;
+  cplx *W = phase_table(N, -1.0);
+  if (!W) return ORC_E_NOMEM;
+  int rc = ORC_OK;
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t b = 0; b < batch; ++b) {
+    cplx *gs = (cplx *)malloc(sizeof(cplx) * (size_t)mu);
+    cplx *ds = (cplx *)malloc(sizeof(cplx) * (size_t)mu);
+    cplx *as = (cplx *)malloc(sizeof(cplx) * (size_t)mu);
+    if (!gs || !ds || !as) { rc = ORC_E_NOMEM; free(gs); free(ds); free(as); continue; }
+    load_signal(M, N, real_io, g + (size_t)b * mu * (real_io ? 1 : 2), gs);
+    for (int m = 0; m < M; ++m) direct_dft(N, n1, gs + (size_t)m * N, W, ds + (size_t)m * N);
+    int64_t badb = 0;
+    int st = solve_band(&cs, ds, allow_zero, as, &badb);
+    if (st != ORC_OK) {
+#pragma omp critical
+      { if (rc == ORC_OK) { rc = st; if (bad) *bad = badb; } }
+    }
+    for (int64_t i = 0; i < mu; ++i) {
+      a_out[2 * ((size_t)b * mu + i)] = creal(as[i]);
+      a_out[2 * ((size_t)b * mu + i) + 1] = cimag(as[i]);
+    }
+    free(gs); free(ds); free(as);
+  }
+  free(W);
+  return rc;
+}
+
+/* Full reconstruction on the output grid t_j = 2 pi j / n_out.
+ *   g : [batch][M][N] real, or [batch][M][N][2] complex
+ *   y : [batch][n_ops][n_out] real (Re of the reconstruction), or [...][2] complex
+ * ops[o] / op_orders[o] choose the output operator of output o. */
+int orc_reconstruct_1d(int M, int64_t N, int64_t n1, const int *kinds, const int *orders, const double *tables,
+                       int n_ops, const int *ops, const int *op_orders, int64_t n_out, int real_io, int allow_zero,
+                       int64_t batch, const double *g, double *y, int64_t *bad) {
+  chanset cs = {M, N, n1, kinds, orders, tables};
+  if (check_chanset(&cs) || n_ops < 1 || n_out < 1 || batch < 0) return ORC_E_INVALID;
+  for (int o = 0; o < n_ops; ++o)
+    if (ops[o] < ORC_OUT_IDENTITY || ops[o] > ORC_OUT_DERIV) return ORC_E_INVALID;
+  const int64_t mu = (int64_t)M * N;
+  cplx *W = phase_table(N, -1.0);
+  cplx *E = phase_table(n_out, +1.0);
+  if (!W || !E) { free(W); free(E); return ORC_E_NOMEM; }
+  int rc = ORC_OK;
+  for (int64_t b = 0; b < batch && rc != ORC_E_NOMEM; ++b) {
+    cplx *gs = (cplx *)malloc(sizeof(cplx) * (size_t)mu);
+    cplx *ds = (cplx *)malloc(sizeof(cplx) * (size_t)mu);
+    cplx *as = (cplx *)malloc(sizeof(cplx) * (size_t)mu);
+    cplx *cs_ = (cplx *)malloc(sizeof(cplx) * (size_t)mu);
+    if (!gs || !ds || !as || !cs_) { rc = ORC_E_NOMEM; free(gs); free(ds); free(as); free(cs_); break; }
+    load_signal(M, N, real_io, g + (size_t)b * mu * (real_io ? 1 : 2), gs);
+#pragma omp parallel for schedule(static)
+    for (int m = 0; m < M; ++m) direct_dft(N, n1, gs + (size_t)m * N, W, ds + (size_t)m * N);
+    int64_t badb = 0;
+    int st = solve_band(&cs, ds, allow_zero, as, &badb);
+    if (st != ORC_OK && rc == ORC_OK) { rc = st; if (bad) *bad = badb; }
+    for (int o = 0; o < n_ops; ++o) {
+      for (int64_t i = 0; i < mu; ++i) cs_[i] = outop(ops[o], op_orders[o], n1 + i) * as[i];
+      double *yo = y + ((size_t)b * n_ops + o) * (size_t)n_out * (real_io ? 1 : 2);
+#pragma omp parallel for schedule(static)
+      for (int64_t j0 = 0; j0 < n_out; j0 += 64) {
+        int64_t cnt = (n_out - j0) < 64 ? (n_out - j0) : 64;
+        for (int64_t j = j0; j < j0 + cnt; ++j) {
+          cplx s = 0.0;
+          for (int64_t i = 0; i < mu; ++i) {
+            int64_t n = n1 + i;
+            int64_t nm = ((n % n_out) + n_out) % n_out;
+            s += cs_[i] * E[(nm * j) % n_out];
+          }
+          if (real_io) yo[j] = creal(s);
+          else { yo[2 * j] = creal(s); yo[2 * j + 1] = cimag(s); }
+        }
+      }
+    }
+    free(gs); free(ds); free(as); free(cs_);
+  }
+  free(W); free(E);
+  return rc;
+}
+
+/* Interpolation function y_m(t) = sum_{n in band} r_m(n) e^{i n t} of eq. ym, with
+ * r_m(n) = q_{m,k}(n - kN) on block I_{k+1} (eq. defrm, 0-based k), evaluated at
+ * arbitrary real t.  Output interleaved complex [n_t][2]. */
+int orc_interp_function(int M, int64_t N, int64_t n1, const int *kinds, const int *orders, const double *tables,
+                        int m, int64_t n_t, const double *t, double *out) {
+  chanset cs = {M, N, n1, kinds, orders, tables};
+  if (check_chanset(&cs) || m < 0 || m >= M) return ORC_E_INVALID;
+  const int64_t mu = (int64_t)M * N;
+  double *q = (double *)malloc(sizeof(double) * (size_t)N * M * M * 2);
+  int *fl = (int *)malloc(sizeof(int) * (size_t)N);
+  if (!q || !fl) { free(q); free(fl); return ORC_E_NOMEM; }
+  orc_inverse_tables(M, N, n1, kinds, orders, tables, q, fl);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < n_t; ++s) {
+    cplx acc = 0.0;
+    for (int64_t i = 0; i < mu; ++i) {
+      int64_t k = i / N, res = i % N; /* n = n1 + i lies in block k at residue n1 + res */
+      size_t o = (((size_t)res * M + m) * M + k) * 2;
+      cplx r = q[o] + I * q[o + 1];
+      acc += r * cexp(I * (double)(n1 + i) * t[s]);
+    }
+    out[2 * s] = creal(acc);
+    out[2 * s + 1] = cimag(acc);
+  }
+  free(q); free(fl);
+  return ORC_OK;
+}
+
+/* Sampling series of Theorem 3.3 (eq. drictexpression):
+ *   f(t) = (1/N) sum_m sum_p g_m(t_p) y_m(t - t_p),   t_p = 2 pi p / N,
+ * evaluated at arbitrary real t.  g is complex [M][N][2]; out is complex [n_t][2].
+ * This route never forms a DFT of the samples, so it checks the step order and the
+ * indexing of the main route independently.  Cost O(n_t M N mu): small cases only. */
+int orc_sampling_series(int M, int64_t N, int64_t n1, const int *kinds, const int *orders, const double *tables,
+                        const double *g, int64_t n_t, const double *t, double *out) {
+  chanset cs = {M, N, n1, kinds, orders, tables};
+  if (check_chanset(&cs)) return ORC_E_INVALID;
+  const int64_t mu = (int64_t)M * N;
+  double *q = (double *)malloc(sizeof(double) * (size_t)N * M * M * 2);
+  int *fl = (int *)malloc(sizeof(int) * (size_t)N);
+  if (!q || !fl) { free(q); free(fl); return ORC_E_NOMEM; }
+  orc_inverse_tables(M, N, n1, kinds, orders, tables, q, fl);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < n_t; ++s) {
+    cplx acc = 0.0;
+    for (int m = 0; m < M; ++m)
+      for (int64_t p = 0; p < N; ++p) {
+        double tp = two_pi() * (double)p / (double)N;
+        cplx gm = g[2 * ((size_t)m * N + p)] + I * g[2 * ((size_t)m * N + p) + 1];
+        cplx ym = 0.0;
+        for (int64_t i = 0; i < mu; ++i) {
+          int64_t k = i / N, res = i % N;
+          size_t o = (((size_t)res * M + m) * M + k) * 2;
+          ym += (q[o] + I * q[o + 1]) * cexp(I * (double)(n1 + i) * (t[s] - tp));
+        }
+        acc += gm * ym;
+      }
+    acc /= (double)N;
+    out[2 * s] = creal(acc);
+    out[2 * s + 1] = cimag(acc);
+  }
+  free(q); free(fl);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Separable 2-D upsampling (Section 5.2): every row, then every column of the result, */
+/* is reconstructed from two channels, the line itself and its three-point centred    */
+/* difference, on a grid s times finer.                                              */
+/* ------------------------------------------------------------------------------ */
+
+/* One 1-D pass on a real line x[0..N) with channels {x, D x}:
+ *   g_2[p] = (x[p+1] - x[p-1]) / (2h),  h = 2 pi / N, indices circular,
+ * multiplier b_2(n) = i n, band n1 = -floor((2N - 1) / 2), Re of the result at
+ * n_out = s N points.  W: e^{-2 pi i k/N}; E: e^{+2 pi i k/n_out}. */
+static int line_pass(int64_t N, int s, const double *x, int64_t xstride, double *y, int64_t ystride, const cplx *W,
+                     const cplx *E, cplx *work) {
+  static const int kinds[2] = {ORC_MULT_DERIV, ORC_MULT_DERIV};
+  static const int orders[2] = {0, 1};
+  const int64_t mu = 2 * N, n1 = -((2 * N - 1) / 2), n_out = (int64_t)s * N;
+  chanset cs = {2, N, n1, kinds, orders, NULL};
+  cplx *g = work, *d = work + mu, *a = work + 2 * mu;
+  const double inv2h = (double)N / (2.0 * two_pi());
+  for (int64_t p = 0; p < N; ++p) {
+    g[p] = x[p * xstride];
+    g[N + p] = (x[((p + 1) % N) * xstride] - x[((p + N - 1) % N) * xstride]) * inv2h;
+  }
+  direct_dft(N, n1, g, W, d);
+  direct_dft(N, n1, g + N, W, d + N);
+  if (solve_band(&cs, d, 0, a, NULL) != ORC_OK) return ORC_E_SINGULAR;
+  for (int64_t j = 0; j < n_out; ++j) {
+    cplx acc = 0.0;
+    for (int64_t i = 0; i < mu; ++i) {
+      int64_t n = n1 + i;
+      int64_t nm = ((n % n_out) + n_out) % n_out;
+      acc += a[i] * E[(nm * j) % n_out];
+    }
+    y[j * ystride] = creal(acc);
+  }
+  return ORC_OK;
+}
+
+/* x: [batch][h][w] real; y: [batch][s h][s w] real.  Rows first, then columns. */
+int orc_upsample_2d(int64_t batch, int64_t h, int64_t w, int s, const double *x, double *y) {
+  if (batch < 0 || h < 1 || w < 1 || s < 1) return ORC_E_INVALID;
+  const int64_t H = (int64_t)s * h, Wd = (int64_t)s * w;
+  cplx *Ww = phase_table(w, -1.0), *Ew = phase_table(Wd, +1.0);
+  cplx *Wh = phase_table(h, -1.0), *Eh = phase_table(H, +1.0);
+  double *mid = (double *)malloc(sizeof(double) * (size_t)h * Wd);
+  int rc = (Ww && Ew && Wh && Eh && mid) ? ORC_OK : ORC_E_NOMEM;
+  for (int64_t b = 0; b < batch && rc == ORC_OK; ++b) {
+    const double *xb = x + (size_t)b * h * w;
+    double *yb = y + (size_t)b * H * Wd;
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t r = 0; r < h; ++r) {
+      cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)6 * w);
+      if (!work || line_pass(w, s, xb + r * w, 1, mid + r * Wd, 1, Ww, Ew, work) != ORC_OK) rc = ORC_E_INVALID;
+      free(work);
+    }
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t c = 0; c < Wd; ++c) {
+      cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)6 * h);
+      if (!work || line_pass(h, s, mid + c, Wd, yb + c, Wd, Wh, Eh, work) != ORC_OK) rc = ORC_E_INVALID;
+      free(work);
+    }
+  }
+  free(Ww); free(Ew); free(Wh); free(Eh); free(mid);
+  return rc;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
