@@ -1,0 +1,186 @@
+/*
+ * mci.h -- C ABI of libmci, an MI355X (gfx950) implementation of FFT multichannel
+ * interpolation (MCI): Cheng & Kou, "FFT Multichannel Interpolation and Application
+ * to Image Super-resolution", arXiv:1802.10291.
+ *
+ * Problem (Section 3, Theorem 3.3): a signal f on [0, 2 pi) with Fourier coefficients
+ * a(n) on the band [n1, n1 + M N) is observed through M linear systems with Fourier
+ * multipliers b_m(n) (eq. sysfunction); each output g_m = f * h_m is sampled at the N
+ * points t_p = 2 pi p / N.  MCI recovers the band coefficients from the M N samples
+ * (exactly when f is in the band, Theorem 3.3; as the approximation operator of
+ * eq. "appxi operator" otherwise) and evaluates f, or a Fourier-multiplier image Qf of
+ * it (end of Section 3), on a uniform output grid t_j = 2 pi j / n_out.
+ *
+ * The path a library call runs, entirely on the GPU:
+ *   1. DFT of every channel (Lemma 3.1): d_m(n) = (1/N) sum_p g_m(t_p) e^{-i n t_p}
+ *   2. per residue n in I_1 = [n1, n1 + N), A_n = D_n H_n^{-1} (eq. matrixeqn1) with
+ *      H_n[j][k] = b_k(n + j N) (eq. defH), and the output operator o(n) applied
+ *   3. the recovered coefficients placed in a spectrum of length n_out at n mod n_out
+ *      (coefficients that land on the same bin add, so n_out < M N is exact)
+ *   4. an inverse DFT of length n_out (eq. DFTexpression evaluated on the grid)
+ * In real mode the result is the real part of the reconstruction.
+ *
+ * Conventions for every call:
+ *  - Every function returns an mci_status; nothing throws across the ABI.
+ *  - Array pointers passed to mci_reconstruct_1d / mci_upsample_2d are DEVICE pointers
+ *    owned by the caller; the library never frees them.  Descriptor pointers (channel
+ *    tables) are HOST pointers, read during the call and copied.
+ *  - Argument errors are reported synchronously, before any work is queued.
+ *  - A singular or ill-conditioned channel system is reported by mci_plan, never by a
+ *    reconstruction call.
+ *  - Reconstruction calls are asynchronous on the given stream; a kernel launch failure
+ *    is reported as MCI_E_DEVICE by that call.
+ *  - A plan is immutable after creation and may be used from several streams at once,
+ *    provided each call has its own workspace.
+ */
+#ifndef MCI_H
+#define MCI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MCI_OK = 0,
+  MCI_E_INVALID_ARG = 1,     /* bad pointer, size, enum value or layout */
+  MCI_E_SINGULAR = 2,        /* some H_n is singular and MCI_ALLOW_SINGULAR_ZERO is not set */
+  MCI_E_ILL_CONDITIONED = 3, /* max over n of cond_1 of the equilibrated H_n^T exceeds cond_max */
+  MCI_E_UNSUPPORTED = 4,     /* valid request this build does not implement */
+  MCI_E_OUT_OF_MEMORY = 5,   /* plan tables could not be allocated */
+  MCI_E_DEVICE = 6           /* a HIP runtime call or kernel launch failed */
+} mci_status;
+
+/* Fourier multiplier of one channel (eq. sysfunction). */
+typedef enum {
+  MCI_MULT_DERIV = 0,   /* b(n) = (i n)^order: the order-th derivative (Example 3.6) */
+  MCI_MULT_HILBERT = 1, /* b(n) = -i sgn n: the circular Hilbert transform (Section 2, Example 3.7) */
+  MCI_MULT_TABLE = 2    /* b(n) given for n in [n1, n1 + M N) */
+} mci_mult_kind;
+
+/* Output operator o(n), applied to the recovered coefficients (Example 3.11 and the
+ * closing paragraph of Section 3). */
+typedef enum {
+  MCI_OUT_IDENTITY = 0, /* f */
+  MCI_OUT_HILBERT = 1,  /* circular Hilbert transform of f: o(n) = -i sgn n */
+  MCI_OUT_DERIV = 2     /* order-th derivative of f: o(n) = (i n)^order */
+} mci_out_op;
+
+typedef enum { MCI_F32 = 0, MCI_F64 = 1 } mci_precision;
+
+/* Storage type of the caller's input/output arrays. */
+typedef enum {
+  MCI_STORE_NATIVE = 0, /* float for MCI_F32 plans, double for MCI_F64 plans */
+  MCI_STORE_F16 = 1     /* IEEE half (MCI_F32 plans only); arithmetic stays FP32 */
+} mci_storage;
+
+#define MCI_MAX_CHANNELS 4
+#define MCI_MAX_OPS 4
+#define MCI_N1_DEFAULT INT64_MIN       /* band start -floor((M N - 1) / 2) */
+#define MCI_ALLOW_SINGULAR_ZERO 1u     /* Remark 3.4: a singular H_n contributes zero coefficients */
+
+typedef struct {
+  int32_t kind;         /* mci_mult_kind */
+  int32_t order;        /* MCI_MULT_DERIV: derivative order, 0..8 */
+  const double* table;  /* MCI_MULT_TABLE: host array of 2*M*N doubles, (re, im) of b(n) for
+                           n = n1 .. n1 + M N - 1; copied by mci_plan.  NULL otherwise. */
+} mci_channel;
+
+typedef struct {
+  int32_t M;                            /* channels, 1..MCI_MAX_CHANNELS */
+  int32_t n_ops;                        /* output operators, 1..MCI_MAX_OPS */
+  int64_t N;                            /* samples per channel (the paper's L), >= 1 */
+  int64_t n1;                           /* band start (the paper's N_1), or MCI_N1_DEFAULT */
+  int64_t n_out;                        /* output grid size, >= 1 */
+  mci_channel ch[MCI_MAX_CHANNELS];     /* first M used */
+  int32_t ops[MCI_MAX_OPS];             /* mci_out_op, first n_ops used */
+  int32_t op_orders[MCI_MAX_OPS];       /* derivative order for MCI_OUT_DERIV, 0..8 */
+  int32_t real_io;                      /* 1: real samples in, real part out; 0: complex in and out */
+  int32_t precision;                    /* mci_precision of the transforms and the apply */
+  int32_t storage;                      /* mci_storage of g and y */
+  uint32_t flags;                       /* MCI_ALLOW_SINGULAR_ZERO */
+  double cond_max;                      /* reject plans above this condition number; 0 => 1e12 */
+} mci_plan_desc;
+
+typedef struct mci_plan_s* mci_plan_t;
+
+typedef struct {
+  double max_cond;          /* max over residues of cond_1 of the row-equilibrated H_n^T */
+  int64_t n_singular;       /* residues whose H_n was singular (zeroed under Remark 3.4) */
+  int64_t first_singular;   /* band index n of the first one, or INT64_MIN */
+  int64_t n1;               /* band start actually used */
+  int64_t fft_len_fwd;      /* transform length executed for the channel DFTs (N, or the Bluestein length) */
+  int64_t fft_len_inv;      /* transform length executed for the output grid */
+  int32_t path;             /* 0: multi-pass path through the workspace, 1: fused single-pass kernel */
+  int32_t reserved;
+} mci_plan_info_t;
+
+/* mci_plan -- build a 1-D reconstruction plan on `device`.
+ * Builds H_n = [b_k(n + jN)]_{jk} for every residue n of I_1 (eq. defH) and inverts it in
+ * FP64 on the GPU; stores the tables q_mj(n) o(n + jN) / N for the apply step, the
+ * transform twiddles and, for transform lengths with a prime factor above 7, the
+ * Bluestein chirp tables.  One device synchronisation (to read back singular flags).
+ * Errors: MCI_E_INVALID_ARG (bad descriptor), MCI_E_SINGULAR (first singular residue is
+ * available through mci_plan_info of no plan: the call fails and *out is NULL),
+ * MCI_E_ILL_CONDITIONED, MCI_E_OUT_OF_MEMORY, MCI_E_DEVICE.  *out is set only on success. */
+mci_status mci_plan(const mci_plan_desc* desc, int device, mci_plan_t* out);
+
+/* mci_plan_destroy -- release a plan's device tables.  NULL is a no-op. */
+mci_status mci_plan_destroy(mci_plan_t plan);
+
+/* mci_plan_info -- describe a plan. */
+mci_status mci_plan_info(mci_plan_t plan, mci_plan_info_t* info);
+
+/* mci_workspace_size -- device bytes of scratch a reconstruction of `batch` signals needs
+ * (0 for plans that run fused).  The caller allocates it, so reconstruction calls never
+ * allocate. */
+mci_status mci_workspace_size(mci_plan_t plan, int64_t batch, size_t* bytes);
+
+/* mci_reconstruct_1d -- reconstruct `batch` signals (Theorem 3.3 / eq. DFTexpression).
+ *   g : device, samples [batch][M][N] (real_io) or [batch][M][N][2] (complex, re/im
+ *       interleaved), element type per precision/storage, contiguous.
+ *   y : device, output [batch][n_ops][n_out] (real_io) or [batch][n_ops][n_out][2].
+ *   workspace / ws_bytes : device scratch of at least mci_workspace_size(plan, batch).
+ *   stream : HIP stream the kernels are queued on (0 = null stream).
+ * batch = 0 is a no-op.  g and y must not overlap. */
+mci_status mci_reconstruct_1d(mci_plan_t plan, const void* g, void* y, int64_t batch, void* workspace,
+                              size_t ws_bytes, hipStream_t stream);
+
+/* ----------------------------------------------------------------------------------- */
+/* 2-D separable upsampling (Section 5.2): every row, then every column of the result,  */
+/* is reconstructed by MCI from two channels -- the line and its three-point centred     */
+/* difference (x[p+1] - x[p-1]) / (2h), h = 2 pi / (line length), circular -- with       */
+/* multipliers {1, i n}, band start -floor((2 len - 1) / 2), on a grid `scale` times      */
+/* finer, keeping the real part after each pass.                                         */
+/* ----------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t h, w;         /* low-resolution image size, each >= 2 */
+  int32_t scale;        /* upsampling factor s >= 1: output is (s h) x (s w) */
+  int32_t precision;    /* MCI_F32 (MCI_F64 accepted for validation runs) */
+  int32_t storage;      /* mci_storage of lr and hr */
+  int32_t reserved;
+} mci_plan2d_desc;
+
+/* mci_plan_2d -- build a 2-D upsampling plan (two 1-D plans, rows and columns). */
+mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out);
+
+/* mci_upsample_2d -- lr [batch][h][w] -> hr [batch][s h][s w], row-major, device pointers.
+ * workspace of mci_workspace_size(plan, batch) bytes (holds the row-pass result). */
+mci_status mci_upsample_2d(mci_plan_t plan, const void* lr, void* hr, int64_t batch, void* workspace,
+                           size_t ws_bytes, hipStream_t stream);
+
+/* mci_status_string -- static text for a status code. */
+const char* mci_status_string(mci_status s);
+
+/* mci_last_error -- text of the last error recorded by this thread (empty if none). */
+const char* mci_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCI_H */

@@ -1,0 +1,185 @@
+"""FFT multichannel interpolation (Cheng & Kou, arXiv:1802.10291) on MI355X.
+
+Python face of libmci (include/mci.h).  Every step of the reconstruction runs in the
+library's HIP kernels; this module only builds descriptors, allocates the caller-side
+workspace with PyTorch and passes device pointers and the current HIP stream.
+
+    plan = Plan1D(N=1366, n_out=16384, channels=[("deriv", 0), ("deriv", 1), ("deriv", 2)])
+    y = plan.reconstruct(g)          # g: float32 cuda tensor [batch, 3, 1366]
+
+    up = Plan2D(h=256, w=256, scale=2)
+    hr = up.upsample(lr)             # lr: float32 cuda tensor [batch, 256, 256]
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence, Tuple, Union
+
+import numpy as np
+
+from . import _lib
+from ._lib import (  # noqa: F401  (the C-ABI names, re-exported)
+    MCIError, mci_plan, mci_plan_destroy, mci_plan_info, mci_workspace_size, mci_reconstruct_1d, mci_plan_2d,
+    mci_upsample_2d,
+)
+
+_KINDS = {"deriv": _lib.MCI_MULT_DERIV, "hilbert": _lib.MCI_MULT_HILBERT, "table": _lib.MCI_MULT_TABLE}
+_OPS = {"identity": _lib.MCI_OUT_IDENTITY, "hilbert": _lib.MCI_OUT_HILBERT, "deriv": _lib.MCI_OUT_DERIV}
+
+Channel = Union[Tuple[str, int], Tuple[str, np.ndarray]]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(device) -> int:
+    torch = _torch()
+    return int(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan1D:
+    """A 1-D reconstruction plan (``mci_plan``).
+
+    channels: list of ("deriv", order) | ("hilbert", 0) | ("table", complex array of
+    length M*N with b(n) for n in [n1, n1 + M N)).  ops: list of ("identity", 0) |
+    ("hilbert", 0) | ("deriv", order).
+    """
+
+    def __init__(self, N: int, n_out: int, channels: Sequence[Channel], ops: Sequence[Tuple[str, int]] = (("identity", 0),),
+                 n1: Optional[int] = None, real: bool = True, precision: str = "f32", storage: str = "native",
+                 allow_singular_zero: bool = False, cond_max: float = 0.0, device: int = 0):
+        d = _lib.mci_plan_desc()
+        d.M = len(channels)
+        d.n_ops = len(ops)
+        d.N = int(N)
+        d.n1 = _lib.MCI_N1_DEFAULT if n1 is None else int(n1)
+        d.n_out = int(n_out)
+        self._tables = []
+        for k, (kind, arg) in enumerate(channels):
+            d.ch[k].kind = _KINDS[kind]
+            if kind == "table":
+                t = np.ascontiguousarray(np.asarray(arg, dtype=np.complex128).ravel().view(np.float64))
+                self._tables.append(t)
+                d.ch[k].table = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            else:
+                d.ch[k].order = int(arg)
+        for o, (op, order) in enumerate(ops):
+            d.ops[o] = _OPS[op]
+            d.op_orders[o] = int(order)
+        d.real_io = 1 if real else 0
+        d.precision = {"f32": _lib.MCI_F32, "f64": _lib.MCI_F64}[precision]
+        d.storage = {"native": _lib.MCI_STORE_NATIVE, "f16": _lib.MCI_STORE_F16}[storage]
+        d.flags = _lib.MCI_ALLOW_SINGULAR_ZERO if allow_singular_zero else 0
+        d.cond_max = float(cond_max)
+        self.desc = d
+        self.M, self.N, self.n_out, self.n_ops, self.real = d.M, int(N), int(n_out), d.n_ops, real
+        self.precision, self.storage, self.device = precision, storage, device
+        self.handle = mci_plan(d, device)
+        self._ws = None
+
+    @property
+    def info(self):
+        return mci_plan_info(self.handle)
+
+    def io_dtype(self):
+        torch = _torch()
+        if self.storage == "f16":
+            return torch.float16
+        return torch.float64 if self.precision == "f64" else torch.float32
+
+    def workspace(self, batch: int):
+        torch = _torch()
+        need = mci_workspace_size(self.handle, batch)
+        if need and (self._ws is None or self._ws.numel() < need):
+            self._ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws if need else None, need
+
+    def reconstruct(self, g, out=None):
+        """g: cuda tensor [batch, M, N] (real) or [batch, M, N, 2] (complex, re/im).
+        Returns [batch, n_ops, n_out] (or [..., 2])."""
+        torch = _torch()
+        if not g.is_cuda:
+            raise ValueError("g must be a device tensor")
+        tail = (self.M, self.N) if self.real else (self.M, self.N, 2)
+        if tuple(g.shape[1:]) != tail or g.dtype != self.io_dtype() or not g.is_contiguous():
+            raise ValueError(f"g must be contiguous {self.io_dtype()} [batch, {', '.join(map(str, tail))}]")
+        batch = g.shape[0]
+        shape = (batch, self.n_ops, self.n_out) if self.real else (batch, self.n_ops, self.n_out, 2)
+        if out is None:
+            out = torch.empty(shape, dtype=self.io_dtype(), device=g.device)
+        elif tuple(out.shape) != shape or out.dtype != self.io_dtype() or not out.is_contiguous():
+            raise ValueError("bad out tensor")
+        ws, need = self.workspace(batch)
+        mci_reconstruct_1d(self.handle, g.data_ptr(), out.data_ptr(), batch, ws.data_ptr() if ws is not None else 0,
+                           need, _stream_handle(g.device))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mci_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan2D:
+    """A 2-D separable upsampling plan (``mci_plan_2d``): lr [batch, h, w] -> hr [batch, s h, s w]."""
+
+    def __init__(self, h: int, w: int, scale: int, precision: str = "f32", storage: str = "native", device: int = 0):
+        d = _lib.mci_plan2d_desc()
+        d.h, d.w, d.scale = int(h), int(w), int(scale)
+        d.precision = {"f32": _lib.MCI_F32, "f64": _lib.MCI_F64}[precision]
+        d.storage = {"native": _lib.MCI_STORE_NATIVE, "f16": _lib.MCI_STORE_F16}[storage]
+        self.desc = d
+        self.h, self.w, self.scale = int(h), int(w), int(scale)
+        self.precision, self.storage, self.device = precision, storage, device
+        self.handle = mci_plan_2d(d, device)
+        self._ws = None
+
+    @property
+    def info(self):
+        return mci_plan_info(self.handle)
+
+    def io_dtype(self):
+        torch = _torch()
+        if self.storage == "f16":
+            return torch.float16
+        return torch.float64 if self.precision == "f64" else torch.float32
+
+    def workspace(self, batch: int):
+        torch = _torch()
+        need = mci_workspace_size(self.handle, batch)
+        if need and (self._ws is None or self._ws.numel() < need):
+            self._ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws if need else None, need
+
+    def upsample(self, lr, out=None):
+        torch = _torch()
+        if not lr.is_cuda or tuple(lr.shape[1:]) != (self.h, self.w) or lr.dtype != self.io_dtype() \
+                or not lr.is_contiguous():
+            raise ValueError(f"lr must be a contiguous device {self.io_dtype()} tensor [batch, {self.h}, {self.w}]")
+        batch = lr.shape[0]
+        shape = (batch, self.scale * self.h, self.scale * self.w)
+        if out is None:
+            out = torch.empty(shape, dtype=self.io_dtype(), device=lr.device)
+        ws, need = self.workspace(batch)
+        mci_upsample_2d(self.handle, lr.data_ptr(), out.data_ptr(), batch, ws.data_ptr() if ws is not None else 0,
+                        need, _stream_handle(lr.device))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mci_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,491 @@
+// mci_api.hip -- host side of libmci: descriptor validation, plan construction (FP64
+// channel-matrix inversion on the GPU, transform tables), and the C ABI of mci.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mci_fused.h"
+#include "mci_internal.h"
+
+using namespace mci;
+
+static thread_local std::string g_last_error;
+
+static mci_status fail(mci_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess) return fail(MCI_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+struct mci_plan_s {
+  int dims = 1;  // 1: 1-D plan, 2: 2-D plan
+  int device = 0;
+  mci_plan_desc d{};
+  int64_t mu = 0;
+  int prec = MCI_F32;
+  int store = ST_F32;
+  void* tab = nullptr;      // [n_ops][M][M][N] complex in plan precision
+  FftSide fwd, inv;
+  double max_cond = 0.0;
+  int64_t n_sing = 0, first_sing = INT64_MIN;
+  FusedPlan fused;          // single-pass kernel choice (fused.kind == 0: none)
+  // 2-D
+  mci_plan2d_desc d2{};
+  mci_plan_s* rows = nullptr;
+  mci_plan_s* cols = nullptr;
+};
+
+// ----------------------------------------------------------------- FFT planning (host)
+static bool factor_7smooth(int64_t n, std::vector<int>& radices) {
+  radices.clear();
+  if (n < 1) return false;
+  int64_t m = n;
+  while (m % 8 == 0) { radices.push_back(8); m /= 8; }
+  if (m % 4 == 0) { radices.push_back(4); m /= 4; }
+  if (m % 2 == 0) { radices.push_back(2); m /= 2; }
+  for (int p : {3, 5, 7})
+    while (m % p == 0) { radices.push_back(p); m /= p; }
+  return m == 1;
+}
+
+static int64_t next_7smooth(int64_t n) {
+  for (int64_t c = std::max<int64_t>(n, 1);; ++c) {
+    int64_t m = c;
+    for (int p : {2, 3, 5, 7})
+      while (m % p == 0) m /= p;
+    if (m == 1) return c;
+  }
+}
+
+// e^{-2 pi i k / L} in FP64: the angle is reduced through the exact integer k mod L
+static std::complex<double> root(int64_t k, int64_t L) {
+  k %= L;
+  if (k < 0) k += L;
+  const double a = -2.0 * M_PI * ((double)k / (double)L);
+  return {std::cos(a), std::sin(a)};
+}
+
+// Host FP64 Stockham FFT (sign S) used only to build Bluestein filter spectra at plan time.
+static void host_fft(std::vector<std::complex<double>>& x, const std::vector<int>& radices, int S) {
+  const int64_t L = (int64_t)x.size();
+  std::vector<std::complex<double>> y(L);
+  int64_t Ns = 1;
+  for (int R : radices) {
+    const int64_t nb = L / R;
+    for (int64_t j = 0; j < nb; ++j) {
+      const int64_t k = j % Ns;
+      std::complex<double> v[8], o[8];
+      for (int r = 0; r < R; ++r) {
+        std::complex<double> w = root(k * r * (L / (Ns * R)), L);
+        if (S > 0) w = std::conj(w);
+        v[r] = x[j + r * nb] * w;
+      }
+      for (int s = 0; s < R; ++s) {
+        std::complex<double> acc = 0;
+        for (int q = 0; q < R; ++q) {
+          std::complex<double> w = root((int64_t)((q * s) % R), R);
+          if (S > 0) w = std::conj(w);
+          acc += v[q] * w;
+        }
+        o[s] = acc;
+      }
+      const int64_t base = (j / Ns) * Ns * R + k;
+      for (int r = 0; r < R; ++r) y[base + r * Ns] = o[r];
+    }
+    x.swap(y);
+    Ns *= R;
+  }
+}
+
+template <typename C>
+static void* upload(const std::vector<std::complex<double>>& v, hipError_t& err) {
+  std::vector<C> h(v.size());
+  for (size_t i = 0; i < v.size(); ++i) {
+    h[i].x = (decltype(C::x))v[i].real();
+    h[i].y = (decltype(C::x))v[i].imag();
+  }
+  void* d = nullptr;
+  err = hipMalloc(&d, h.size() * sizeof(C));
+  if (err != hipSuccess) return nullptr;
+  err = hipMemcpy(d, h.data(), h.size() * sizeof(C), hipMemcpyHostToDevice);
+  return d;
+}
+
+static void free_side(FftSide& f) {
+  if (f.tw) (void)hipFree(f.tw);
+  if (f.chirp) (void)hipFree(f.chirp);
+  if (f.bhat) (void)hipFree(f.bhat);
+  f.tw = f.chirp = f.bhat = nullptr;
+}
+
+static mci_status build_side(FftSide& f, int64_t len, int sign, int prec) {
+  f.len = len;
+  f.sign = sign;
+  f.blue = !factor_7smooth(len, f.radices);
+  f.lexec = f.blue ? next_7smooth(2 * len - 1) : len;
+  if (f.blue) factor_7smooth(f.lexec, f.radices);
+  std::vector<std::complex<double>> tw(f.lexec);
+  for (int64_t k = 0; k < f.lexec; ++k) tw[k] = root(k, f.lexec);
+  hipError_t e;
+  f.tw = prec == MCI_F64 ? upload<double2>(tw, e) : upload<float2>(tw, e);
+  if (!f.tw) return fail(MCI_E_OUT_OF_MEMORY, "twiddle table");
+  if (e != hipSuccess) return fail(MCI_E_DEVICE, "twiddle upload");
+  if (!f.blue) return MCI_OK;
+  // chirp c[k] = e^{sign i pi k^2 / len}; k^2 reduced modulo 2 len exactly
+  std::vector<std::complex<double>> c(len), b(f.lexec, 0.0);
+  for (int64_t k = 0; k < len; ++k) {
+    const int64_t q = (int64_t)(((__int128)k * k) % (2 * len));
+    const double a = (double)sign * M_PI * ((double)q / (double)len);
+    c[k] = {std::cos(a), std::sin(a)};
+  }
+  for (int64_t m = 0; m < len; ++m) {
+    b[m] = std::conj(c[m]);
+    if (m) b[f.lexec - m] = std::conj(c[m]);
+  }
+  host_fft(b, f.radices, -1);
+  for (auto& v : b) v /= (double)f.lexec;
+  f.chirp = prec == MCI_F64 ? upload<double2>(c, e) : upload<float2>(c, e);
+  if (!f.chirp || e != hipSuccess) return fail(MCI_E_DEVICE, "chirp upload");
+  f.bhat = prec == MCI_F64 ? upload<double2>(b, e) : upload<float2>(b, e);
+  if (!f.bhat || e != hipSuccess) return fail(MCI_E_DEVICE, "chirp spectrum upload");
+  return MCI_OK;
+}
+
+// ----------------------------------------------------------------- validation
+static mci_status validate(const mci_plan_desc* d) {
+  if (!d) return fail(MCI_E_INVALID_ARG, "desc is NULL");
+  if (d->M < 1 || d->M > MCI_MAX_CHANNELS) return fail(MCI_E_INVALID_ARG, "M must be in 1..4");
+  if (d->n_ops < 1 || d->n_ops > MCI_MAX_OPS) return fail(MCI_E_INVALID_ARG, "n_ops must be in 1..4");
+  if (d->N < 1 || d->N > (int64_t)1 << 26) return fail(MCI_E_INVALID_ARG, "N out of range");
+  if (d->n_out < 1 || d->n_out > (int64_t)1 << 28) return fail(MCI_E_INVALID_ARG, "n_out out of range");
+  if (d->precision != MCI_F32 && d->precision != MCI_F64) return fail(MCI_E_INVALID_ARG, "precision");
+  if (d->storage != MCI_STORE_NATIVE && d->storage != MCI_STORE_F16) return fail(MCI_E_INVALID_ARG, "storage");
+  if (d->storage == MCI_STORE_F16 && d->precision != MCI_F32)
+    return fail(MCI_E_INVALID_ARG, "F16 storage needs an F32 plan");
+  if (d->real_io != 0 && d->real_io != 1) return fail(MCI_E_INVALID_ARG, "real_io must be 0 or 1");
+  if (d->flags & ~MCI_ALLOW_SINGULAR_ZERO) return fail(MCI_E_INVALID_ARG, "unknown flag");
+  if (!(d->cond_max >= 0.0)) return fail(MCI_E_INVALID_ARG, "cond_max");
+  for (int k = 0; k < d->M; ++k) {
+    const mci_channel& c = d->ch[k];
+    if (c.kind == MCI_MULT_DERIV) {
+      if (c.order < 0 || c.order > 8) return fail(MCI_E_INVALID_ARG, "derivative order must be in 0..8");
+    } else if (c.kind == MCI_MULT_TABLE) {
+      if (!c.table) return fail(MCI_E_INVALID_ARG, "table channel without table");
+    } else if (c.kind != MCI_MULT_HILBERT) {
+      return fail(MCI_E_INVALID_ARG, "unknown multiplier kind");
+    }
+  }
+  for (int o = 0; o < d->n_ops; ++o) {
+    if (d->ops[o] < MCI_OUT_IDENTITY || d->ops[o] > MCI_OUT_DERIV) return fail(MCI_E_INVALID_ARG, "unknown output op");
+    if (d->ops[o] == MCI_OUT_DERIV && (d->op_orders[o] < 0 || d->op_orders[o] > 8))
+      return fail(MCI_E_INVALID_ARG, "output derivative order must be in 0..8");
+  }
+  return MCI_OK;
+}
+
+static void destroy_plan(mci_plan_s* p) {
+  if (!p) return;
+  if (p->tab) (void)hipFree(p->tab);
+  free_side(p->fwd);
+  free_side(p->inv);
+  fused_release(p->fused);
+  destroy_plan(p->rows);
+  destroy_plan(p->cols);
+  delete p;
+}
+
+struct DevBufs {
+  std::vector<void*> v;
+  ~DevBufs() {
+    for (void* p : v)
+      if (p) (void)hipFree(p);
+  }
+  void* alloc(size_t n, hipError_t& e) {
+    void* p = nullptr;
+    e = hipMalloc(&p, n);
+    if (e == hipSuccess) v.push_back(p);
+    return e == hipSuccess ? p : nullptr;
+  }
+};
+
+static mci_status build_plan(const mci_plan_desc* desc, int device, mci_plan_s** out) {
+  mci_status st = validate(desc);
+  if (st != MCI_OK) return st;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(MCI_E_INVALID_ARG, "device index");
+  HIP_TRY(hipSetDevice(device));
+  mci_plan_s* p = new (std::nothrow) mci_plan_s();
+  if (!p) return fail(MCI_E_OUT_OF_MEMORY, "plan");
+  p->device = device;
+  p->d = *desc;
+  for (int k = 0; k < MCI_MAX_CHANNELS; ++k) p->d.ch[k].table = nullptr;
+  p->mu = (int64_t)desc->M * desc->N;
+  if (p->d.n1 == MCI_N1_DEFAULT) p->d.n1 = -((p->mu - 1) / 2);
+  if (p->d.cond_max == 0.0) p->d.cond_max = 1e12;
+  p->prec = desc->precision;
+  p->store = desc->precision == MCI_F64 ? ST_F64 : (desc->storage == MCI_STORE_F16 ? ST_F16 : ST_F32);
+
+  const int M = desc->M, n_ops = desc->n_ops;
+  const int64_t N = desc->N, mu = p->mu;
+  DevBufs tmp;
+  hipError_t e;
+  // channel tables (FP64) on the device
+  double2* d_tables = nullptr;
+  bool any_table = false;
+  for (int k = 0; k < M; ++k) any_table |= desc->ch[k].kind == MCI_MULT_TABLE;
+  if (any_table) {
+    std::vector<double2> h((size_t)M * mu, make_double2(0.0, 0.0));
+    for (int k = 0; k < M; ++k)
+      if (desc->ch[k].kind == MCI_MULT_TABLE)
+        for (int64_t i = 0; i < mu; ++i) h[(size_t)k * mu + i] = make_double2(desc->ch[k].table[2 * i], desc->ch[k].table[2 * i + 1]);
+    d_tables = (double2*)tmp.alloc(h.size() * sizeof(double2), e);
+    if (!d_tables) { destroy_plan(p); return fail(MCI_E_OUT_OF_MEMORY, "channel tables"); }
+    if ((e = hipMemcpy(d_tables, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice)) != hipSuccess) {
+      destroy_plan(p);
+      return fail(MCI_E_DEVICE, "channel table upload");
+    }
+  }
+  const size_t ntab = (size_t)n_ops * M * M * N;
+  double2* tab64 = (double2*)tmp.alloc(ntab * sizeof(double2), e);
+  float2* tab32 = (float2*)tmp.alloc(ntab * sizeof(float2), e);
+  double* cond = (double*)tmp.alloc((size_t)N * sizeof(double), e);
+  int* sing = (int*)tmp.alloc((size_t)N * sizeof(int), e);
+  if (!tab64 || !tab32 || !cond || !sing) { destroy_plan(p); return fail(MCI_E_OUT_OF_MEMORY, "plan scratch"); }
+
+  PlanKernelArgs a{};
+  a.M = M; a.n_ops = n_ops; a.N = N; a.n1 = p->d.n1;
+  for (int k = 0; k < M; ++k) { a.kinds[k] = desc->ch[k].kind; a.orders[k] = desc->ch[k].order; }
+  for (int o = 0; o < n_ops; ++o) { a.ops[o] = desc->ops[o]; a.op_orders[o] = desc->op_orders[o]; }
+  a.tables = d_tables; a.tab64 = tab64; a.tab32 = tab32; a.cond = cond; a.sing = sing;
+  a.allow_zero = (desc->flags & MCI_ALLOW_SINGULAR_ZERO) ? 1 : 0;
+  if ((e = launch_plan_tables(a, 0)) != hipSuccess) { destroy_plan(p); return fail(MCI_E_DEVICE, hipGetErrorString(e)); }
+  std::vector<double> hc(N);
+  std::vector<int> hs(N);
+  if ((e = hipMemcpy(hc.data(), cond, N * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess ||
+      (e = hipMemcpy(hs.data(), sing, N * sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) {
+    destroy_plan(p);
+    return fail(MCI_E_DEVICE, std::string("plan readback: ") + hipGetErrorString(e));
+  }
+  for (int64_t i = 0; i < N; ++i) {
+    if (hs[i]) {
+      if (!p->n_sing) p->first_sing = p->d.n1 + i;
+      ++p->n_sing;
+    } else {
+      p->max_cond = std::max(p->max_cond, hc[i]);
+    }
+  }
+  if (p->n_sing && !(desc->flags & MCI_ALLOW_SINGULAR_ZERO)) {
+    const int64_t bad = p->first_sing;
+    destroy_plan(p);
+    return fail(MCI_E_SINGULAR, "H_n singular at n = " + std::to_string(bad));
+  }
+  if (p->max_cond > p->d.cond_max) {
+    const double c = p->max_cond;
+    destroy_plan(p);
+    return fail(MCI_E_ILL_CONDITIONED, "max condition number " + std::to_string(c));
+  }
+  // keep the table in plan precision
+  if (p->prec == MCI_F64) {
+    if ((e = hipMalloc(&p->tab, ntab * sizeof(double2))) != hipSuccess) { destroy_plan(p); return fail(MCI_E_OUT_OF_MEMORY, "tab"); }
+    if ((e = hipMemcpy(p->tab, tab64, ntab * sizeof(double2), hipMemcpyDeviceToDevice)) != hipSuccess) { destroy_plan(p); return fail(MCI_E_DEVICE, "tab copy"); }
+  } else {
+    if ((e = hipMalloc(&p->tab, ntab * sizeof(float2))) != hipSuccess) { destroy_plan(p); return fail(MCI_E_OUT_OF_MEMORY, "tab"); }
+    if ((e = hipMemcpy(p->tab, tab32, ntab * sizeof(float2), hipMemcpyDeviceToDevice)) != hipSuccess) { destroy_plan(p); return fail(MCI_E_DEVICE, "tab copy"); }
+  }
+  if ((st = build_side(p->fwd, N, -1, p->prec)) != MCI_OK) { destroy_plan(p); return st; }
+  if ((st = build_side(p->inv, desc->n_out, +1, p->prec)) != MCI_OK) { destroy_plan(p); return st; }
+  if ((st = fused_select(p->d, p->prec, p->store, p->tab, p->fused)) != MCI_OK) { destroy_plan(p); return st; }
+  HIP_TRY(hipDeviceSynchronize());
+  *out = p;
+  return MCI_OK;
+}
+
+static Generic1D generic_of(const mci_plan_s* p) {
+  Generic1D g;
+  g.M = p->d.M; g.n_ops = p->d.n_ops; g.real_io = p->d.real_io;
+  g.N = p->d.N; g.n1 = p->d.n1; g.n_out = p->d.n_out;
+  g.tab = p->tab; g.fwd = &p->fwd; g.inv = &p->inv;
+  return g;
+}
+
+static size_t ws_1d(const mci_plan_s* p, int64_t batch) {
+  if (batch <= 0) return 0;
+  if (p->fused.kind) return 0;
+  return generic_1d_workspace(generic_of(p), p->prec, batch);
+}
+
+
+static size_t ws_2d(const mci_plan_s* p, int64_t batch) {
+  if (batch <= 0) return 0;
+  const int64_t h = p->d2.h, w = p->d2.w, s = p->d2.scale;
+  const size_t e = p->prec == MCI_F64 ? 8 : 4;
+  auto al = [](size_t n) { return (n + 255) & ~(size_t)255; };
+  // row channels, mid image, column channels, column result, and the larger 1-D workspace
+  size_t rows_in = al((size_t)batch * h * 2 * w * e);
+  size_t mid = al((size_t)batch * h * s * w * e);
+  size_t cols_in = al((size_t)batch * s * w * 2 * h * e);
+  size_t cols_out = al((size_t)batch * s * w * s * h * e);
+  size_t w1 = std::max(ws_1d(p->rows, batch * h), ws_1d(p->cols, batch * s * w));
+  return rows_in + mid + cols_in + cols_out + al(w1) + 256;
+}
+
+// ================================================================= C ABI
+extern "C" {
+
+const char* mci_status_string(mci_status s) {
+  switch (s) {
+    case MCI_OK: return "MCI_OK";
+    case MCI_E_INVALID_ARG: return "MCI_E_INVALID_ARG";
+    case MCI_E_SINGULAR: return "MCI_E_SINGULAR";
+    case MCI_E_ILL_CONDITIONED: return "MCI_E_ILL_CONDITIONED";
+    case MCI_E_UNSUPPORTED: return "MCI_E_UNSUPPORTED";
+    case MCI_E_OUT_OF_MEMORY: return "MCI_E_OUT_OF_MEMORY";
+    case MCI_E_DEVICE: return "MCI_E_DEVICE";
+  }
+  return "MCI_E_UNKNOWN";
+}
+
+const char* mci_last_error(void) { return g_last_error.c_str(); }
+
+mci_status mci_plan(const mci_plan_desc* desc, int device, mci_plan_t* out) {
+  if (!out) return fail(MCI_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  mci_plan_s* p = nullptr;
+  mci_status st = build_plan(desc, device, &p);
+  if (st == MCI_OK) *out = p;
+  return st;
+}
+
+mci_status mci_plan_destroy(mci_plan_t plan) {
+  if (!plan) return MCI_OK;
+  (void)hipSetDevice(plan->device);
+  destroy_plan(plan);
+  return MCI_OK;
+}
+
+mci_status mci_plan_info(mci_plan_t p, mci_plan_info_t* info) {
+  if (!p || !info) return fail(MCI_E_INVALID_ARG, "NULL argument");
+  const mci_plan_s* q = p->dims == 2 ? p->rows : p;
+  info->max_cond = q->max_cond;
+  info->n_singular = q->n_sing;
+  info->first_singular = q->first_sing;
+  info->n1 = q->d.n1;
+  info->fft_len_fwd = q->fwd.lexec;
+  info->fft_len_inv = q->inv.lexec;
+  info->path = p->dims == 2 ? (p->rows->fused.kind ? 1 : 0) : (p->fused.kind ? 1 : 0);
+  info->reserved = 0;
+  return MCI_OK;
+}
+
+mci_status mci_workspace_size(mci_plan_t p, int64_t batch, size_t* bytes) {
+  if (!p || !bytes || batch < 0) return fail(MCI_E_INVALID_ARG, "bad argument");
+  *bytes = p->dims == 2 ? ws_2d(p, batch) : ws_1d(p, batch);
+  return MCI_OK;
+}
+
+mci_status mci_reconstruct_1d(mci_plan_t p, const void* g, void* y, int64_t batch, void* workspace, size_t ws_bytes,
+                              hipStream_t stream) {
+  if (!p || p->dims != 1) return fail(MCI_E_INVALID_ARG, "not a 1-D plan");
+  if (batch < 0) return fail(MCI_E_INVALID_ARG, "batch < 0");
+  if (batch == 0) return MCI_OK;
+  if (!g || !y) return fail(MCI_E_INVALID_ARG, "NULL data pointer");
+  if (batch > ((int64_t)1 << 40) / std::max<int64_t>(p->mu, p->d.n_out * p->d.n_ops))
+    return fail(MCI_E_INVALID_ARG, "batch too large");
+  const size_t need = ws_1d(p, batch);
+  if (need && (!workspace || ws_bytes < need))
+    return fail(MCI_E_INVALID_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
+  HIP_TRY(hipSetDevice(p->device));
+  hipError_t e;
+  if (p->fused.kind) e = fused_run(p->fused, g, y, batch, stream);
+  else e = run_generic_1d(generic_of(p), p->prec, p->store, g, y, batch, workspace, stream);
+  if (e != hipSuccess) return fail(MCI_E_DEVICE, std::string("reconstruct: ") + hipGetErrorString(e));
+  return MCI_OK;
+}
+
+mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out) {
+  if (!out) return fail(MCI_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(MCI_E_INVALID_ARG, "desc is NULL");
+  if (desc->h < 2 || desc->w < 2 || desc->scale < 1 || desc->h > (1 << 16) || desc->w > (1 << 16) || desc->scale > 16)
+    return fail(MCI_E_INVALID_ARG, "image size or scale out of range");
+  if (desc->precision != MCI_F32 && desc->precision != MCI_F64) return fail(MCI_E_INVALID_ARG, "precision");
+  if (desc->storage != MCI_STORE_NATIVE && desc->storage != MCI_STORE_F16) return fail(MCI_E_INVALID_ARG, "storage");
+  if (desc->storage == MCI_STORE_F16 && desc->precision != MCI_F32) return fail(MCI_E_INVALID_ARG, "F16 needs F32");
+  mci_plan_s* p = new (std::nothrow) mci_plan_s();
+  if (!p) return fail(MCI_E_OUT_OF_MEMORY, "plan");
+  p->dims = 2;
+  p->device = device;
+  p->d2 = *desc;
+  p->prec = desc->precision;
+  p->store = desc->precision == MCI_F64 ? ST_F64 : (desc->storage == MCI_STORE_F16 ? ST_F16 : ST_F32);
+  for (int axis = 0; axis < 2; ++axis) {
+    const int64_t len = axis == 0 ? desc->w : desc->h;
+    mci_plan_desc d{};
+    d.M = 2; d.n_ops = 1; d.N = len; d.n1 = MCI_N1_DEFAULT; d.n_out = (int64_t)desc->scale * len;
+    d.ch[0].kind = MCI_MULT_DERIV; d.ch[0].order = 0;
+    d.ch[1].kind = MCI_MULT_DERIV; d.ch[1].order = 1;
+    d.ops[0] = MCI_OUT_IDENTITY;
+    d.real_io = 1;
+    d.precision = desc->precision;
+    d.storage = MCI_STORE_NATIVE;
+    mci_plan_s* q = nullptr;
+    mci_status st = build_plan(&d, device, &q);
+    if (st != MCI_OK) { destroy_plan(p); return st; }
+    (axis == 0 ? p->rows : p->cols) = q;
+  }
+  *out = p;
+  return MCI_OK;
+}
+
+mci_status mci_upsample_2d(mci_plan_t p, const void* lr, void* hr, int64_t batch, void* workspace, size_t ws_bytes,
+                           hipStream_t stream) {
+  if (!p || p->dims != 2) return fail(MCI_E_INVALID_ARG, "not a 2-D plan");
+  if (batch < 0) return fail(MCI_E_INVALID_ARG, "batch < 0");
+  if (batch == 0) return MCI_OK;
+  if (!lr || !hr) return fail(MCI_E_INVALID_ARG, "NULL data pointer");
+  const size_t need = ws_2d(p, batch);
+  if (!workspace || ws_bytes < need) return fail(MCI_E_INVALID_ARG, "workspace too small: need " + std::to_string(need));
+  HIP_TRY(hipSetDevice(p->device));
+  const int64_t h = p->d2.h, w = p->d2.w, s = p->d2.scale, H = s * h, W = s * w;
+  const size_t e = p->prec == MCI_F64 ? 8 : 4;
+  auto al = [](size_t n) { return (n + 255) & ~(size_t)255; };
+  char* base = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+  char* rows_in = base;
+  char* mid = rows_in + al((size_t)batch * h * 2 * w * e);
+  char* cols_in = mid + al((size_t)batch * h * W * e);
+  char* cols_out = cols_in + al((size_t)batch * W * 2 * h * e);
+  char* w1 = cols_out + al((size_t)batch * W * H * e);
+  const size_t w1_bytes = ws_bytes - (size_t)(w1 - (char*)workspace);
+  const int st_native = p->prec == MCI_F64 ? ST_F64 : ST_F32;
+  hipError_t err;
+  if ((err = launch_fd_channels(p->prec, p->store, lr, rows_in, batch, h, w, 0, stream)) != hipSuccess)
+    return fail(MCI_E_DEVICE, hipGetErrorString(err));
+  mci_status st = MCI_OK;
+  if (p->rows->fused.kind) err = fused_run(p->rows->fused, rows_in, mid, batch * h, stream);
+  else err = run_generic_1d(generic_of(p->rows), p->prec, st_native, rows_in, mid, batch * h, w1, stream);
+  if (err != hipSuccess) return fail(MCI_E_DEVICE, hipGetErrorString(err));
+  if ((err = launch_fd_channels(p->prec, st_native, mid, cols_in, batch, h, W, 1, stream)) != hipSuccess)
+    return fail(MCI_E_DEVICE, hipGetErrorString(err));
+  if (p->cols->fused.kind) err = fused_run(p->cols->fused, cols_in, cols_out, batch * W, stream);
+  else err = run_generic_1d(generic_of(p->cols), p->prec, st_native, cols_in, cols_out, batch * W, w1, stream);
+  if (err != hipSuccess) return fail(MCI_E_DEVICE, hipGetErrorString(err));
+  if ((err = launch_transpose_out(p->prec, p->store, cols_out, hr, batch, W, H, stream)) != hipSuccess)
+    return fail(MCI_E_DEVICE, hipGetErrorString(err));
+  (void)w1_bytes;
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// mci_internal.h -- host-side structures and kernel launchers shared by the libmci
+// translation units (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mci.h"
+
+namespace mci {
+
+// One direction of a DFT of logical length `len` as the library executes it: a Stockham
+// FFT of length `lexec` (= len, or the Bluestein length P for lengths with a prime
+// factor above 7) with the given radices.
+struct FftSide {
+  int64_t len = 0;
+  int sign = -1;          // -1: e^{-2 pi i k n / len} (forward), +1: inverse
+  bool blue = false;
+  int64_t lexec = 0;
+  std::vector<int> radices;   // radices of lexec
+  void* tw = nullptr;         // e^{-2 pi i k / lexec}, lexec entries, plan precision
+  void* chirp = nullptr;      // Bluestein: e^{sign i pi k^2 / len}, len entries
+  void* bhat = nullptr;       // Bluestein: forward DFT_P of the conjugate chirp, divided by P
+};
+
+// Arguments of the FP64 plan kernel.
+struct PlanKernelArgs {
+  int M, n_ops;
+  int64_t N, n1;
+  int kinds[MCI_MAX_CHANNELS], orders[MCI_MAX_CHANNELS];
+  int ops[MCI_MAX_OPS], op_orders[MCI_MAX_OPS];
+  const double2* tables;  // [M][mu] or null
+  double2* tab64;         // [n_ops][M][M][N]
+  float2* tab32;          // [n_ops][M][M][N]
+  double* cond;           // [N]
+  int* sing;              // [N]
+  int allow_zero;
+};
+
+// Arguments of the generic (multi-pass) 1-D path.
+struct Generic1D {
+  int M, n_ops, real_io;
+  int64_t N, n1, n_out;
+  const void* tab;        // [n_ops][M][M][N] complex, plan precision
+  const FftSide* fwd;
+  const FftSide* inv;
+};
+
+enum StoreKind { ST_F32 = 0, ST_F64 = 1, ST_F16 = 2 };
+
+// Launchers (mci_kernels.hip).  All return hipSuccess or the launch error.
+hipError_t launch_plan_tables(const PlanKernelArgs& a, hipStream_t s);
+size_t generic_1d_workspace(const Generic1D& g, int prec, int64_t batch);
+hipError_t run_generic_1d(const Generic1D& g, int prec, int store, const void* in, void* out, int64_t batch,
+                          void* ws, hipStream_t s);
+// 2-D helpers: build the two channels {x, centred difference} of every line.
+//   rows: x [B][h][w] -> G [B*h][2][w];  cols: x [B][H][W] (column c is a line of length H)
+//   -> G [B*W][2][H].  `deriv_scale` = len / (4 pi).
+hipError_t launch_fd_channels(int prec, int store_in, const void* x, void* G, int64_t B, int64_t h, int64_t w,
+                              int along_cols, hipStream_t s);
+// transpose [B][W][H] -> [B][H][W] with storage conversion to the output type
+hipError_t launch_transpose_out(int prec, int store_out, const void* src, void* dst, int64_t B, int64_t W,
+                                int64_t H, hipStream_t s);
+
+}  // namespace mci

@@ -1,0 +1,206 @@
+"""GPU parity: libmci (HIP, gfx950) against the FP64 oracle on the same seeded inputs.
+
+Tolerances (relative L2 error per result, ||y - y_ref|| / ||y_ref||):
+  * FP64 plans: 1e-12 -- the transforms accumulate O(log n) roundings of 1.1e-16 with
+    tables accurate to ~1e-16, and the per-residue tables are built in FP64;
+  * FP32 plans: 1e-5  -- FP32 unit roundoff 6e-8 times a few tens of roundings along the
+    path (log2 of the transform lengths, the M-term apply and the Bluestein chirps),
+    times the growth of the equilibrated per-residue systems (condition <= ~20 here);
+  * FP16 storage: the output's own rounding, 2^-11 relative, dominates: 1e-3.
+Inputs are rounded once to the storage type and those rounded values go to both sides.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import images as SI
+from synth import signals as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1802_10291_amd  # noqa: F401  (fails loudly without the built library)
+    return torch
+
+
+def rel_l2(got, want):
+    got = np.asarray(got, dtype=np.complex128 if np.iscomplexobj(got) or np.iscomplexobj(want) else np.float64)
+    num = np.linalg.norm((got - want).reshape(got.shape[0], -1), axis=1)
+    den = np.linalg.norm(np.asarray(want).reshape(got.shape[0], -1), axis=1)
+    return num / np.maximum(den, 1e-300)
+
+
+_OK = {"deriv": O.MULT_DERIV, "hilbert": O.MULT_HILBERT, "table": O.MULT_TABLE}
+_OO = {"identity": O.OUT_IDENTITY, "hilbert": O.OUT_HILBERT, "deriv": O.OUT_DERIV}
+
+
+def oracle_channels(channels, N, n1):
+    kinds = [_OK[k] for k, _ in channels]
+    orders = [int(v) if k != "table" else 0 for k, v in channels]
+    tabs = None
+    if any(k == "table" for k, _ in channels):
+        mu = len(channels) * N
+        tabs = np.zeros((len(channels), mu), dtype=complex)
+        for i, (k, v) in enumerate(channels):
+            if k == "table":
+                tabs[i] = v
+    return O.Channels(N=N, kinds=kinds, orders=orders, n1=n1, tables=tabs)
+
+
+def run_case(torch, N, n_out, channels, ops=(("identity", 0),), real=True, precision="f32", storage="native",
+             batch=3, n1=None, seed=0, allow_zero=False, g=None):
+    from paper_1802_10291_amd import Plan1D
+    M = len(channels)
+    ch = oracle_channels(channels, N, n1)
+    rng = np.random.default_rng(seed)
+    if g is None:
+        if real:
+            g = rng.standard_normal((batch, M, N))
+        else:
+            g = rng.standard_normal((batch, M, N)) + 1j * rng.standard_normal((batch, M, N))
+    np_dt = {"f64": np.float64, "f32": np.float32}[precision] if storage == "native" else np.float16
+    if real:
+        g_store = g.astype(np_dt)
+        g_ref = g_store.astype(np.float64)
+        g_dev = torch.from_numpy(g_store).cuda()
+    else:
+        parts = np.stack([g.real, g.imag], axis=-1).astype(np_dt)
+        g_ref = parts[..., 0].astype(np.float64) + 1j * parts[..., 1].astype(np.float64)
+        g_dev = torch.from_numpy(np.ascontiguousarray(parts)).cuda()
+    plan = Plan1D(N=N, n_out=n_out, channels=channels, ops=ops, n1=n1, real=real, precision=precision,
+                  storage=storage, allow_singular_zero=allow_zero)
+    y = plan.reconstruct(g_dev)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy().astype(np.float64)
+    if not real:
+        y = y[..., 0] + 1j * y[..., 1]
+    want = O.reconstruct_1d(ch, g_ref, n_out, ops=[_OO[o] for o, _ in ops], op_orders=[int(v) for _, v in ops],
+                            allow_singular_zero=allow_zero)
+    return y, want, plan
+
+
+def assert_parity(y, want, tol):
+    B, n_ops = y.shape[0], y.shape[1]
+    err = rel_l2(y.reshape(B * n_ops, -1), want.reshape(B * n_ops, -1))
+    assert err.max() <= tol, f"max rel L2 {err.max():.3e} > {tol:.0e} (median {np.median(err):.3e})"
+    return err
+
+
+# ----------------------------------------------------------------------- single signal, FP64
+def test_single_signal_fp64_exact(torch_cuda):
+    """The single-signal FP64 workload: f of degree 127 from {f, f'} with 128 samples each,
+    f and Hf on 4096 points; exact recovery and oracle match at 1e-12."""
+    g, n, a = S.single_signal_fp64(seed=1, degree=127, N=128)
+    y, want, plan = run_case(torch_cuda, 128, 4096, [("deriv", 0), ("deriv", 1)],
+                             ops=[("identity", 0), ("hilbert", 0)], precision="f64", g=g[None])
+    assert plan.info.n1 == -127
+    assert_parity(y, want, TOL["f64"])
+    tj = 2 * np.pi * np.arange(4096) / 4096
+    E = np.exp(1j * np.outer(tj, n))
+    f = (E @ a).real
+    Hf = (E @ (-1j * np.sign(n) * a)).real
+    assert np.linalg.norm(y[0, 0] - f) <= 1e-12 * np.linalg.norm(f)
+    assert np.linalg.norm(y[0, 1] - Hf) <= 1e-12 * np.linalg.norm(Hf)
+
+
+# ----------------------------------------------------------------------- parity sweep
+SWEEP = [
+    # N, n_out, channels, ops, real
+    (16, 64, [("deriv", 0), ("deriv", 1)], [("identity", 0)], True),
+    (24, 96, [("deriv", 0), ("deriv", 1), ("deriv", 2)], [("identity", 0), ("hilbert", 0)], True),
+    (13, 52, [("deriv", 0), ("deriv", 1), ("deriv", 2)], [("identity", 0)], True),        # Bluestein N
+    (11, 97, [("deriv", 0), ("hilbert", 0)], [("identity", 0), ("deriv", 1)], False),     # Bluestein n_out
+    (20, 30, [("deriv", 0), ("deriv", 1), ("deriv", 2), ("deriv", 3)], [("identity", 0)], True),  # n_out < mu folds
+    (9, 36, [("deriv", 0)], [("identity", 0), ("hilbert", 0)], True),
+    (1, 8, [("deriv", 0), ("deriv", 1)], [("identity", 0)], True),                        # one sample per channel
+    (7, 1, [("deriv", 0), ("deriv", 1)], [("identity", 0)], False),                       # one output point
+    (100, 700, [("deriv", 0), ("deriv", 1), ("deriv", 2)], [("identity", 0), ("deriv", 2)], True),
+    (128, 512, [("deriv", 0), ("deriv", 1)], [("identity", 0)], True),
+]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", range(len(SWEEP)))
+def test_parity_sweep(torch_cuda, precision, case):
+    N, n_out, channels, ops, real = SWEEP[case]
+    y, want, _ = run_case(torch_cuda, N, n_out, channels, ops=ops, real=real, precision=precision, seed=case)
+    assert_parity(y, want, TOL[precision])
+
+
+def test_parity_random_table_multipliers(torch_cuda):
+    rng = np.random.default_rng(7)
+    for M in (2, 3, 4):
+        N = 10
+        tabs = [("table", rng.standard_normal(M * N) + 1j * rng.standard_normal(M * N)) for _ in range(M)]
+        for precision in ("f64", "f32"):
+            y, want, plan = run_case(torch_cuda, N, 64, tabs, real=False, precision=precision, seed=M)
+            assert_parity(y, want, TOL[precision] * (10 if precision == "f32" else 1))
+
+
+def test_parity_f16_storage(torch_cuda):
+    y, want, _ = run_case(torch_cuda, 64, 256, [("deriv", 0), ("deriv", 1)], storage="f16", batch=4, seed=3)
+    assert_parity(y, want, TOL["f16"])
+
+
+def test_hilbert_only_singular_and_remark_3_4(torch_cuda):
+    from paper_1802_10291_amd import MCIError, Plan1D
+    with pytest.raises(MCIError) as ei:
+        Plan1D(N=9, n_out=40, channels=[("hilbert", 0)], real=False)
+    assert ei.value.status == 2
+    n, a = S.random_bandlimited(seed=3, n_lo=-4, n_hi=4)
+    a[4] = 0.0
+    g = S.sample_channels(n, a, [lambda k: -1j * np.sign(k)], 9)[None]
+    y, want, plan = run_case(torch_cuda, 9, 40, [("hilbert", 0)], real=False, precision="f64", g=g, allow_zero=True)
+    assert plan.info.n_singular == 1 and plan.info.first_singular == 0
+    assert_parity(y, want, TOL["f64"])
+    truth = np.exp(1j * np.outer(2 * np.pi * np.arange(40) / 40, n)) @ a
+    assert np.abs(y[0, 0] - truth).max() < 1e-12
+
+
+def test_ill_conditioned_rejected(torch_cuda):
+    from paper_1802_10291_amd import MCIError, Plan1D
+    with pytest.raises(MCIError) as ei:
+        Plan1D(N=64, n_out=256, channels=[("deriv", 0), ("deriv", 1), ("deriv", 2)], cond_max=1.5)
+    assert ei.value.status == 3
+    p = Plan1D(N=64, n_out=256, channels=[("deriv", 0), ("deriv", 1), ("deriv", 2)])
+    assert 1.0 <= p.info.max_cond < 100.0
+
+
+def test_batch_zero_is_noop(torch_cuda):
+    from paper_1802_10291_amd import Plan1D
+    p = Plan1D(N=16, n_out=64, channels=[("deriv", 0), ("deriv", 1)])
+    g = torch_cuda.zeros((0, 2, 16), device="cuda")
+    assert p.reconstruct(g).shape == (0, 1, 64)
+
+
+# ----------------------------------------------------------------------- batched FP32 workload
+def test_batched_fp32_small_batch_full_parity(torch_cuda):
+    """The batched FP32 workload's shape (M = 3 derivative channels, N = 1366, band
+    [-2048, 2049], 16384 output points) on a small batch, every output compared."""
+    g = S.smooth_noisy_batch(0, 4, 3, 1366, 8192)
+    y, want, plan = run_case(torch_cuda, 1366, 16384, [("deriv", 0), ("deriv", 1), ("deriv", 2)], g=g)
+    assert plan.info.n1 == -2048
+    err = assert_parity(y, want, TOL["f32"])
+    print("batched-fp32 small batch rel L2:", err)
+
+
+# ----------------------------------------------------------------------- 2-D
+@pytest.mark.parametrize("s", [2, 4])
+def test_2d_parity_small(torch_cuda, s):
+    from paper_1802_10291_amd import Plan2D
+    lr = SI.random_field_images(0, 2, 48, 40)
+    for precision, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        x = lr.astype(np.float64 if precision == "f64" else np.float32)
+        plan = Plan2D(48, 40, s, precision=precision)
+        hr = plan.upsample(torch_cuda.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
+        want = O.upsample_2d(x.astype(np.float64), s)
+        err = rel_l2(hr, want)
+        assert err.max() <= tol, err
+        assert np.abs(hr[:, ::s, ::s] - x).max() <= (1e-12 if precision == "f64" else 1e-5)

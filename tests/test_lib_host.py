@@ -1,0 +1,104 @@
+"""Host-side checks of libmci that need no GPU: the library loads, exports every symbol
+include/mci.h declares, its ctypes structures match the header's layout, and
+descriptor validation rejects bad input before any device call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mci.h")
+
+
+def _lib():
+    from paper_1802_10291_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libmci.so not built")
+    return L
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(mci_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared_functions()
+    for n in ("mci_plan", "mci_reconstruct_1d", "mci_upsample_2d", "mci_plan_2d", "mci_plan_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_declared_functions()) <= set(L.EXPORTS)
+
+
+def test_struct_sizes_match_c_layout():
+    L = _lib()
+    # int32 M, n_ops; int64 N, n1, n_out; 4 x {int32, int32, ptr}; 4 + 4 int32; 4 int32 fields; double
+    assert ctypes.sizeof(L.mci_channel) == 16
+    assert ctypes.sizeof(L.mci_plan_desc) == 8 + 24 + 64 + 32 + 16 + 8
+    assert L.mci_plan_desc.cond_max.offset == 144
+    assert ctypes.sizeof(L.mci_plan_info_t) == 56
+    assert ctypes.sizeof(L.mci_plan2d_desc) == 24
+
+
+def test_status_strings():
+    L = _lib()
+    lib = L.load()
+    for code, name in L.STATUS.items():
+        assert lib.mci_status_string(code).decode() == name
+
+
+def _desc(L, **kw):
+    d = L.mci_plan_desc()
+    d.M, d.n_ops, d.N, d.n1, d.n_out = 2, 1, 16, L.MCI_N1_DEFAULT, 64
+    d.ch[0].kind, d.ch[0].order = L.MCI_MULT_DERIV, 0
+    d.ch[1].kind, d.ch[1].order = L.MCI_MULT_DERIV, 1
+    d.ops[0] = L.MCI_OUT_IDENTITY
+    d.real_io, d.precision, d.storage = 1, L.MCI_F32, L.MCI_STORE_NATIVE
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("field,value", [("M", 0), ("M", 5), ("n_ops", 0), ("N", 0), ("n_out", 0),
+                                         ("precision", 7), ("storage", 9), ("real_io", 2), ("flags", 8)])
+def test_invalid_descriptors_rejected_without_device(field, value):
+    L = _lib()
+    lib = L.load()
+    d = _desc(L, **{field: value})
+    h = ctypes.c_void_p()
+    assert lib.mci_plan(ctypes.byref(d), 0, ctypes.byref(h)) == 1   # MCI_E_INVALID_ARG
+    assert h.value is None
+    assert lib.mci_last_error().decode()
+
+
+def test_invalid_channel_kinds_rejected():
+    L = _lib()
+    lib = L.load()
+    h = ctypes.c_void_p()
+    d = _desc(L)
+    d.ch[1].kind = 9
+    assert lib.mci_plan(ctypes.byref(d), 0, ctypes.byref(h)) == 1
+    d = _desc(L)
+    d.ch[1].kind = L.MCI_MULT_TABLE      # table channel without a table
+    assert lib.mci_plan(ctypes.byref(d), 0, ctypes.byref(h)) == 1
+    d = _desc(L, storage=L.MCI_STORE_F16, precision=L.MCI_F64)
+    assert lib.mci_plan(ctypes.byref(d), 0, ctypes.byref(h)) == 1
+
+
+def test_null_arguments_rejected():
+    L = _lib()
+    lib = L.load()
+    assert lib.mci_plan(None, 0, None) == 1
+    assert lib.mci_plan_destroy(None) == 0
+    assert lib.mci_reconstruct_1d(None, None, None, 1, None, 0, None) == 1
+    n = ctypes.c_size_t()
+    assert lib.mci_workspace_size(None, 1, ctypes.byref(n)) == 1
