@@ -1,0 +1,257 @@
+"""Throughput benchmark of the batched FP32 multichannel-interpolation workload on one GPU.
+
+Workload (default): 65536 independent real signals, each observed through M = 3
+derivative channels {f, f', f''} with N = 1366 samples per channel (band of
+mu = 4098 coefficients, [-2048, 2049]), reconstructed on a 16384-point grid (4x the
+4096-sample signal length), FP32 transforms.  Inputs are seeded synthetic signals with
+spectrum e^{-0.01|n|} CN(0,1) + 1e-3 CN(0,1) out to |n| = 8192 (not bandlimited): a
+pool of 8192 distinct signals tiled 8 times, resident in HBM before timing starts.
+
+A step is one mci_reconstruct_1d call over the whole batch (every step of the method:
+channel DFTs, per-residue apply, placement on the output grid, inverse DFT).  Prints
+one JSON line with throughput (reconstructed output samples/s), the roofline of the
+dominant kernel (timed with HIP events on its stream) and the FP64 CPU oracle on a
+bounded sample of the same workload, plus the relative error of that sample.
+
+  python bench.py [--steps K] [--warmup W] [--workload batched1d|sisr2|sisr4] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP32_VALU_PEAK_TFLOPS = 157.3   # vendor figure (packed FP32); 78.6 without packed instructions
+METRIC = "reconstructed samples/s (1-D batch, 2-D ×2/×4) vs HBM roofline; rel err vs FP64"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched1d", choices=["batched1d", "sisr2", "sisr4"])
+    ap.add_argument("--batch", type=int, default=0, help="override the batch size (0 = workload default)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="signals/images in the CPU sample (0 = default)")
+    return ap.parse_args()
+
+
+def source_hash(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name, khash, per_launch_units):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_hash") != khash or t.get("units_per_launch") != per_launch_units:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def time_steps(torch, fn, steps, warmup, stream):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [a.elapsed_time(b) for a, b in evs]
+    return wall, per
+
+
+def copy_bandwidth(torch, nbytes=2 << 30):
+    """Achievable HBM bandwidth of a plain device-to-device copy (read + write bytes)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(10):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / 10
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def bench_batched1d(args, torch):
+    from paper_1802_10291_amd import Plan1D
+    from synth import signals as S
+
+    B = args.batch or 65536
+    M, N, n_out, n_max = 3, 1366, 16384, 8192
+    pool = min(8192, B)
+    log(f"generating {pool} seeded signals (tiled to {B})")
+    from concurrent.futures import ThreadPoolExecutor
+    host = np.empty((pool, M, N), dtype=np.float32)
+    chunk = 256
+
+    def work(c):
+        n = min(chunk, pool - c)
+        host[c:c + n] = S.smooth_noisy_batch(c, n, M, N, n_max)
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(work, range(0, pool, chunk)))
+    dev_pool = torch.from_numpy(host).cuda()
+    g = dev_pool.repeat((B + pool - 1) // pool, 1, 1)[:B].contiguous()
+    del dev_pool
+    plan = Plan1D(N=N, n_out=n_out, channels=[("deriv", 0), ("deriv", 1), ("deriv", 2)], precision="f32")
+    info = plan.info
+    y = torch.empty((B, 1, n_out), dtype=torch.float32, device="cuda")
+    ws, need = plan.workspace(B)
+    stream = torch.cuda.current_stream()
+    log(f"plan: path={'fused' if info.path else 'multi-pass'} fwd_len={info.fft_len_fwd} inv_len={info.fft_len_inv} "
+        f"max_cond={info.max_cond:.3g} workspace={need / 2**30:.2f} GiB")
+
+    def step():
+        plan.reconstruct(g, out=y)
+
+    wall, per = time_steps(torch, step, args.steps, args.warmup, stream)
+    ms = float(np.mean(per))
+    samples = B * n_out
+    value = samples * args.steps / (sum(per) * 1e-3)
+    alg_bytes = B * (M * N * 4 + n_out * 4)
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    kernel_src = ["paper_1802_10291_amd/csrc/mci_fused.hip", "paper_1802_10291_amd/csrc/mci_device.h"] if info.path \
+        else ["paper_1802_10291_amd/csrc/mci_kernels.hip", "paper_1802_10291_amd/csrc/mci_device.h"]
+    khash = source_hash(kernel_src)
+    traffic = load_traffic("mci1d_batched_fp32", khash, B) if info.path else None
+    result = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "1-D batched FP32 MCI: 65536 signals x M=3 derivative channels {f,f',f''} x N=1366 "
+                               "samples (band mu=4098, [-2048,2049]) -> 16384-point grid",
+                   "batch": B, "M": M, "N": N, "n_out": n_out, "path": "fused" if info.path else "multi-pass"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "mci1d fused" if info.path else "whole multi-pass step",
+                     "algorithmic_bytes_per_launch": alg_bytes, "kernel_source_hash": khash},
+        "wall_s": wall,
+    }
+    # CPU oracle on a bounded sample of the same workload
+    if not args.no_cpu:
+        from oracle import oracle as O
+        ns = args.cpu_sample or 128
+        idx = np.linspace(0, B - 1, ns).astype(np.int64)
+        g_s = g[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+        y_s = y[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+        ch = O.Channels(N=N, kinds=[O.MULT_DERIV] * 3, orders=[0, 1, 2])
+        log(f"CPU oracle on {ns} signals with {O.num_threads()} threads")
+        t0 = time.perf_counter()
+        want = O.reconstruct_1d(ch, g_s, n_out)
+        dt = time.perf_counter() - t0
+        err = np.linalg.norm((y_s - want).reshape(ns, -1), axis=1) / np.linalg.norm(want.reshape(ns, -1), axis=1)
+        result["cpu_baseline"] = {"value": ns * n_out / dt, "unit": "samples/s", "cores": O.num_threads(),
+                                  "kind": "oracle",
+                                  "sample": f"{ns} of the {B} signals (evenly spaced indices), FP64 direct DFT + "
+                                            f"Gaussian elimination + direct trigonometric sum; {dt:.1f} s"}
+        result["rel_err_vs_fp64_oracle"] = {"max": float(err.max()), "median": float(np.median(err)),
+                                            "signals": int(ns)}
+    result["copy_bandwidth_GBs"] = copy_bandwidth(torch)
+    return result
+
+
+def bench_sisr(args, torch, s):
+    from paper_1802_10291_amd import Plan2D
+    from synth import images as SI
+
+    B = args.batch or 256
+    H = W = 512
+    h, w = H // s, W // s
+    pool = min(32, B)
+    log(f"generating {pool} seeded {H}x{W} images (tiled to {B}), decimating by {s}")
+    hr_host = SI.random_field_images(0, pool, H, W)
+    lr_host = SI.decimate(hr_host, s)
+    lr = torch.from_numpy(lr_host).cuda().repeat((B + pool - 1) // pool, 1, 1)[:B].contiguous()
+    plan = Plan2D(h, w, s)
+    out = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
+    ws, need = plan.workspace(B)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan.upsample(lr, out=out)
+
+    wall, per = time_steps(torch, step, args.steps, args.warmup, stream)
+    ms = float(np.mean(per))
+    px = B * H * W
+    value = px * args.steps / (sum(per) * 1e-3)
+    alg_bytes = B * (h * w * 4 + H * W * 4)
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    # quality vs the ground-truth images
+    up = out[:pool].cpu().numpy().astype(np.float64)
+    from oracle import oracle as O
+    psnr = [O.psnr(up[i], hr_host[i].astype(np.float64)) for i in range(pool)]
+    result = {
+        "metric": METRIC, "value": value, "unit": "px/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2-D separable MCI x{s}: {B} images {h}x{w} -> {H}x{W}, M=2 (line + centred "
+                               "difference) per axis", "batch": B, "scale": s},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "whole 2-D step",
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "psnr_db_mean": float(np.mean(psnr)),
+        "wall_s": wall,
+    }
+    if not args.no_cpu:
+        ns = args.cpu_sample or 2
+        t0 = time.perf_counter()
+        want = O.upsample_2d(lr_host[:ns].astype(np.float64), s)
+        dt = time.perf_counter() - t0
+        err = np.linalg.norm((up[:ns] - want).reshape(ns, -1), axis=1) / np.linalg.norm(want.reshape(ns, -1), axis=1)
+        result["cpu_baseline"] = {"value": ns * H * W / dt, "unit": "px/s", "cores": O.num_threads(),
+                                  "kind": "oracle", "sample": f"{ns} images; {dt:.1f} s"}
+        result["rel_err_vs_fp64_oracle"] = {"max": float(err.max()), "median": float(np.median(err)), "images": ns}
+    return result
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (each signal or image is "
+              "independent; see the sharding note in the design document). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    if args.workload == "batched1d":
+        res = bench_batched1d(args, torch)
+    else:
+        res = bench_sisr(args, torch, 2 if args.workload == "sisr2" else 4)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "mci_fused.h"
+#include "mci_host_util.h"
 #include "mci_internal.h"
 
 using namespace mci;
@@ -69,46 +70,6 @@ static int64_t next_7smooth(int64_t n) {
   }
 }
 
-// e^{-2 pi i k / L} in FP64: the angle is reduced through the exact integer k mod L
-static std::complex<double> root(int64_t k, int64_t L) {
-  k %= L;
-  if (k < 0) k += L;
-  const double a = -2.0 * M_PI * ((double)k / (double)L);
-  return {std::cos(a), std::sin(a)};
-}
-
-// Host FP64 Stockham FFT (sign S) used only to build Bluestein filter spectra at plan time.
-static void host_fft(std::vector<std::complex<double>>& x, const std::vector<int>& radices, int S) {
-  const int64_t L = (int64_t)x.size();
-  std::vector<std::complex<double>> y(L);
-  int64_t Ns = 1;
-  for (int R : radices) {
-    const int64_t nb = L / R;
-    for (int64_t j = 0; j < nb; ++j) {
-      const int64_t k = j % Ns;
-      std::complex<double> v[8], o[8];
-      for (int r = 0; r < R; ++r) {
-        std::complex<double> w = root(k * r * (L / (Ns * R)), L);
-        if (S > 0) w = std::conj(w);
-        v[r] = x[j + r * nb] * w;
-      }
-      for (int s = 0; s < R; ++s) {
-        std::complex<double> acc = 0;
-        for (int q = 0; q < R; ++q) {
-          std::complex<double> w = root((int64_t)((q * s) % R), R);
-          if (S > 0) w = std::conj(w);
-          acc += v[q] * w;
-        }
-        o[s] = acc;
-      }
-      const int64_t base = (j / Ns) * Ns * R + k;
-      for (int r = 0; r < R; ++r) y[base + r * Ns] = o[r];
-    }
-    x.swap(y);
-    Ns *= R;
-  }
-}
-
 template <typename C>
 static void* upload(const std::vector<std::complex<double>>& v, hipError_t& err) {
   std::vector<C> h(v.size());
@@ -137,7 +98,7 @@ static mci_status build_side(FftSide& f, int64_t len, int sign, int prec) {
   f.lexec = f.blue ? next_7smooth(2 * len - 1) : len;
   if (f.blue) factor_7smooth(f.lexec, f.radices);
   std::vector<std::complex<double>> tw(f.lexec);
-  for (int64_t k = 0; k < f.lexec; ++k) tw[k] = root(k, f.lexec);
+  for (int64_t k = 0; k < f.lexec; ++k) tw[k] = root_of_unity(k, f.lexec);
   hipError_t e;
   f.tw = prec == MCI_F64 ? upload<double2>(tw, e) : upload<float2>(tw, e);
   if (!f.tw) return fail(MCI_E_OUT_OF_MEMORY, "twiddle table");
@@ -146,9 +107,7 @@ static mci_status build_side(FftSide& f, int64_t len, int sign, int prec) {
   // chirp c[k] = e^{sign i pi k^2 / len}; k^2 reduced modulo 2 len exactly
   std::vector<std::complex<double>> c(len), b(f.lexec, 0.0);
   for (int64_t k = 0; k < len; ++k) {
-    const int64_t q = (int64_t)(((__int128)k * k) % (2 * len));
-    const double a = (double)sign * M_PI * ((double)q / (double)len);
-    c[k] = {std::cos(a), std::sin(a)};
+    c[k] = chirp_value(k, len, sign);
   }
   for (int64_t m = 0; m < len; ++m) {
     b[m] = std::conj(c[m]);

@@ -9,6 +9,11 @@ namespace mci {
 struct FusedPlan {
   int kind = 0;            // 0: no fused kernel for this plan
   void* tables = nullptr;  // device tables owned by the fused plan
+  void* args = nullptr;    // kernel argument block (host)
+  void* launch = nullptr;  // launcher of the chosen instantiation
+  int lds_bytes = 0;
+  int grid_cap = 0;
+  int ti = 1;              // output transforms run side by side
 };
 
 // Choose a fused kernel for the descriptor (kind stays 0 when none applies).

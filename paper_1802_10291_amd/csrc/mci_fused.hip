@@ -1,23 +1,548 @@
-// mci_fused.hip -- single-pass fused 1-D kernels.
+// mci_fused.hip -- single-pass fused kernel for batched real-mode 1-D reconstruction.
+//
+// One 256-thread workgroup handles one signal at a time (grid-stride over the batch) and
+// never leaves LDS between reading the M channel sample rows and writing the output row:
+//
+//  1. channel DFTs (Lemma 3.1): the real row g_m of length N = 2H is read as H complex
+//     pairs z[p] = g[2p] + i g[2p+1]; Z = DFT_H(z) runs as a power-of-two Stockham FFT,
+//     through Bluestein's chirp convolution when H is not a power of two (e.g. H = 683);
+//     X_m[k] = E[k] + e^{-2 pi i k / N} O[k], k = 0..H, with E, O the DFTs of the even and
+//     odd samples recovered from Z.  X_m[N - k] = conj X_m[k] covers the other half.
+//  2. apply (eq. matrixeqn1): for residue n = n1 + i, a(n + jN) = sum_m X_m[n mod N]
+//     Tab[m][j][i], Tab holding q_mj(n) o(n + jN) / N.  In real mode the output is
+//     Re sum_k a(k) e^{ikt} = sum_k S(k) e^{ikt} with S(k) = (a(k) + conj a(-k)) / 2.  The
+//     negatives of residue i's band positions all have residue i' = (-2 n1 - i) mod N,
+//     so one thread solving the pair {i, i'} owns S(|k|) for all of them: no atomics.
+//  3. output grid: with Q polyphase components, y[Q q + r] = sum_k S(k) w^{k r} e^{2 pi i k q / P}
+//     (P = n_out / Q, w = e^{2 pi i / n_out}); the components are real, so components
+//     r0 = 2c and r1 = 2c + 1 share one complex inverse FFT of length P:
+//     Zc[b] = sum_{k = b mod P} S(k) (w^{k r0} + i w^{k r1}),  y[Qq + r0] + i y[Qq + r1] = IDFT(Zc)[q].
+//     The last FFT pass leaves element q = tid + 256 c in thread tid, so the Q outputs
+//     of q are written by one vector store and a wave writes 64 consecutive q.
+//
+// The FFTs are register-staged Stockham passes: every thread holds E = L / 256 elements,
+// input slot c of a pass is element tid + 256 c for every radix, and so is output slot c
+// of the last pass -- which lets the Bluestein forward FFT, the pointwise product and the
+// inverse FFT run back to back in registers.
+#include <algorithm>
+#include <cstdlib>
+#include <complex>
+#include <vector>
+
+#include "mci_device.h"
 #include "mci_fused.h"
+#include "mci_host_util.h"
 
 namespace mci {
 
+constexpr int NT = 256;
+
+struct FusedArgs {
+  const void* g;
+  void* y;
+  int64_t batch;
+  int M, N, H, n1;
+  int Nout, K;        // K = max |k| over the band
+  int C, Ch, n_items; // residue pairing: i' = (C - i) mod N; canonical items
+  int zero_s;         // 1 when some |k| <= K is in neither the band nor its negative
+  const float2* twF;  // PF entries e^{-2 pi i k / PF}
+  const float2* chirp;  // H entries e^{-i pi k^2 / H} (Bluestein)
+  const float2* bhat;   // PF entries: DFT_PF of the conjugate chirp, / PF
+  const float2* wN;     // H + 1 entries e^{-2 pi i k / N}
+  const float2* tab;    // [M][M][N]: q_mj(n1 + i) o(.) / N
+  const float2* twI;    // P entries e^{-2 pi i k / P}
+  const float2* U;      // [Q/2][2K + 1]: w^{k r0} + i w^{k r1} for k = -K..K, w = e^{2 pi i / Nout}
+};
+
+// ---------------------------------------------------------------- register-staged FFT
+// LDS index with one padding slot per 16 complex values: the stride-R writes of the first
+// Stockham passes then spread over all banks.
+__device__ __forceinline__ int pad(int x) { return x + (x >> 4); }
+constexpr int padded(int n) { return n + (n >> 4) + 1; }
+
+template <int R, int S>
+__device__ __forceinline__ void dft_r(float2* u) {
+  if constexpr (R == 2) dft2<S>(u[0], u[1]);
+  else if constexpr (R == 4) dft4<S>(u[0], u[1], u[2], u[3]);
+  else if constexpr (R == 8) dft8<S>(u);
+  else {
+    static_assert(R == 16, "radix");
+    // 16 = 4 x 4: DFT4 over each stride-4 group, twiddles e^{S 2 pi i q s / 16}, DFT4 across
+    constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, h = 0.70710678118654752440f;
+    float2 a[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      a[q] = u[q]; a[q + 4] = u[q + 4]; a[q + 8] = u[q + 8]; a[q + 12] = u[q + 12];
+      dft4<S>(a[q], a[q + 4], a[q + 8], a[q + 12]);
+    }
+    const float cs[10] = {1.f, c1, h, s1, 0.f, -s1, -h, -c1, -1.f, -c1};
+    const float sn[10] = {0.f, s1, h, c1, 1.f, c1, h, s1, 0.f, -s1};
+#pragma unroll
+    for (int q = 1; q < 4; ++q)
+#pragma unroll
+      for (int s = 1; s < 4; ++s) {
+        const int m = q * s;
+        const float wc = cs[m], ws = (float)S * sn[m];
+        const float2 x = a[q + 4 * s];
+        a[q + 4 * s] = make_float2(x.x * wc - x.y * ws, x.x * ws + x.y * wc);
+      }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) dft4<S>(a[4 * s], a[4 * s + 1], a[4 * s + 2], a[4 * s + 3]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) u[s + 4 * t] = a[t + 4 * s];
+  }
+}
+
+// Powers w^r, r = 1..R-1, of a butterfly's base twiddle from two exact table entries
+// (w^1 and w^4): every power is at most three roundings away from a table value.
+template <int R, int S>
+__device__ __forceinline__ void twiddle_powers(const float2* __restrict__ tw, int k1, float2* w) {
+  float2 w1 = tw[k1];
+  if constexpr (S > 0) w1.y = -w1.y;
+  w[1] = w1;
+  if constexpr (R >= 4) {
+    w[2] = cmul(w1, w1);
+    w[3] = cmul(w[2], w1);
+  }
+  if constexpr (R >= 8) {
+    float2 w4 = tw[4 * k1];
+    if constexpr (S > 0) w4.y = -w4.y;
+    w[4] = w4;
+    w[5] = cmul(w4, w1);
+    w[6] = cmul(w4, w[2]);
+    w[7] = cmul(w4, w[3]);
+  }
+  if constexpr (R >= 16) {
+    const float2 w8 = cmul(w[4], w[4]);
+    const float2 w12 = cmul(w8, w[4]);
+    w[8] = w8;
+#pragma unroll
+    for (int b = 1; b < 4; ++b) {
+      w[8 + b] = cmul(w8, w[b]);
+      w[12 + b] = cmul(w12, w[b]);
+    }
+    w[12] = w12;
+  }
+}
+
+template <int... Rs> struct RList {};
+
+// T independent length-L transforms (buffer t at lds + t * padded(L)); one Stockham pass of
+// radix R at stage size NS, then the remaining passes.  On entry v[t][c] holds element
+// tid + NT c of transform t's pass input; after the last pass it holds element tid + NT c
+// of the transform.
+template <int L, int S, int T, int NS, int R, int... Rest>
+__device__ __forceinline__ void fft_passes(float2* __restrict__ lds, float2 (&v)[T][L / NT],
+                                           const float2* __restrict__ tw, RList<R, Rest...>) {
+  constexpr int E = L / NT;
+  constexpr int BPT = E / R;
+  constexpr int LP = padded(L);
+  static_assert(BPT * R == E, "radix must divide the elements per thread");
+  const int tid = threadIdx.x;
+  float2 u[T][BPT][R];
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    float2 w[R];
+    if constexpr (NS > 1) {
+      const int j = tid + NT * b;
+      twiddle_powers<R, S>(tw, (j % NS) * (L / (NS * R)), w);
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[t][b][r] = v[t][b + r * BPT];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) u[t][b][r] = cmul(u[t][b][r], w[r]);
+      }
+      dft_r<R, S>(u[t][b]);
+    }
+  }
+  if constexpr (sizeof...(Rest) == 0) {
+    static_assert(NS * R == L, "radices must multiply to L");
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int b = 0; b < BPT; ++b)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[t][b + r * BPT] = u[t][b][r];
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int b = 0; b < BPT; ++b) {
+        const int j = tid + NT * b;
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[t * LP + pad(base + r * NS)] = u[t][b][r];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int c = 0; c < E; ++c) v[t][c] = lds[t * LP + pad(tid + NT * c)];
+    fft_passes<L, S, T, NS * R>(lds, v, tw, RList<Rest...>{});
+  }
+}
+
+template <int L> struct Radices;
+template <> struct Radices<1024> { using type = RList<4, 4, 4, 4, 4>; };
+template <> struct Radices<2048> { using type = RList<8, 8, 8, 4>; };
+template <> struct Radices<4096> { using type = RList<16, 16, 16>; };
+
+template <int L, int S, int T>
+__device__ __forceinline__ void fft(float2* lds, float2 (&v)[T][L / NT], const float2* tw) {
+  fft_passes<L, S, T, 1>(lds, v, tw, typename Radices<L>::type{});
+}
+
+// ---------------------------------------------------------------- the fused kernel
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+
+// LDS use of one workgroup, in complex slots (see the layout in the kernel).
+// When all Q/2 output transforms run together S is dead once they are formed and their
+// scratch starts at 0; otherwise it starts after S, which later transforms still read.
+__host__ __device__ constexpr int fused_slots(int PF, int P, int TI, int Q, int M, int H, int K) {
+  const int fwd = M * padded(PF);
+  const int mid = (K + 1) + M * (H + 1) + M * H;
+  const int inv = (TI * 2 == Q ? 0 : K + 1) + TI * padded(P);
+  return fwd > mid ? (fwd > inv ? fwd : inv) : (mid > inv ? mid : inv);
+}
+
+// TI: how many of the Q/2 output transforms run side by side (1 or Q/2).
+template <int PF, bool BLUE, int P, int Q, int M, int TI>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_mci1d_fused(FusedArgs a) {
+  extern __shared__ float2 sm[];
+  constexpr int EF = PF / NT, EI = P / NT;
+  const int tid = threadIdx.x;
+  const int N = a.N, H = a.H, XH = a.H + 1;
+  // layout: forward scratch [M][padded(PF)] | S [K+1], X [M][H+1], Zc [M][H] | output scratch [TI][padded(P)]
+  float2* F = sm;
+  float2* Sv = sm;
+  float2* X = sm + (a.K + 1);
+  float2* Zc = X + M * XH;
+  float2* Z = (TI * 2 == Q) ? sm : sm + (a.K + 1);
+
+  for (int64_t sig = blockIdx.x; sig < a.batch; sig += gridDim.x) {
+    const float* gs = (const float*)a.g + sig * (int64_t)M * N;
+    // ---------------- 1. channel DFTs, all M channels side by side
+    {
+      float2 v[M][EF];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const float2* zin = (const float2*)(gs + (int64_t)m * N);
+#pragma unroll
+        for (int c = 0; c < EF; ++c) {
+          const int p = tid + NT * c;
+          float2 z = make_float2(0.f, 0.f);
+          if (p < H) z = zin[p];
+          v[m][c] = z;
+        }
+      }
+      if constexpr (BLUE) {
+#pragma unroll
+        for (int c = 0; c < EF; ++c) {
+          const int p = tid + NT * c;
+          if (p < H) {
+            const float2 ch = a.chirp[p];
+#pragma unroll
+            for (int m = 0; m < M; ++m) v[m][c] = cmul(v[m][c], ch);
+          }
+        }
+      }
+      fft<PF, -1, M>(F, v, a.twF);
+      if constexpr (BLUE) {
+#pragma unroll
+        for (int c = 0; c < EF; ++c) {
+          const float2 bh = a.bhat[tid + NT * c];
+#pragma unroll
+          for (int m = 0; m < M; ++m) v[m][c] = cmul(v[m][c], bh);
+        }
+        fft<PF, +1, M>(F, v, a.twF);
+#pragma unroll
+        for (int c = 0; c < EF; ++c) {
+          const int k = tid + NT * c;
+          if (k < H) {
+            const float2 ch = a.chirp[k];
+#pragma unroll
+            for (int m = 0; m < M; ++m) v[m][c] = cmul(v[m][c], ch);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int c = 0; c < EF; ++c) {
+          const int k = tid + NT * c;
+          if (k < H) Zc[m * H + k] = v[m][c];
+        }
+    }
+    __syncthreads();
+    if (a.zero_s)
+      for (int k = tid; k <= a.K; k += NT) Sv[k] = make_float2(0.f, 0.f);
+    for (int k = tid; k <= H; k += NT) {
+      const float2 wn = a.wN[k];
+      const int k1 = k == H ? 0 : k, k2 = k == 0 ? 0 : H - k;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const float2 z1 = Zc[m * H + k1];
+        const float2 z2 = conjf2(Zc[m * H + k2]);
+        const float2 e = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
+        const float2 o = make_float2(0.5f * (z1.y - z2.y), -0.5f * (z1.x - z2.x));   // (z1 - z2) / (2i)
+        X[m * XH + k] = cadd(e, cmul(wn, o));
+      }
+    }
+    __syncthreads();
+    // ---------------- 2. apply, residue pairs -> S
+    for (int it = tid; it < a.n_items; it += NT) {
+      const int i = it <= a.Ch ? it : a.C + 1 + (it - a.Ch - 1);
+      const int ip = i <= a.C ? a.C - i : a.C - i + N;
+      float2 av[2][M];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int ii = q ? ip : i;
+        int r = (a.n1 + ii) % N;
+        if (r < 0) r += N;
+        float2 d[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) d[m] = r <= H ? X[m * XH + r] : conjf2(X[m * XH + (N - r)]);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int m = 0; m < M; ++m) acc = cadd(acc, cmul(d[m], a.tab[(m * M + j) * N + ii]));
+          av[q][j] = acc;
+        }
+      }
+      const bool single = ip == i;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (q == 1 && single) break;
+        const int ii = q ? ip : i, io = q ? i : ip;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const int k = a.n1 + ii + j * N;
+          const int num = -k - a.n1 - io;        // partner -k = n1 + io + jp N
+          float2 pv = make_float2(0.f, 0.f);
+          bool has = false;
+#pragma unroll
+          for (int jp = 0; jp < M; ++jp)
+            if (num == jp * N) { has = true; pv = av[q ^ (single ? 0 : 1)][jp]; }
+          const float2 val = av[q][j];
+          if (k >= 0) Sv[k] = make_float2(0.5f * (val.x + pv.x), 0.5f * (val.y - pv.y));
+          else if (!has) Sv[-k] = make_float2(0.5f * val.x, -0.5f * val.y);
+        }
+      }
+    }
+    __syncthreads();
+    // ---------------- 3. output grid: Q/2 complex inverse FFTs of length P, TI at a time
+    float* ys = (float*)a.y + sig * (int64_t)a.Nout;
+#pragma unroll 1
+    for (int pc0 = 0; pc0 < Q / 2; pc0 += TI) {
+      float2 v[TI][EI];
+#pragma unroll
+      for (int t = 0; t < TI; ++t) {
+        const float2* U = a.U + (int64_t)(pc0 + t) * (2 * a.K + 1) + a.K;   // U[k], k = -K..K
+#pragma unroll
+        for (int c = 0; c < EI; ++c) {
+          const int b = tid + NT * c;
+          float2 acc = make_float2(0.f, 0.f);
+          if (b <= a.K) acc = cmul(Sv[b], U[b]);
+          const int k2 = b - P;                  // the other band position congruent to b (K < P)
+          if (k2 >= -a.K) acc = cadd(acc, cmul(conjf2(Sv[-k2]), U[k2]));
+          v[t][c] = acc;
+        }
+      }
+      fft<P, +1, TI>(Z, v, a.twI);
+      if constexpr (Q == 4 && TI == 2) {
+#pragma unroll
+        for (int c = 0; c < EI; ++c) {
+          const int q = tid + NT * c;
+          *(float4*)(ys + 4 * q) = make_float4(v[0][c].x, v[0][c].y, v[1][c].x, v[1][c].y);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < TI; ++t)
+#pragma unroll
+          for (int c = 0; c < EI; ++c) {
+            const int q = tid + NT * c;
+            *(float2*)(ys + Q * q + 2 * (pc0 + t)) = v[t][c];
+          }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- host side
+struct FusedTables {
+  float2 *twF, *chirp, *bhat, *wN, *twI, *wout;
+};
+
+template <int PF, bool BLUE, int P, int Q, int M, int TI>
+static hipError_t launch_mt(const FusedPlan& fp, const void* g, void* y, int64_t batch, hipStream_t s) {
+  FusedArgs a = *(const FusedArgs*)fp.args;
+  a.g = g;
+  a.y = y;
+  a.batch = batch;
+  const size_t lds = (size_t)fp.lds_bytes;
+  const int64_t grid = std::min<int64_t>(batch, (int64_t)fp.grid_cap);
+  auto kern = k_mci1d_fused<PF, BLUE, P, Q, M, TI>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int PF, bool BLUE, int P, int Q, int M>
+static hipError_t launch_m(const FusedPlan& fp, const void* g, void* y, int64_t batch, hipStream_t s) {
+  if (fp.ti == 2) return launch_mt<PF, BLUE, P, Q, M, 2>(fp, g, y, batch, s);
+  return launch_mt<PF, BLUE, P, Q, M, 1>(fp, g, y, batch, s);
+}
+
+template <int PF, bool BLUE, int P, int Q>
+static hipError_t launch_t(const FusedPlan& fp, const void* g, void* y, int64_t batch, hipStream_t s) {
+  switch (((const FusedArgs*)fp.args)->M) {
+    case 1: return launch_m<PF, BLUE, P, Q, 1>(fp, g, y, batch, s);
+    case 2: return launch_m<PF, BLUE, P, Q, 2>(fp, g, y, batch, s);
+    case 3: return launch_m<PF, BLUE, P, Q, 3>(fp, g, y, batch, s);
+    default: return launch_m<PF, BLUE, P, Q, 4>(fp, g, y, batch, s);
+  }
+}
+
+using LaunchFn = hipError_t (*)(const FusedPlan&, const void*, void*, int64_t, hipStream_t);
+
+struct Variant {
+  int PF;
+  bool blue;
+  int P, Q;
+  LaunchFn fn;
+};
+
+static const Variant kVariants[] = {
+    {2048, true, 4096, 4, launch_t<2048, true, 4096, 4>},
+    {1024, true, 4096, 4, launch_t<1024, true, 4096, 4>},
+    {1024, false, 4096, 4, launch_t<1024, false, 4096, 4>},
+    {2048, false, 4096, 4, launch_t<2048, false, 4096, 4>},
+    {2048, true, 2048, 4, launch_t<2048, true, 2048, 4>},
+    {1024, false, 1024, 4, launch_t<1024, false, 1024, 4>},
+    {2048, false, 2048, 4, launch_t<2048, false, 2048, 4>},
+};
+
+static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
 mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void* tab, FusedPlan& fp) {
-  (void)d; (void)prec; (void)store; (void)tab;
   fp.kind = 0;
+  if (prec != MCI_F32 || store != ST_F32 || !d.real_io || d.n_ops != 1 || d.M > MCI_MAX_CHANNELS) return MCI_OK;
+  if (std::getenv("MCI_DISABLE_FUSED")) return MCI_OK;
+  const int64_t N = d.N, M = d.M, n1 = d.n1, mu = M * N;
+  if (N % 2 || N < 4 || N > (1 << 15) || d.n_out > (1 << 20)) return MCI_OK;
+  const int64_t H = N / 2;
+  const int64_t K = std::max<int64_t>(std::llabs(n1), std::llabs(n1 + mu - 1));
+  const Variant* pick = nullptr;
+  for (const Variant& v : kVariants) {
+    const bool fwd_ok = v.blue ? (2 * H - 1 <= v.PF && !is_pow2(H)) : (H == v.PF);
+    if (!fwd_ok || (int64_t)v.P * v.Q != d.n_out) continue;
+    if (!pick || v.PF < pick->PF) pick = &v;
+  }
+  if (!pick || K >= pick->P) return MCI_OK;
+  int max_lds = 64 * 1024;
+  {
+    int dev = 0, v = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0) max_lds = v;
+  }
+  const char* ti_env = std::getenv("MCI_FUSED_TI");
+  int ti = (ti_env && std::atoi(ti_env) == 2) ? pick->Q / 2 : 1;
+  int64_t lds = (int64_t)fused_slots(pick->PF, pick->P, ti, pick->Q, (int)M, (int)H, (int)K) * (int64_t)sizeof(float2);
+  if (lds > max_lds && ti > 1) {
+    ti = 1;
+    lds = (int64_t)fused_slots(pick->PF, pick->P, ti, pick->Q, (int)M, (int)H, (int)K) * (int64_t)sizeof(float2);
+  }
+  if (lds > max_lds) return MCI_OK;
+
+  // tables (FP64 on the host, stored FP32)
+  const int PF = pick->PF, P = pick->P;
+  const int Q = pick->Q;
+  std::vector<std::complex<double>> twF(PF), chirp(H), bhat(PF, 0.0), wN(H + 1), twI(P), U((size_t)(Q / 2) * (2 * K + 1));
+  for (int k = 0; k < PF; ++k) twF[k] = root_of_unity(k, PF);
+  for (int64_t k = 0; k <= H; ++k) wN[k] = root_of_unity(k, N);
+  for (int k = 0; k < P; ++k) twI[k] = root_of_unity(k, P);
+  // U[pc][k + K] = w^{k r0} + i w^{k r1}, r0 = 2 pc, r1 = 2 pc + 1, w = e^{2 pi i / n_out}
+  for (int pc = 0; pc < Q / 2; ++pc)
+    for (int64_t k = -K; k <= K; ++k) {
+      const std::complex<double> w0 = std::conj(root_of_unity(k * (2 * pc), d.n_out));
+      const std::complex<double> w1 = std::conj(root_of_unity(k * (2 * pc + 1), d.n_out));
+      U[(size_t)pc * (2 * K + 1) + (k + K)] = w0 + std::complex<double>(0.0, 1.0) * w1;
+    }
+  if (pick->blue) {
+    for (int64_t k = 0; k < H; ++k) chirp[k] = chirp_value(k, H, -1);
+    for (int64_t m = 0; m < H; ++m) {
+      bhat[m] = std::conj(chirp[m]);
+      if (m) bhat[PF - m] = std::conj(chirp[m]);
+    }
+    std::vector<int> rad;
+    for (int64_t r = PF; r > 1; r /= 8) rad.push_back(r >= 8 ? 8 : (int)r);
+    host_fft(bhat, rad, -1);
+    for (auto& x : bhat) x /= (double)PF;
+  }
+  const size_t n_all = twF.size() + chirp.size() + bhat.size() + wN.size() + twI.size() + U.size();
+  std::vector<float2> h(n_all);
+  size_t o = 0;
+  auto put = [&](const std::vector<std::complex<double>>& v) {
+    const size_t at = o;
+    for (auto& x : v) h[o++] = make_float2((float)x.real(), (float)x.imag());
+    return at;
+  };
+  const size_t o_twF = put(twF), o_chirp = put(chirp), o_bhat = put(bhat), o_wN = put(wN), o_twI = put(twI),
+               o_U = put(U);
+  float2* dt = nullptr;
+  if (hipMalloc(&dt, n_all * sizeof(float2)) != hipSuccess) return MCI_E_OUT_OF_MEMORY;
+  if (hipMemcpy(dt, h.data(), n_all * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(dt);
+    return MCI_E_DEVICE;
+  }
+  FusedArgs* a = new FusedArgs();
+  a->M = (int)M; a->N = (int)N; a->H = (int)H; a->n1 = (int)n1;
+  a->Nout = (int)d.n_out; a->K = (int)K;
+  a->C = (int)((((-2 * n1) % N) + N) % N);
+  a->Ch = a->C / 2;
+  // S(k), 0 <= k <= K, is written by the apply iff k or -k lies in [n1, n1 + mu)
+  a->zero_s = (n1 > 0 || n1 + mu - 1 < 0) ? 1 : 0;
+  a->n_items = a->Ch + 1 + (int)((a->C + N) / 2 - a->C);
+  a->twF = dt + o_twF; a->chirp = dt + o_chirp; a->bhat = dt + o_bhat; a->wN = dt + o_wN;
+  a->tab = (const float2*)tab; a->twI = dt + o_twI; a->U = dt + o_U;
+  fp.tables = dt;
+  fp.args = a;
+  fp.lds_bytes = (int)lds;
+  fp.ti = ti;
+  fp.launch = (void*)pick->fn;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int cus = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int per_cu = std::max<int>(1, (int)((160 * 1024) / std::max<int64_t>(lds, 1)));
+  fp.grid_cap = std::max(1, cus) * std::min(per_cu, 8);
+  fp.kind = 1;
   return MCI_OK;
 }
 
 void fused_release(FusedPlan& fp) {
   if (fp.tables) (void)hipFree(fp.tables);
+  delete (FusedArgs*)fp.args;
   fp.tables = nullptr;
+  fp.args = nullptr;
   fp.kind = 0;
 }
 
 hipError_t fused_run(const FusedPlan& fp, const void* g, void* y, int64_t batch, hipStream_t s) {
-  (void)fp; (void)g; (void)y; (void)batch; (void)s;
-  return hipErrorInvalidValue;
+  return ((LaunchFn)fp.launch)(fp, g, y, batch, s);
 }
 
 }  // namespace mci

@@ -204,3 +204,43 @@ def test_2d_parity_small(torch_cuda, s):
         err = rel_l2(hr, want)
         assert err.max() <= tol, err
         assert np.abs(hr[:, ::s, ::s] - x).max() <= (1e-12 if precision == "f64" else 1e-5)
+
+
+# ----------------------------------------------------------------------- fused single-pass kernel
+FUSED = [
+    # N, n_out, channels, n1
+    (1366, 16384, [("deriv", 0), ("deriv", 1), ("deriv", 2)], None),    # Bluestein forward (H = 683)
+    (2048, 16384, [("deriv", 0), ("deriv", 1)], None),                  # direct forward (H = 1024)
+    (1000, 16384, [("deriv", 0), ("deriv", 1), ("deriv", 2)], None),    # Bluestein, PF = 1024
+    (1022, 8192, [("deriv", 0), ("deriv", 1), ("deriv", 2), ("deriv", 3)], None),  # M = 4, P = 2048
+    (1366, 16384, [("deriv", 0), ("deriv", 1), ("deriv", 2)], -2500),   # shifted band
+    (2048, 16384, [("deriv", 0), ("hilbert", 0)], None),                # Hilbert channel
+    (1000, 16384, [("deriv", 0), ("deriv", 1), ("deriv", 2)], 100),     # band not containing 0
+]
+
+
+@pytest.mark.parametrize("case", range(len(FUSED)))
+def test_fused_kernel_parity(torch_cuda, case):
+    N, n_out, channels, n1 = FUSED[case]
+    M = len(channels)
+    g = S.smooth_noisy_batch(10 * case, 3, M, N, 2 * N)
+    if channels[1][0] == "hilbert":
+        g = np.random.default_rng(case).standard_normal((3, M, N))
+    y, want, plan = run_case(torch_cuda, N, n_out, channels, g=g, n1=n1)
+    assert plan.info.path == 1, "expected the fused kernel"
+    assert_parity(y, want, TOL["f32"])
+
+
+def test_fused_matches_multipass(torch_cuda, monkeypatch):
+    """Both paths compute the same thing: compare them on a batch bigger than the grid."""
+    from paper_1802_10291_amd import Plan1D
+    g = torch_cuda.from_numpy(S.smooth_noisy_batch(0, 64, 3, 1366, 8192)).cuda()
+    chans = [("deriv", 0), ("deriv", 1), ("deriv", 2)]
+    fused = Plan1D(N=1366, n_out=16384, channels=chans)
+    monkeypatch.setenv("MCI_DISABLE_FUSED", "1")
+    multi = Plan1D(N=1366, n_out=16384, channels=chans)
+    assert fused.info.path == 1 and multi.info.path == 0
+    a = fused.reconstruct(g).cpu().numpy().astype(np.float64)
+    b = multi.reconstruct(g).cpu().numpy().astype(np.float64)
+    err = rel_l2(a.reshape(64, -1), b.reshape(64, -1))
+    assert err.max() < 2e-6, err.max()
