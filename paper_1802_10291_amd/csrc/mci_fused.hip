@@ -1,6 +1,6 @@
 // mci_fused.hip -- single-pass fused kernel for batched real-mode 1-D reconstruction.
 //
-// One 256-thread workgroup handles one signal at a time (grid-stride over the batch) and
+// One 256-thread workgroup handles one signal and
 // never leaves LDS between reading the M channel sample rows and writing the output row:
 //
 //  1. channel DFTs (Lemma 3.1): the real row g_m of length N = 2H is read as H complex
@@ -95,38 +95,6 @@ __device__ __forceinline__ void dft_r(float2* u) {
   }
 }
 
-// Powers w^r, r = 1..R-1, of a butterfly's base twiddle from two exact table entries
-// (w^1 and w^4): every power is at most three roundings away from a table value.
-template <int R, int S>
-__device__ __forceinline__ void twiddle_powers(const float2* __restrict__ tw, int k1, float2* w) {
-  float2 w1 = tw[k1];
-  if constexpr (S > 0) w1.y = -w1.y;
-  w[1] = w1;
-  if constexpr (R >= 4) {
-    w[2] = cmul(w1, w1);
-    w[3] = cmul(w[2], w1);
-  }
-  if constexpr (R >= 8) {
-    float2 w4 = tw[4 * k1];
-    if constexpr (S > 0) w4.y = -w4.y;
-    w[4] = w4;
-    w[5] = cmul(w4, w1);
-    w[6] = cmul(w4, w[2]);
-    w[7] = cmul(w4, w[3]);
-  }
-  if constexpr (R >= 16) {
-    const float2 w8 = cmul(w[4], w[4]);
-    const float2 w12 = cmul(w8, w[4]);
-    w[8] = w8;
-#pragma unroll
-    for (int b = 1; b < 4; ++b) {
-      w[8 + b] = cmul(w8, w[b]);
-      w[12 + b] = cmul(w12, w[b]);
-    }
-    w[12] = w12;
-  }
-}
-
 template <int... Rs> struct RList {};
 
 // T independent length-L transforms (buffer t at lds + t * padded(L)); one Stockham pass of
@@ -144,21 +112,50 @@ __device__ __forceinline__ void fft_passes(float2* __restrict__ lds, float2 (&v)
   float2 u[T][BPT][R];
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    float2 w[R];
-    if constexpr (NS > 1) {
-      const int j = tid + NT * b;
-      twiddle_powers<R, S>(tw, (j % NS) * (L / (NS * R)), w);
-    }
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
+    for (int t = 0; t < T; ++t)
 #pragma unroll
       for (int r = 0; r < R; ++r) u[t][b][r] = v[t][b + r * BPT];
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) u[t][b][r] = cmul(u[t][b][r], w[r]);
+    if constexpr (NS > 1) {
+      // powers w^r of the butterfly's base twiddle, formed as they are used; w^1 and w^4 are
+      // exact table entries, every other power is at most three roundings away from them
+      const int j = tid + NT * b;
+      const int k1 = (j % NS) * (L / (NS * R));
+      float2 w1 = tw[k1];
+      if constexpr (S > 0) w1.y = -w1.y;
+      float2 w4 = w1;
+      if constexpr (R >= 8) {
+        w4 = tw[4 * k1];
+        if constexpr (S > 0) w4.y = -w4.y;
       }
-      dft_r<R, S>(u[t][b]);
+      float2 wl[4];
+      wl[1] = w1;
+      if constexpr (R >= 4) {
+        wl[2] = cmul(w1, w1);
+        wl[3] = cmul(wl[2], w1);
+      }
+#pragma unroll
+      for (int r = 1; r < (R < 4 ? R : 4); ++r)
+#pragma unroll
+        for (int t = 0; t < T; ++t) u[t][b][r] = cmul(u[t][b][r], wl[r]);
+      if constexpr (R >= 8) {
+        float2 wh = w4;    // w^{4a}
+#pragma unroll
+        for (int a4 = 1; a4 < R / 4; ++a4) {
+          if (a4 > 1) wh = cmul(wh, w4);
+#pragma unroll
+          for (int t = 0; t < T; ++t) u[t][b][4 * a4] = cmul(u[t][b][4 * a4], wh);
+#pragma unroll
+          for (int r = 1; r < 4; ++r) {
+            const float2 w = cmul(wh, wl[r]);
+#pragma unroll
+            for (int t = 0; t < T; ++t) u[t][b][4 * a4 + r] = cmul(u[t][b][4 * a4 + r], w);
+          }
+        }
+      }
     }
+#pragma unroll
+    for (int t = 0; t < T; ++t) dft_r<R, S>(u[t][b]);
   }
   if constexpr (sizeof...(Rest) == 0) {
     static_assert(NS * R == L, "radices must multiply to L");
@@ -213,7 +210,7 @@ __host__ __device__ constexpr int fused_slots(int PF, int P, int TI, int Q, int 
 
 // TI: how many of the Q/2 output transforms run side by side (1 or Q/2).
 template <int PF, bool BLUE, int P, int Q, int M, int TI>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
 void k_mci1d_fused(FusedArgs a) {
   extern __shared__ float2 sm[];
   constexpr int EF = PF / NT, EI = P / NT;
@@ -226,7 +223,10 @@ void k_mci1d_fused(FusedArgs a) {
   float2* Zc = X + M * XH;
   float2* Z = (TI * 2 == Q) ? sm : sm + (a.K + 1);
 
-  for (int64_t sig = blockIdx.x; sig < a.batch; sig += gridDim.x) {
+  {
+    // one signal per workgroup: a persistent loop would keep the loop invariants of every
+    // phase live across the whole body and cut the occupancy
+    const int64_t sig = blockIdx.x;
     const float* gs = (const float*)a.g + sig * (int64_t)M * N;
     // ---------------- 1. channel DFTs, all M channels side by side
     {
@@ -390,7 +390,7 @@ static hipError_t launch_mt(const FusedPlan& fp, const void* g, void* y, int64_t
   a.y = y;
   a.batch = batch;
   const size_t lds = (size_t)fp.lds_bytes;
-  const int64_t grid = std::min<int64_t>(batch, (int64_t)fp.grid_cap);
+  const int64_t grid = batch;   // one signal per workgroup
   auto kern = k_mci1d_fused<PF, BLUE, P, Q, M, TI>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
