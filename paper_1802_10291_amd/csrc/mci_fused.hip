@@ -341,7 +341,8 @@ void k_mci1d_fused(FusedArgs a) {
     __syncthreads();
     // ---------------- 3. output grid: Q/2 complex inverse FFTs of length P, TI at a time
     float* ys = (float*)a.y + sig * (int64_t)a.Nout;
-#pragma unroll 1
+    float2 keep[(Q / 2 - TI > 0 ? Q / 2 - TI : 1)][EI];   // earlier transforms' outputs
+#pragma unroll
     for (int pc0 = 0; pc0 < Q / 2; pc0 += TI) {
       float2 v[TI][EI];
 #pragma unroll
@@ -358,20 +359,24 @@ void k_mci1d_fused(FusedArgs a) {
         }
       }
       fft<P, +1, TI>(Z, v, a.twI);
-      if constexpr (Q == 4 && TI == 2) {
-#pragma unroll
-        for (int c = 0; c < EI; ++c) {
-          const int q = tid + NT * c;
-          *(float4*)(ys + 4 * q) = make_float4(v[0][c].x, v[0][c].y, v[1][c].x, v[1][c].y);
-        }
-      } else {
+      if (pc0 + TI < Q / 2) {
 #pragma unroll
         for (int t = 0; t < TI; ++t)
 #pragma unroll
-          for (int c = 0; c < EI; ++c) {
-            const int q = tid + NT * c;
-            *(float2*)(ys + Q * q + 2 * (pc0 + t)) = v[t][c];
-          }
+          for (int c = 0; c < EI; ++c) keep[pc0 + t][c] = v[t][c];
+        continue;
+      }
+      // all Q outputs of element q are in this thread: one vector store per q
+#pragma unroll
+      for (int c = 0; c < EI; ++c) {
+        const int q = tid + NT * c;
+        if constexpr (Q == 4) {
+          const float2 lo = TI == 2 ? v[0][c] : keep[0][c];
+          const float2 hi = TI == 2 ? v[TI - 1][c] : v[0][c];
+          *(float4*)(ys + 4 * q) = make_float4(lo.x, lo.y, hi.x, hi.y);
+        } else {
+          *(float2*)(ys + 2 * q) = v[0][c];
+        }
       }
     }
     __syncthreads();
