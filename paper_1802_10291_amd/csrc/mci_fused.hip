@@ -59,6 +59,7 @@ struct FusedArgs {
 // Stockham passes then spread over all banks.
 __device__ __forceinline__ int pad(int x) { return x + (x >> 4); }
 constexpr int padded(int n) { return n + (n >> 4) + 1; }
+static_assert(NT % 16 == 0, "pad(tid + NT c) = pad(tid) + c (NT + NT / 16) needs NT % 16 == 0");
 
 template <int R, int S>
 __device__ __forceinline__ void dft_r(float2* u) {
@@ -166,21 +167,25 @@ __device__ __forceinline__ void fft_passes(float2* __restrict__ lds, float2 (&v)
 #pragma unroll
         for (int r = 0; r < R; ++r) v[t][b + r * BPT] = u[t][b][r];
   } else {
+    // For power-of-two NS and R, base % 16 + (r NS) % 16 < 16, so
+    // pad(base + r NS) = pad(base) + r NS + (r NS) / 16: one address per butterfly, the
+    // rest are immediate offsets.  Likewise pad(tid + NT c) = pad(tid) + c (NT + NT / 16).
     __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      const int j = tid + NT * b;
+      const int pb = pad((j / NS) * NS * R + (j % NS));
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[t * LP + pb + r * NS + (r * NS) / 16] = u[t][b][r];
+    }
+    __syncthreads();
+    const int pt = pad(tid);
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int b = 0; b < BPT; ++b) {
-        const int j = tid + NT * b;
-        const int base = (j / NS) * NS * R + (j % NS);
-#pragma unroll
-        for (int r = 0; r < R; ++r) lds[t * LP + pad(base + r * NS)] = u[t][b][r];
-      }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-      for (int c = 0; c < E; ++c) v[t][c] = lds[t * LP + pad(tid + NT * c)];
+      for (int c = 0; c < E; ++c) v[t][c] = lds[t * LP + pt + c * (NT + NT / 16)];
     fft_passes<L, S, T, NS * R>(lds, v, tw, RList<Rest...>{});
   }
 }
