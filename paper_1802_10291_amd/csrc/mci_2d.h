@@ -1,0 +1,27 @@
+// mci_2d.h -- fused line passes of the separable 2-D upsampling.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <vector>
+
+#include "mci_internal.h"
+
+namespace mci {
+
+struct LinePassArgs {
+  const void* x;
+  void* y;
+  int64_t lines;       // rows mode: number of lines
+  int64_t W;           // columns mode: columns per image (lines per image)
+  const float2* H;     // [SC][N] polyphase windows
+  const float2* tw;    // N entries e^{-2 pi i k / N}
+};
+
+bool line_pass_supported(int N, int SC);
+std::vector<std::complex<double>> line_windows(const std::vector<std::complex<double>>& tab, int64_t N, int64_t n1,
+                                               int SC);
+hipError_t run_line_pass(int N, int SC, bool cols, int store_in, int store_out, const LinePassArgs& a,
+                         int64_t images, hipStream_t s);
+
+}  // namespace mci

@@ -1,0 +1,313 @@
+// mci_2d.hip -- fused line-pass kernels for separable 2-D upsampling (Section 5.2).
+//
+// One pass reconstructs every line of length N (rows or columns) from the channels {x, Dx},
+// Dx the circular centred difference (x[p+1] - x[p-1]) N / (4 pi) whose Fourier multiplier is
+// fd(n) = i N sin(2 pi n / N) / (2 pi), with multipliers {1, i n} on the band [n1, n1 + 2N),
+// and keeps the real part on the grid s times finer.  Composed, these steps are a real
+// linear map that commutes with shifting the line by one sample (and the output by s):
+//   a(k) = X(k mod N) G(k),  G(n + jN) = Tab[0][j][i] + fd(n) Tab[1][j][i]   (eq. matrixeqn1),
+//   S(k) = (a(k) + conj a(-k)) / 2 = X(k mod N) Wr(k),  Wr(k) = (G(k) + conj G(-k)) / 2,
+// with X the DFT of the line.  Splitting the output into its s polyphase components,
+//   y[s q + r] = sum_k S(k) e^{2 pi i k (s q + r) / (s N)} = IDFT_N(X H_r)[q],
+//   H_r[k'] = sum_{k = k' mod N} Wr(k) e^{2 pi i k r / (s N)},
+// so a pass is one length-N DFT, s products with fixed windows H_r and s inverse DFTs.  The
+// windows are built at plan time in FP64 from the FP64 per-residue inverses.  The map is
+// complex-linear, so two real lines a, b go through it together as z = a + i b: Re of the
+// result is line a upsampled, Im is line b.
+//
+// A workgroup takes 32 lines (16 pairs); lanes are grouped G = N / 16 per pair and hold 16
+// elements each (element l + G c in lane l).  Both transforms are two Stockham passes.
+// Columns run first (input and output go through LDS tiles so global accesses stay
+// row-contiguous), rows last (the output rows leave straight from registers as s-float
+// vectors, G lanes covering 128 contiguous bytes).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+#include <complex>
+#include <vector>
+
+#include "mci_2d.h"
+#include "mci_device.h"
+#include "mci_host_util.h"
+
+namespace mci {
+
+namespace l2d {
+
+constexpr int LINES = 32;   // lines per workgroup
+constexpr int PAIRS = 16;
+
+__device__ __forceinline__ int pad(int x) { return x + (x >> 4); }
+constexpr int padded(int n) { return n + (n >> 4) + 1; }
+
+template <int R, int S>
+__device__ __forceinline__ void dft_r(float2* u) {
+  if constexpr (R == 2) dft2<S>(u[0], u[1]);
+  else if constexpr (R == 4) dft4<S>(u[0], u[1], u[2], u[3]);
+  else if constexpr (R == 8) dft8<S>(u);
+  else {
+    static_assert(R == 16, "radix");
+    constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, h = 0.70710678118654752440f;
+    float2 a[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      a[q] = u[q]; a[q + 4] = u[q + 4]; a[q + 8] = u[q + 8]; a[q + 12] = u[q + 12];
+      dft4<S>(a[q], a[q + 4], a[q + 8], a[q + 12]);
+    }
+    const float cs[10] = {1.f, c1, h, s1, 0.f, -s1, -h, -c1, -1.f, -c1};
+    const float sn[10] = {0.f, s1, h, c1, 1.f, c1, h, s1, 0.f, -s1};
+#pragma unroll
+    for (int q = 1; q < 4; ++q)
+#pragma unroll
+      for (int s = 1; s < 4; ++s) {
+        const int m = q * s;
+        const float wc = cs[m], ws = (float)S * sn[m];
+        const float2 x = a[q + 4 * s];
+        a[q + 4 * s] = make_float2(x.x * wc - x.y * ws, x.x * ws + x.y * wc);
+      }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) dft4<S>(a[4 * s], a[4 * s + 1], a[4 * s + 2], a[4 * s + 3]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) u[s + 4 * t] = a[t + 4 * s];
+  }
+}
+
+template <int... Rs> struct RList {};
+
+// Length-L transform by a group of G lanes (lane l holds elements l + G c, c < E = L / G);
+// buffer = this group's LDS scratch of padded(L) slots.  Same Stockham scheme as the 1-D
+// kernel; the whole workgroup passes the barriers together.
+template <int L, int G, int S, int NS, int R, int... Rest>
+__device__ __forceinline__ void gfft_passes(float2* __restrict__ buf, int l, float2 (&v)[L / G],
+                                            const float2* __restrict__ tw, RList<R, Rest...>) {
+  constexpr int E = L / G;
+  constexpr int BPT = E / R;
+  static_assert(BPT * R == E, "radix must divide the elements per lane");
+  float2 u[BPT][R];
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[b][r] = v[b + r * BPT];
+    if constexpr (NS > 1) {
+      const int j = l + G * b;
+      const int k1 = (j % NS) * (L / (NS * R));
+      float2 w1 = tw[k1];
+      if constexpr (S > 0) w1.y = -w1.y;
+      float2 w = w1;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        if (r > 1) w = (r % 4 == 0) ? [&] { float2 t = tw[r * k1]; if constexpr (S > 0) t.y = -t.y; return t; }()
+                                    : cmul(w, w1);
+        u[b][r] = cmul(u[b][r], w);
+      }
+    }
+    dft_r<R, S>(u[b]);
+  }
+  if constexpr (sizeof...(Rest) == 0) {
+#pragma unroll
+    for (int b = 0; b < BPT; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b + r * BPT] = u[b][r];
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      const int j = l + G * b;
+      const int pb = pad((j / NS) * NS * R + (j % NS));
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[pb + r * NS + (r * NS) / 16] = u[b][r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < E; ++c) v[c] = buf[pad(l + G * c)];
+    gfft_passes<L, G, S, NS * R>(buf, l, v, tw, RList<Rest...>{});
+  }
+}
+
+template <int L> struct Radices16;   // E = 16 elements per lane
+template <> struct Radices16<64> { using type = RList<16, 4>; };
+template <> struct Radices16<128> { using type = RList<16, 8>; };
+template <> struct Radices16<256> { using type = RList<16, 16>; };
+
+template <int L, int S>
+__device__ __forceinline__ void gfft(float2* buf, int l, float2 (&v)[16], const float2* tw) {
+  gfft_passes<L, L / 16, S, 1>(buf, l, v, tw, typename Radices16<L>::type{});
+}
+
+// COLS: lines are the columns of x [B][N][W] (blockIdx.x = block of 32 columns, blockIdx.y =
+// image); output [B][SC N][W].  Rows: lines are the rows of x [lines][N], output [lines][SC N].
+template <int N, int SC, bool COLS, typename TI, typename TO>
+__global__ __launch_bounds__(N) void k_line_pass(LinePassArgs a) {
+  constexpr int G = N / 16, E = 16, NT = N;
+  extern __shared__ float2 sm2[];
+  float* tile = (float*)sm2;                   // input [32][N + 1] floats
+  float* otile = (float*)sm2;                  // output half tile [SC N / 2][32 + 1] floats (columns)
+  const int tid = threadIdx.x;
+  const int g = tid / G, l = tid % G;          // pair g = lines 2g, 2g + 1
+  float2* buf = sm2 + g * padded(N);           // FFT scratch of pair g
+  constexpr int TS = N + 1;
+  const TI* x = (const TI*)a.x;
+  TO* y = (TO*)a.y;
+  int64_t line0;
+  int64_t img = 0, col0 = 0;
+  if constexpr (COLS) {
+    col0 = (int64_t)blockIdx.x * LINES;
+    img = blockIdx.y;
+  } else {
+    line0 = (int64_t)blockIdx.x * LINES;
+  }
+  // ---- load 32 lines into the tile (line-major)
+  if constexpr (COLS) {
+    // row n of image img, columns col0 .. col0 + 31: 32 contiguous values per row
+    for (int e = tid; e < N * LINES; e += NT) {
+      const int n = e / LINES, c = e % LINES;
+      const int64_t col = col0 + c;
+      float v = 0.f;
+      if (col < a.W) v = ld_as<float>(x, (img * N + n) * (int64_t)a.W + col);
+      tile[c * TS + n] = v;
+    }
+  } else {
+    for (int e = tid; e < N * LINES; e += NT) {
+      const int c = e / N, n = e % N;
+      const int64_t line = line0 + c;
+      float v = 0.f;
+      if (line < a.lines) v = ld_as<float>(x, line * N + n);
+      tile[c * TS + n] = v;
+    }
+  }
+  __syncthreads();
+  float2 z[E];
+#pragma unroll
+  for (int c = 0; c < E; ++c) {
+    const int n = l + G * c;
+    z[c] = make_float2(tile[(2 * g) * TS + n], tile[(2 * g + 1) * TS + n]);
+  }
+  // the tile and the scratch share LDS: gfft's first store waits on a barrier
+  gfft<N, -1>(buf, l, z, a.tw);
+  float2 out[SC][E];
+#pragma unroll
+  for (int r = 0; r < SC; ++r) {
+    float2 v[E];
+#pragma unroll
+    for (int c = 0; c < E; ++c) v[c] = cmul(z[c], a.H[r * N + l + G * c]);
+    gfft<N, +1>(buf, l, v, a.tw);
+#pragma unroll
+    for (int c = 0; c < E; ++c) out[r][c] = v[c];
+  }
+  if constexpr (!COLS) {
+    // rows: line 2g gets Re, line 2g + 1 gets Im; SC consecutive outputs per q
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      const int64_t line = line0 + 2 * g + h2;
+      if (line >= a.lines) continue;
+      TO* yl = y + line * (int64_t)(SC * N);
+#pragma unroll
+      for (int c = 0; c < E; ++c) {
+        const int q = l + G * c;
+        float o[SC];
+#pragma unroll
+        for (int r = 0; r < SC; ++r) o[r] = h2 ? out[r][c].y : out[r][c].x;
+        if constexpr (std::is_same<TO, float>::value && SC == 4) {
+          *(float4*)(yl + 4 * q) = make_float4(o[0], o[1], o[2], o[3]);
+        } else if constexpr (std::is_same<TO, float>::value && SC == 2) {
+          *(float2*)(yl + 2 * q) = make_float2(o[0], o[1]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < SC; ++r) st_as<float>(yl, (int64_t)SC * q + r, o[r]);
+        }
+      }
+    }
+  } else {
+    // columns: output rows SC q + r; two halves (q < N/2, q >= N/2) through an LDS tile
+    constexpr int OT = LINES + 1;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      __syncthreads();
+#pragma unroll
+      for (int c = half * (E / 2); c < (half + 1) * (E / 2); ++c) {
+        const int q = l + G * c;
+#pragma unroll
+        for (int r = 0; r < SC; ++r) {
+          const int row = SC * q + r - half * (SC * N / 2);
+          otile[row * OT + 2 * g] = out[r][c].x;
+          otile[row * OT + 2 * g + 1] = out[r][c].y;
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < (SC * N / 2) * LINES; e += NT) {
+        const int row = e / LINES, c = e % LINES;
+        const int64_t col = col0 + c;
+        if (col < a.W)
+          st_as<float>(y, (img * (SC * N) + half * (SC * N / 2) + row) * (int64_t)a.W + col, otile[row * OT + c]);
+      }
+    }
+  }
+}
+
+template <int N, int SC, bool COLS, typename TI, typename TO>
+static hipError_t launch(const LinePassArgs& a, int64_t images, hipStream_t s) {
+  const size_t tile = (size_t)LINES * (N + 1) * sizeof(float);
+  const size_t scratch = (size_t)PAIRS * padded(N) * sizeof(float2);
+  const size_t otile = COLS ? (size_t)(SC * N / 2) * (LINES + 1) * sizeof(float) : 0;
+  const size_t lds = std::max(tile, std::max(scratch, otile));
+  dim3 grid;
+  if constexpr (COLS) grid = dim3((unsigned)((a.W + LINES - 1) / LINES), (unsigned)images);
+  else grid = dim3((unsigned)((a.lines + LINES - 1) / LINES));
+  hipLaunchKernelGGL((k_line_pass<N, SC, COLS, TI, TO>), grid, dim3(N), lds, s, a);
+  return hipGetLastError();
+}
+
+template <bool COLS, typename TI, typename TO>
+static hipError_t dispatch(int N, int SC, const LinePassArgs& a, int64_t images, hipStream_t s) {
+#define MCI_LP(NN, SS) \
+  if (N == NN && SC == SS) return launch<NN, SS, COLS, TI, TO>(a, images, s);
+  MCI_LP(64, 2) MCI_LP(64, 4) MCI_LP(128, 2) MCI_LP(128, 4) MCI_LP(256, 2) MCI_LP(256, 4)
+#undef MCI_LP
+  return hipErrorInvalidValue;
+}
+
+}  // namespace l2d
+
+bool line_pass_supported(int N, int SC) { return (N == 64 || N == 128 || N == 256) && (SC == 2 || SC == 4); }
+
+// Polyphase windows of one axis from the FP64 apply table Tab[2][2][N] (identity output,
+// channels {x, Dx}, multipliers {1, i n}).  Returns H[SC][N] (FP64).
+std::vector<std::complex<double>> line_windows(const std::vector<std::complex<double>>& tab, int64_t N, int64_t n1,
+                                               int SC) {
+  using C = std::complex<double>;
+  const int64_t mu = 2 * N;
+  const int64_t K = std::max<int64_t>(std::llabs(n1), std::llabs(n1 + mu - 1));
+  std::vector<C> G(2 * K + 1, 0.0);  // G(k), k = -K..K, zero outside the band
+  for (int64_t i = 0; i < N; ++i) {
+    const int64_t n = n1 + i;
+    const double s = std::sin(2.0 * M_PI * (double)(((n % N) + N) % N) / (double)N);
+    const C fd(0.0, (double)N * s / (2.0 * M_PI));
+    for (int j = 0; j < 2; ++j) {
+      const int64_t k = n + j * N;
+      G[k + K] = tab[(0 * 2 + j) * N + i] + fd * tab[(1 * 2 + j) * N + i];
+    }
+  }
+  std::vector<C> H((size_t)SC * N, 0.0);
+  for (int64_t k = -K; k <= K; ++k) {
+    const C wr = 0.5 * (G[k + K] + std::conj(G[-k + K]));
+    if (wr == 0.0) continue;
+    const int64_t kp = ((k % N) + N) % N;
+    for (int r = 0; r < SC; ++r) H[(size_t)r * N + kp] += wr * std::conj(root_of_unity(k * r, SC * N));
+  }
+  return H;
+}
+
+hipError_t run_line_pass(int N, int SC, bool cols, int store_in, int store_out, const LinePassArgs& a,
+                         int64_t images, hipStream_t s) {
+  if (cols) {
+    if (store_in == ST_F16) return l2d::dispatch<true, __half, float>(N, SC, a, images, s);
+    return l2d::dispatch<true, float, float>(N, SC, a, images, s);
+  }
+  if (store_out == ST_F16) return l2d::dispatch<false, float, __half>(N, SC, a, images, s);
+  return l2d::dispatch<false, float, float>(N, SC, a, images, s);
+}
+
+}  // namespace mci

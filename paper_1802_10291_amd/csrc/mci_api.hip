@@ -5,12 +5,14 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <new>
 #include <string>
 #include <vector>
 
+#include "mci_2d.h"
 #include "mci_fused.h"
 #include "mci_host_util.h"
 #include "mci_internal.h"
@@ -42,6 +44,11 @@ struct mci_plan_s {
   double max_cond = 0.0;
   int64_t n_sing = 0, first_sing = INT64_MIN;
   FusedPlan fused;          // single-pass kernel choice (fused.kind == 0: none)
+  std::vector<std::complex<double>> tab_host;   // FP64 apply table [n_ops][M][M][N]
+  // 2-D fused line passes: windows H[SC][len] and twiddles per axis (cols, rows)
+  bool lp = false;
+  void* lp_H[2] = {nullptr, nullptr};
+  void* lp_tw[2] = {nullptr, nullptr};
   // 2-D
   mci_plan2d_desc d2{};
   mci_plan_s* rows = nullptr;
@@ -156,6 +163,10 @@ static mci_status validate(const mci_plan_desc* d) {
 
 static void destroy_plan(mci_plan_s* p) {
   if (!p) return;
+  for (int a = 0; a < 2; ++a) {
+    if (p->lp_H[a]) (void)hipFree(p->lp_H[a]);
+    if (p->lp_tw[a]) (void)hipFree(p->lp_tw[a]);
+  }
   if (p->tab) (void)hipFree(p->tab);
   free_side(p->fwd);
   free_side(p->inv);
@@ -256,6 +267,15 @@ static mci_status build_plan(const mci_plan_desc* desc, int device, mci_plan_s**
     destroy_plan(p);
     return fail(MCI_E_ILL_CONDITIONED, "max condition number " + std::to_string(c));
   }
+  {
+    std::vector<double2> h64(ntab);
+    if ((e = hipMemcpy(h64.data(), tab64, ntab * sizeof(double2), hipMemcpyDeviceToHost)) != hipSuccess) {
+      destroy_plan(p);
+      return fail(MCI_E_DEVICE, "table readback");
+    }
+    p->tab_host.resize(ntab);
+    for (size_t q = 0; q < ntab; ++q) p->tab_host[q] = {h64[q].x, h64[q].y};
+  }
   // keep the table in plan precision
   if (p->prec == MCI_F64) {
     if ((e = hipMalloc(&p->tab, ntab * sizeof(double2))) != hipSuccess) { destroy_plan(p); return fail(MCI_E_OUT_OF_MEMORY, "tab"); }
@@ -289,6 +309,7 @@ static size_t ws_1d(const mci_plan_s* p, int64_t batch) {
 
 static size_t ws_2d(const mci_plan_s* p, int64_t batch) {
   if (batch <= 0) return 0;
+  if (p->lp) return (size_t)batch * p->d2.scale * p->d2.h * p->d2.w * sizeof(float) + 256;
   const int64_t h = p->d2.h, w = p->d2.w, s = p->d2.scale;
   const size_t e = p->prec == MCI_F64 ? 8 : 4;
   auto al = [](size_t n) { return (n + 255) & ~(size_t)255; };
@@ -344,7 +365,7 @@ mci_status mci_plan_info(mci_plan_t p, mci_plan_info_t* info) {
   info->n1 = q->d.n1;
   info->fft_len_fwd = q->fwd.lexec;
   info->fft_len_inv = q->inv.lexec;
-  info->path = p->dims == 2 ? (p->rows->fused.kind ? 1 : 0) : (p->fused.kind ? 1 : 0);
+  info->path = p->dims == 2 ? (p->lp ? 1 : 0) : (p->fused.kind ? 1 : 0);
   info->reserved = 0;
   return MCI_OK;
 }
@@ -405,6 +426,23 @@ mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out)
     if (st != MCI_OK) { destroy_plan(p); return st; }
     (axis == 0 ? p->rows : p->cols) = q;
   }
+  if (desc->precision == MCI_F32 && line_pass_supported(desc->h, desc->scale) &&
+      line_pass_supported(desc->w, desc->scale) && !std::getenv("MCI_DISABLE_FUSED")) {
+    // axis 0: columns (length h), axis 1: rows (length w)
+    for (int axis = 0; axis < 2; ++axis) {
+      const mci_plan_s* q = axis == 0 ? p->cols : p->rows;
+      const int64_t len = q->d.N;
+      std::vector<std::complex<double>> H = line_windows(q->tab_host, len, q->d.n1, desc->scale);
+      std::vector<std::complex<double>> tw(len);
+      for (int64_t k = 0; k < len; ++k) tw[k] = root_of_unity(k, len);
+      hipError_t e;
+      p->lp_H[axis] = upload<float2>(H, e);
+      if (!p->lp_H[axis] || e != hipSuccess) { destroy_plan(p); return fail(MCI_E_DEVICE, "window upload"); }
+      p->lp_tw[axis] = upload<float2>(tw, e);
+      if (!p->lp_tw[axis] || e != hipSuccess) { destroy_plan(p); return fail(MCI_E_DEVICE, "twiddle upload"); }
+    }
+    p->lp = true;
+  }
   *out = p;
   return MCI_OK;
 }
@@ -418,6 +456,18 @@ mci_status mci_upsample_2d(mci_plan_t p, const void* lr, void* hr, int64_t batch
   const size_t need = ws_2d(p, batch);
   if (!workspace || ws_bytes < need) return fail(MCI_E_INVALID_ARG, "workspace too small: need " + std::to_string(need));
   HIP_TRY(hipSetDevice(p->device));
+  if (p->lp) {
+    // columns first: lr [B][h][w] -> mid [B][s h][w]; then rows: mid -> hr [B][s h][s w]
+    const int64_t h = p->d2.h, w = p->d2.w, sc = p->d2.scale;
+    float* mid = (float*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    LinePassArgs ac{lr, mid, 0, w, (const float2*)p->lp_H[0], (const float2*)p->lp_tw[0]};
+    hipError_t err = run_line_pass((int)h, (int)sc, true, p->store, ST_F32, ac, batch, stream);
+    if (err != hipSuccess) return fail(MCI_E_DEVICE, std::string("column pass: ") + hipGetErrorString(err));
+    LinePassArgs ar{mid, hr, batch * sc * h, 0, (const float2*)p->lp_H[1], (const float2*)p->lp_tw[1]};
+    err = run_line_pass((int)w, (int)sc, false, ST_F32, p->store, ar, 0, stream);
+    if (err != hipSuccess) return fail(MCI_E_DEVICE, std::string("row pass: ") + hipGetErrorString(err));
+    return MCI_OK;
+  }
   const int64_t h = p->d2.h, w = p->d2.w, s = p->d2.scale, H = s * h, W = s * w;
   const size_t e = p->prec == MCI_F64 ? 8 : 4;
   auto al = [](size_t n) { return (n + 255) & ~(size_t)255; };

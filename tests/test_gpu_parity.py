@@ -244,3 +244,30 @@ def test_fused_matches_multipass(torch_cuda, monkeypatch):
     b = multi.reconstruct(g).cpu().numpy().astype(np.float64)
     err = rel_l2(a.reshape(64, -1), b.reshape(64, -1))
     assert err.max() < 2e-6, err.max()
+
+
+# ----------------------------------------------------------------------- fused 2-D line passes
+@pytest.mark.parametrize("h,w,s", [(256, 256, 2), (128, 128, 4), (64, 128, 2), (128, 64, 4), (256, 128, 4)])
+def test_2d_line_pass_parity(torch_cuda, h, w, s):
+    """Columns then rows through the polyphase-window line passes, against the FP64 oracle
+    (rows then columns: the two passes act on different axes and commute)."""
+    from paper_1802_10291_amd import Plan2D
+    lr = SI.random_field_images(7, 2, h, w)
+    plan = Plan2D(h, w, s)
+    assert plan.info.path == 1
+    hr = plan.upsample(torch_cuda.from_numpy(lr).cuda()).cpu().numpy().astype(np.float64)
+    want = O.upsample_2d(lr.astype(np.float64), s)
+    err = rel_l2(hr, want)
+    assert err.max() <= 1e-5, err
+    assert np.abs(hr[:, ::s, ::s] - lr).max() <= 1e-5
+
+
+def test_2d_line_pass_ragged_batch(torch_cuda):
+    """Batch sizes that leave partial 32-line blocks in the row pass."""
+    from paper_1802_10291_amd import Plan2D
+    lr = SI.random_field_images(11, 3, 64, 64)
+    plan = Plan2D(64, 64, 2)
+    for b in (1, 3):
+        hr = plan.upsample(torch_cuda.from_numpy(lr[:b]).cuda()).cpu().numpy().astype(np.float64)
+        want = O.upsample_2d(lr[:b].astype(np.float64), 2)
+        assert rel_l2(hr, want).max() <= 1e-5
