@@ -173,6 +173,47 @@ mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out)
 mci_status mci_upsample_2d(mci_plan_t plan, const void* lr, void* hr, int64_t batch, void* workspace,
                            size_t ws_bytes, hipStream_t stream);
 
+/* ----------------------------------------------------------------------------------- */
+/* Learned residual refiner (not part of the paper; its closing remarks on Section 5.2   */
+/* suggest MCI as the interpolation stage of learning-based super-resolution).          */
+/* y = u + CNN(u), u the MCI upsample of an RGB image, CNN = conv3x3 3->32, ReLU,        */
+/* conv3x3 32->32, ReLU, conv3x3 32->32, ReLU, conv3x3 32->3 (zero padding), BF16 MFMA    */
+/* with FP32 accumulation, FP32 master weights and Adam state.  Images are FP32           */
+/* [batch][3][h][w] device arrays; h and w are any positive sizes.                         */
+/* Parameter vector (20259 FP32): W1[32][9][3], b1[32], W2[32][9][32], b2[32],            */
+/* W3[32][9][32], b3[32], W4[3][9][32], b4[3]; W[co][tap][ci], tap = 3 dy + dx.            */
+/* ----------------------------------------------------------------------------------- */
+typedef struct mci_refiner_s* mci_refiner_t;
+
+/* Create a refiner on `device` with seeded He-normal hidden weights and a near-zero last
+ * layer (starts close to y = u).  Fallback bound tau = 0 until set. */
+mci_status mci_refiner_create(int device, uint64_t seed, mci_refiner_t* out);
+mci_status mci_refiner_destroy(mci_refiner_t r);
+int64_t mci_refiner_num_params(void);
+/* Copy the FP32 parameters (and the fallback bound) to / from host memory (checkpointing). */
+mci_status mci_refiner_get_params(mci_refiner_t r, float* host_params, float* tau);
+mci_status mci_refiner_set_params(mci_refiner_t r, const float* host_params, float tau);
+/* Gradient of the last backward / train step, FP32 host copy in the parameter layout. */
+mci_status mci_refiner_get_grads(mci_refiner_t r, float* host_grads);
+/* Device scratch for a batch of `batch` images of h x w (activations, gradients, partials). */
+mci_status mci_refiner_workspace_size(int64_t batch, int h, int w, size_t* bytes);
+/* y = u + CNN(u).  With ratio != NULL, ratio[b] = ||y_b - u_b|| / ||u_b|| (device, [batch]);
+ * with apply_fallback, images whose ratio exceeds tau (or is NaN) are replaced by u and
+ * used[b] (device int) records 1 for refined, 0 for fallback. */
+mci_status mci_refiner_forward(mci_refiner_t r, const float* u, float* y, int64_t batch, int h, int w,
+                               int apply_fallback, float* ratio, int* used, void* workspace, size_t ws_bytes,
+                               hipStream_t stream);
+/* Gradient of the loss mean((u + CNN(u) - hr)^2) over all batch*3*h*w values.  loss_parts
+ * (device, >= 1024 floats) receives per-block partial sums of the squared error, *n_parts
+ * their count. */
+mci_status mci_refiner_backward(mci_refiner_t r, const float* u, const float* hr, int64_t batch, int h, int w,
+                                float* loss_parts, int* n_parts, void* workspace, size_t ws_bytes, hipStream_t stream);
+/* backward, then one Adam step (beta 0.9 / 0.999, eps 1e-8) with learning rate lr. */
+mci_status mci_refiner_train_step(mci_refiner_t r, const float* u, const float* hr, int64_t batch, int h, int w,
+                                  float lr, float* loss_parts, int* n_parts, void* workspace, size_t ws_bytes,
+                                  hipStream_t stream);
+const char* mci_refiner_last_error(void);
+
 /* mci_status_string -- static text for a status code. */
 const char* mci_status_string(mci_status s);
 

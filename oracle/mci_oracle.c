@@ -494,3 +494,165 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------------ */
+/* Residual CNN refiner y = u + CNN(u) (an addition to the paper's method, used as   */
+/* the learned stage of super-resolution).  Plain FP64 loops over planar [C][H][W]    */
+/* images, zero padding.  Parameter vector: W1[32][9][3] b1[32] W2[32][9][32] b2[32]   */
+/* W3[32][9][32] b3[32] W4[3][9][32] b4[3], W[co][tap][ci], tap = 3 dy + dx, the tap   */
+/* reading input pixel (y + dy - 1, x + dx - 1).                                      */
+/* ------------------------------------------------------------------------------ */
+enum { CNN_NPARAM = 32 * 27 + 32 + 2 * (32 * 288 + 32) + 3 * 288 + 3 };
+
+static void cnn_offsets(int64_t off[8]) {
+  off[0] = 0;                      /* W1 */
+  off[1] = off[0] + 32 * 27;       /* b1 */
+  off[2] = off[1] + 32;            /* W2 */
+  off[3] = off[2] + 32 * 288;      /* b2 */
+  off[4] = off[3] + 32;            /* W3 */
+  off[5] = off[4] + 32 * 288;      /* b3 */
+  off[6] = off[5] + 32;            /* W4 */
+  off[7] = off[6] + 3 * 288;       /* b4 */
+}
+
+/* out[co][y][x] = b[co] + sum_{ci,dy,dx} W[co][3dy+dx][ci] in[ci][y+dy-1][x+dx-1] */
+static void conv3x3(int cin, int cout, int H, int W, const double *w, const double *b, const double *in, double *out) {
+#pragma omp parallel for schedule(static)
+  for (int co = 0; co < cout; ++co)
+    for (int y = 0; y < H; ++y)
+      for (int x = 0; x < W; ++x) {
+        double s = b ? b[co] : 0.0;
+        for (int dy = 0; dy < 3; ++dy) {
+          const int yy = y + dy - 1;
+          if (yy < 0 || yy >= H) continue;
+          for (int dx = 0; dx < 3; ++dx) {
+            const int xx = x + dx - 1;
+            if (xx < 0 || xx >= W) continue;
+            for (int ci = 0; ci < cin; ++ci)
+              s += w[((size_t)co * 9 + dy * 3 + dx) * cin + ci] * in[((size_t)ci * H + yy) * W + xx];
+          }
+        }
+        out[((size_t)co * H + y) * W + x] = s;
+      }
+}
+
+static void relu_inplace(double *a, size_t n) {
+  for (size_t i = 0; i < n; ++i) a[i] = a[i] > 0.0 ? a[i] : 0.0;
+}
+
+/* y = u + CNN(u) for `batch` images [3][H][W]; optionally the three hidden activations of
+ * the last image ([32][H][W] each, after ReLU) */
+int orc_cnn_forward(const double *p, int64_t batch, int H, int W, const double *u, double *y) {
+  int64_t off[8];
+  cnn_offsets(off);
+  const size_t hw = (size_t)H * W;
+  double *a1 = (double *)malloc(sizeof(double) * 32 * hw), *a2 = (double *)malloc(sizeof(double) * 32 * hw);
+  double *r = (double *)malloc(sizeof(double) * 3 * hw);
+  if (!a1 || !a2 || !r) { free(a1); free(a2); free(r); return ORC_E_NOMEM; }
+  for (int64_t b = 0; b < batch; ++b) {
+    const double *ub = u + (size_t)b * 3 * hw;
+    conv3x3(3, 32, H, W, p + off[0], p + off[1], ub, a1); relu_inplace(a1, 32 * hw);
+    conv3x3(32, 32, H, W, p + off[2], p + off[3], a1, a2); relu_inplace(a2, 32 * hw);
+    conv3x3(32, 32, H, W, p + off[4], p + off[5], a2, a1); relu_inplace(a1, 32 * hw);
+    conv3x3(32, 3, H, W, p + off[6], p + off[7], a1, r);
+    for (size_t i = 0; i < 3 * hw; ++i) y[(size_t)b * 3 * hw + i] = ub[i] + r[i];
+  }
+  free(a1); free(a2); free(r);
+  return ORC_OK;
+}
+
+/* Backward of one conv layer: given gout = dL/dout [cout][H][W] and its input in [cin][H][W],
+ * accumulate dW, db and (if gin != NULL) write gin = dL/din. */
+static void conv3x3_backward(int cin, int cout, int H, int W, const double *w, const double *in, const double *gout,
+                             double *gw, double *gb, double *gin) {
+  const size_t hw = (size_t)H * W;
+#pragma omp parallel for schedule(static)
+  for (int co = 0; co < cout; ++co) {
+    double sb = 0.0;
+    for (size_t i = 0; i < hw; ++i) sb += gout[(size_t)co * hw + i];
+    gb[co] += sb;
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3, dx = t % 3;
+      for (int ci = 0; ci < cin; ++ci) {
+        double s = 0.0;
+        for (int y = 0; y < H; ++y) {
+          const int yy = y + dy - 1;
+          if (yy < 0 || yy >= H) continue;
+          for (int x = 0; x < W; ++x) {
+            const int xx = x + dx - 1;
+            if (xx < 0 || xx >= W) continue;
+            s += gout[((size_t)co * H + y) * W + x] * in[((size_t)ci * H + yy) * W + xx];
+          }
+        }
+        gw[((size_t)co * 9 + t) * cin + ci] += s;
+      }
+    }
+  }
+  if (!gin) return;
+  /* gin[ci][yy][xx] = sum over (co, tap) with y = yy - dy + 1, x = xx - dx + 1 in range */
+#pragma omp parallel for schedule(static)
+  for (int ci = 0; ci < cin; ++ci)
+    for (int yy = 0; yy < H; ++yy)
+      for (int xx = 0; xx < W; ++xx) {
+        double s = 0.0;
+        for (int dy = 0; dy < 3; ++dy) {
+          const int y = yy - dy + 1;
+          if (y < 0 || y >= H) continue;
+          for (int dx = 0; dx < 3; ++dx) {
+            const int x = xx - dx + 1;
+            if (x < 0 || x >= W) continue;
+            for (int co = 0; co < cout; ++co)
+              s += gout[((size_t)co * H + y) * W + x] * w[((size_t)co * 9 + dy * 3 + dx) * cin + ci];
+          }
+        }
+        gin[((size_t)ci * H + yy) * W + xx] = s;
+      }
+}
+
+/* loss = mean over all batch*3*H*W values of (u + CNN(u) - hr)^2, and its gradient with
+ * respect to the parameter vector */
+int orc_cnn_grad(const double *p, int64_t batch, int H, int W, const double *u, const double *hr, double *grad,
+                 double *loss) {
+  int64_t off[8];
+  cnn_offsets(off);
+  const size_t hw = (size_t)H * W;
+  const double count = (double)batch * 3.0 * (double)hw;
+  double *z1 = malloc(sizeof(double) * 32 * hw), *a1 = malloc(sizeof(double) * 32 * hw);
+  double *z2 = malloc(sizeof(double) * 32 * hw), *a2 = malloc(sizeof(double) * 32 * hw);
+  double *z3 = malloc(sizeof(double) * 32 * hw), *a3 = malloc(sizeof(double) * 32 * hw);
+  double *r = malloc(sizeof(double) * 3 * hw), *g4 = malloc(sizeof(double) * 3 * hw);
+  double *ga = malloc(sizeof(double) * 32 * hw), *gb = malloc(sizeof(double) * 32 * hw);
+  if (!z1 || !a1 || !z2 || !a2 || !z3 || !a3 || !r || !g4 || !ga || !gb) {
+    free(z1); free(a1); free(z2); free(a2); free(z3); free(a3); free(r); free(g4); free(ga); free(gb);
+    return ORC_E_NOMEM;
+  }
+  for (int i = 0; i < CNN_NPARAM; ++i) grad[i] = 0.0;
+  double se = 0.0;
+  for (int64_t b = 0; b < batch; ++b) {
+    const double *ub = u + (size_t)b * 3 * hw, *hb = hr + (size_t)b * 3 * hw;
+    conv3x3(3, 32, H, W, p + off[0], p + off[1], ub, z1);
+    for (size_t i = 0; i < 32 * hw; ++i) a1[i] = z1[i] > 0 ? z1[i] : 0.0;
+    conv3x3(32, 32, H, W, p + off[2], p + off[3], a1, z2);
+    for (size_t i = 0; i < 32 * hw; ++i) a2[i] = z2[i] > 0 ? z2[i] : 0.0;
+    conv3x3(32, 32, H, W, p + off[4], p + off[5], a2, z3);
+    for (size_t i = 0; i < 32 * hw; ++i) a3[i] = z3[i] > 0 ? z3[i] : 0.0;
+    conv3x3(32, 3, H, W, p + off[6], p + off[7], a3, r);
+    for (size_t i = 0; i < 3 * hw; ++i) {
+      const double d = ub[i] + r[i] - hb[i];
+      se += d * d;
+      g4[i] = 2.0 * d / count;
+    }
+    conv3x3_backward(32, 3, H, W, p + off[6], a3, g4, grad + off[6], grad + off[7], ga);
+    for (size_t i = 0; i < 32 * hw; ++i) ga[i] = z3[i] > 0 ? ga[i] : 0.0;
+    conv3x3_backward(32, 32, H, W, p + off[4], a2, ga, grad + off[4], grad + off[5], gb);
+    for (size_t i = 0; i < 32 * hw; ++i) gb[i] = z2[i] > 0 ? gb[i] : 0.0;
+    conv3x3_backward(32, 32, H, W, p + off[2], a1, gb, grad + off[2], grad + off[3], ga);
+    for (size_t i = 0; i < 32 * hw; ++i) ga[i] = z1[i] > 0 ? ga[i] : 0.0;
+    conv3x3_backward(3, 32, H, W, p + off[0], ub, ga, grad + off[0], grad + off[1], NULL);
+  }
+  *loss = se / count;
+  free(z1); free(a1); free(z2); free(a2); free(z3); free(a3); free(r); free(g4); free(ga); free(gb);
+  return ORC_OK;
+}
+
+int orc_cnn_num_params(void) { return CNN_NPARAM; }

@@ -281,3 +281,49 @@ def psnr(img: np.ndarray, ref: np.ndarray, clip: bool = True) -> float:
     x = np.clip(img, 0.0, 1.0) if clip else img
     mse = float(np.mean((np.asarray(x, dtype=np.float64) - ref) ** 2))
     return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
+
+
+# ------------------------------------------------------------------ residual CNN refiner
+CNN_SLICES = {}
+_o = 0
+for _name, _n in (("W1", 32 * 27), ("b1", 32), ("W2", 32 * 288), ("b2", 32), ("W3", 32 * 288), ("b3", 32),
+                  ("W4", 3 * 288), ("b4", 3)):
+    CNN_SLICES[_name] = slice(_o, _o + _n)
+    _o += _n
+CNN_NPARAM = _o
+
+
+def _cnn_lib():
+    lib = _load()
+    if not hasattr(lib, "_cnn_ready"):
+        P = ctypes.POINTER
+        pd = P(ctypes.c_double)
+        lib.orc_cnn_forward.argtypes = [pd, ctypes.c_int64, ctypes.c_int, ctypes.c_int, pd, pd]
+        lib.orc_cnn_grad.argtypes = [pd, ctypes.c_int64, ctypes.c_int, ctypes.c_int, pd, pd, pd, pd]
+        lib.orc_cnn_forward.restype = ctypes.c_int
+        lib.orc_cnn_grad.restype = ctypes.c_int
+        lib._cnn_ready = True
+    return lib
+
+
+def cnn_forward(params: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """y = u + CNN(u) for images u [B][3][H][W] (FP64, zero padding)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    assert p.size == CNN_NPARAM
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    B, c, H, W = u.shape
+    y = np.empty_like(u)
+    _check(_cnn_lib().orc_cnn_forward(_pd(p), B, H, W, _pd(u), _pd(y)))
+    return y
+
+
+def cnn_grad(params: np.ndarray, u: np.ndarray, hr: np.ndarray):
+    """(loss, grad): loss = mean((u + CNN(u) - hr)^2), grad = dloss/dparams (FP64)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    hr = np.ascontiguousarray(hr, dtype=np.float64)
+    B, c, H, W = u.shape
+    g = np.zeros(CNN_NPARAM)
+    loss = ctypes.c_double(0.0)
+    _check(_cnn_lib().orc_cnn_grad(_pd(p), B, H, W, _pd(u), _pd(hr), _pd(g), ctypes.byref(loss)))
+    return loss.value, g

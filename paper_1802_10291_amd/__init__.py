@@ -183,3 +183,106 @@ class Plan2D:
             self.close()
         except Exception:
             pass
+
+
+class Refiner:
+    """Learned residual refiner y = u + CNN(u) (``mci_refiner_*``): BF16 MFMA kernels, FP32
+    master weights, Adam.  Images are float32 cuda tensors [B, 3, H, W]."""
+
+    def __init__(self, seed: int = 0, device: int = 0):
+        lib = _lib.load_refiner()
+        h = ctypes.c_void_p()
+        _lib.rcheck(lib.mci_refiner_create(device, seed, ctypes.byref(h)), "mci_refiner_create")
+        self.handle, self.device = h.value, device
+        self.n_params = int(lib.mci_refiner_num_params())
+        self._ws = None
+        self._lp = None
+
+    def _workspace(self, B, H, W):
+        torch = _torch()
+        n = ctypes.c_size_t()
+        _lib.rcheck(_lib.load_refiner().mci_refiner_workspace_size(B, H, W, ctypes.byref(n)), "workspace_size")
+        if self._ws is None or self._ws.numel() < n.value:
+            self._ws = torch.empty(n.value, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws, n.value
+
+    @staticmethod
+    def _check_img(t):
+        if not t.is_cuda or t.dtype != _torch().float32 or t.dim() != 4 or t.shape[1] != 3 or not t.is_contiguous():
+            raise ValueError("images must be contiguous float32 cuda tensors [B, 3, H, W]")
+
+    def get_params(self):
+        p = np.empty(self.n_params, dtype=np.float32)
+        tau = ctypes.c_float()
+        _lib.rcheck(_lib.load_refiner().mci_refiner_get_params(self.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                               ctypes.byref(tau)), "get_params")
+        return p, tau.value
+
+    def set_params(self, params, tau: float = 0.0):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.n_params:
+            raise ValueError("wrong parameter count")
+        _lib.rcheck(_lib.load_refiner().mci_refiner_set_params(self.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                               float(tau)), "set_params")
+
+    def get_grads(self):
+        g = np.empty(self.n_params, dtype=np.float32)
+        _lib.rcheck(_lib.load_refiner().mci_refiner_get_grads(self.handle, g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+                    "get_grads")
+        return g
+
+    def forward(self, u, fallback: bool = False, out=None):
+        """Returns (y, ratio, used): ratio[b] = ||y_b - u_b|| / ||u_b||; with fallback, images
+        above the stored bound get y_b = u_b and used[b] = 0."""
+        torch = _torch()
+        self._check_img(u)
+        B, _, H, W = u.shape
+        y = torch.empty_like(u) if out is None else out
+        ratio = torch.empty(B, dtype=torch.float32, device=u.device)
+        used = torch.ones(B, dtype=torch.int32, device=u.device)
+        ws, n = self._workspace(B, H, W)
+        _lib.rcheck(_lib.load_refiner().mci_refiner_forward(self.handle, u.data_ptr(), y.data_ptr(), B, H, W, int(fallback),
+                                                            ratio.data_ptr(), used.data_ptr(), ws.data_ptr(), n,
+                                                            _stream_handle(u.device)), "mci_refiner_forward")
+        return y, ratio, used
+
+    def _loss_call(self, fn, u, hr, *extra):
+        torch = _torch()
+        self._check_img(u)
+        self._check_img(hr)
+        B, _, H, W = u.shape
+        if self._lp is None:
+            self._lp = torch.zeros(4096, dtype=torch.float32, device=u.device)
+        ws, n = self._workspace(B, H, W)
+        nparts = ctypes.c_int()
+        _lib.rcheck(fn(self.handle, u.data_ptr(), hr.data_ptr(), B, H, W, *extra, self._lp.data_ptr(),
+                       ctypes.byref(nparts), ws.data_ptr(), n, _stream_handle(u.device)), fn.__name__)
+        return self._lp[: nparts.value], B * 3 * H * W
+
+    def backward(self, u, hr):
+        """Fills the gradient of mean((u + CNN(u) - hr)^2); returns the loss (device scalar)."""
+        parts, count = self._loss_call(_lib.load_refiner().mci_refiner_backward, u, hr)
+        return parts.sum() / count
+
+    def train_step(self, u, hr, lr: float = 1e-3):
+        parts, count = self._loss_call(_lib.load_refiner().mci_refiner_train_step, u, hr, ctypes.c_float(lr))
+        return parts.sum() / count
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.load_refiner().mci_refiner_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def upsample_rgb(plan: "Plan2D", lr_rgb, out=None):
+    """MCI upsample of RGB images [B, 3, h, w] plane by plane with a Plan2D."""
+    B = lr_rgb.shape[0]
+    planes = lr_rgb.reshape(B * 3, lr_rgb.shape[2], lr_rgb.shape[3])
+    hr = plan.upsample(planes, None if out is None else out.reshape(B * 3, out.shape[2], out.shape[3]))
+    return hr.reshape(B, 3, hr.shape[1], hr.shape[2])

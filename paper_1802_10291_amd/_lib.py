@@ -137,3 +137,42 @@ def mci_plan_2d(desc: mci_plan2d_desc, device: int = 0) -> int:
 def mci_upsample_2d(plan: int, lr_ptr: int, hr_ptr: int, batch: int, ws_ptr: int, ws_bytes: int,
                     stream: int) -> None:
     check(load().mci_upsample_2d(plan, lr_ptr, hr_ptr, batch, ws_ptr, ws_bytes, stream), "mci_upsample_2d")
+
+
+# ----------------------------------------------------------------------------- refiner
+REFINER_EXPORTS = ["mci_refiner_create", "mci_refiner_destroy", "mci_refiner_num_params", "mci_refiner_get_params",
+                   "mci_refiner_set_params", "mci_refiner_get_grads", "mci_refiner_workspace_size",
+                   "mci_refiner_forward", "mci_refiner_backward", "mci_refiner_train_step", "mci_refiner_last_error"]
+EXPORTS += REFINER_EXPORTS
+
+
+def load_refiner():
+    lib = load()
+    if getattr(lib, "_refiner_ready", False):
+        return lib
+    vp, i64, i32, sz, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t, ctypes.c_float
+    P = ctypes.POINTER
+    lib.mci_refiner_create.argtypes = [i32, ctypes.c_uint64, P(vp)]
+    lib.mci_refiner_destroy.argtypes = [vp]
+    lib.mci_refiner_num_params.argtypes = []
+    lib.mci_refiner_num_params.restype = i64
+    lib.mci_refiner_get_params.argtypes = [vp, P(f32), P(f32)]
+    lib.mci_refiner_set_params.argtypes = [vp, P(f32), f32]
+    lib.mci_refiner_get_grads.argtypes = [vp, P(f32)]
+    lib.mci_refiner_workspace_size.argtypes = [i64, i32, i32, P(sz)]
+    lib.mci_refiner_forward.argtypes = [vp, vp, vp, i64, i32, i32, i32, vp, vp, vp, sz, vp]
+    lib.mci_refiner_backward.argtypes = [vp, vp, vp, i64, i32, i32, vp, P(i32), vp, sz, vp]
+    lib.mci_refiner_train_step.argtypes = [vp, vp, vp, i64, i32, i32, f32, vp, P(i32), vp, sz, vp]
+    lib.mci_refiner_last_error.argtypes = []
+    lib.mci_refiner_last_error.restype = ctypes.c_char_p
+    for n in ("mci_refiner_create", "mci_refiner_destroy", "mci_refiner_get_params", "mci_refiner_set_params",
+              "mci_refiner_get_grads", "mci_refiner_workspace_size", "mci_refiner_forward", "mci_refiner_backward",
+              "mci_refiner_train_step"):
+        getattr(lib, n).restype = i32
+    lib._refiner_ready = True
+    return lib
+
+
+def rcheck(status: int, where: str):
+    if status != 0:
+        raise MCIError(status, where, load_refiner().mci_refiner_last_error().decode(errors="replace"))
