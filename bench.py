@@ -40,7 +40,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batched1d", choices=["batched1d", "sisr2", "sisr4"])
+    ap.add_argument("--workload", default="batched1d", choices=["batched1d", "sisr2", "sisr4", "refiner"])
+    ap.add_argument("--pairs", type=int, default=20000, help="refiner: training pairs")
+    ap.add_argument("--epochs", type=int, default=3, help="refiner: training epochs")
     ap.add_argument("--batch", type=int, default=0, help="override the batch size (0 = workload default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=0, help="signals/images in the CPU sample (0 = default)")
@@ -235,6 +237,50 @@ def bench_sisr(args, torch, s):
     return result
 
 
+def bench_refiner(args, torch):
+    """Refiner workload: train on method-generated pairs, then time MCI alone and MCI + CNN on
+    RGB 512 x 512 images upsampled x2 from 256 x 256, and report the PSNR gain."""
+    from paper_1802_10291_amd import Plan2D, Refiner, upsample_rgb
+    from paper_1802_10291_amd import refiner_train as RT
+
+    r = Refiner(seed=0)
+    hist, tau = RT.train(r, n_pairs=args.pairs, batch=16, size=128, lr=1e-3, epochs=args.epochs, log=log)
+    p_mci, p_ref, frac = RT.evaluate(r, n_images=16, size=512)
+    log(f"held-out PSNR: MCI {p_mci:.3f} dB, MCI + CNN {p_ref:.3f} dB, refined {frac:.2f}")
+    B = args.batch or 64
+    hr = RT.make_hr(0, min(B, 16), 512, 7_000_000)
+    hr_dev = torch.from_numpy(hr).cuda().repeat((B + hr.shape[0] - 1) // hr.shape[0], 1, 1, 1)[:B].contiguous()
+    lr_img = hr_dev[:, :, ::2, ::2].contiguous()
+    plan = Plan2D(256, 256, 2)
+    u = torch.empty_like(hr_dev)
+    y = torch.empty_like(hr_dev)
+    stream = torch.cuda.current_stream()
+    w_mci, per_mci = time_steps(torch, lambda: upsample_rgb(plan, lr_img, out=u), args.steps, args.warmup, stream)
+    ms_mci = float(np.mean(per_mci))
+
+    def step():
+        upsample_rgb(plan, lr_img, out=u)
+        r.forward(u, fallback=True, out=y)
+
+    wall, per = time_steps(torch, step, args.steps, args.warmup, stream)
+    ms = float(np.mean(per))
+    flops = 40320.0 * 512 * 512 * B          # four 3x3 convolutions per output pixel
+    achieved = flops / ((ms - ms_mci) * 1e-3) / 1e12
+    return {
+        "metric": METRIC, "value": B * 512 * 512 / (ms * 1e-3), "unit": "px/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"MCI x2 (256^2 -> 512^2, RGB) + residual CNN refiner (4 conv3x3, 32 ch, BF16 MFMA), "
+                               f"trained on {args.pairs} method-generated 128^2 pairs x {args.epochs} epochs",
+                   "batch": B},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": achieved / 2500.0, "traffic": None, "kernel": "refiner forward (4 conv layers)"},
+        "images_per_s": {"mci": B / (ms_mci * 1e-3), "mci_plus_cnn": B / (ms * 1e-3)},
+        "psnr_db": {"mci": p_mci, "mci_plus_cnn": p_ref, "gain": p_ref - p_mci, "images": 16, "refined_fraction": frac},
+        "fallback_tau": tau, "train_loss": hist[-1][1] if hist else None, "wall_s": wall,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -248,6 +294,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batched1d":
         res = bench_batched1d(args, torch)
+    elif args.workload == "refiner":
+        res = bench_refiner(args, torch)
     else:
         res = bench_sisr(args, torch, 2 if args.workload == "sisr2" else 4)
     print(json.dumps(res), flush=True)

@@ -73,6 +73,10 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} not found: build it with __graft_entry__.build() "
                           "(python -m paper_1802_10291_amd.build); there is no fallback")
+    # PyTorch ships its own HIP runtime under the same soname as the system one: loading
+    # torch first makes libmci bind to that runtime, so both share one device context and
+    # torch's stream handles are valid here.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
     P = ctypes.POINTER
