@@ -30,8 +30,9 @@
  *    reconstruction call.
  *  - Reconstruction calls are asynchronous on the given stream; a kernel launch failure
  *    is reported as MCI_E_DEVICE by that call.
- *  - A plan is immutable after creation and may be used from several streams at once,
- *    provided each call has its own workspace.
+ *  - A plan may be used from several streams at once, provided each call has its own
+ *    workspace.  Only mci_plan_set_variant and mci_plan_autotune change a plan; they must
+ *    not run while work queued with the plan is pending.
  */
 #ifndef MCI_H
 #define MCI_H
@@ -116,7 +117,7 @@ typedef struct {
   int64_t fft_len_fwd;      /* transform length executed for the channel DFTs (N, or the Bluestein length) */
   int64_t fft_len_inv;      /* transform length executed for the output grid */
   int32_t path;             /* 0: multi-pass path through the workspace, 1: fused single-pass kernel */
-  int32_t reserved;
+  int32_t variant;          /* active mci_variant */
 } mci_plan_info_t;
 
 /* mci_plan -- build a 1-D reconstruction plan on `device`.
@@ -172,6 +173,86 @@ mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out)
  * workspace of mci_workspace_size(plan, batch) bytes (holds the row-pass result). */
 mci_status mci_upsample_2d(mci_plan_t plan, const void* lr, void* hr, int64_t batch, void* workspace,
                            size_t ws_bytes, hipStream_t stream);
+
+/* ----------------------------------------------------------------------------------- */
+/* Kernel variants and the autotuner (not in the paper: a choice among equivalent          */
+/* schedules of the same arithmetic, steps 1-4 above; every variant meets the same        */
+/* tolerance against the FP64 definition).                                                */
+/* ----------------------------------------------------------------------------------- */
+typedef enum {
+  MCI_VARIANT_MULTIPASS_R8 = 0, /* multi-pass Stockham, radix-8 passes first */
+  MCI_VARIANT_MULTIPASS_R4 = 1, /* multi-pass Stockham, radix-4 passes (more, lighter passes) */
+  MCI_VARIANT_FUSED_T1 = 2,     /* 1-D single-pass kernel, output transforms one at a time */
+  MCI_VARIANT_FUSED_T2 = 3,     /* 1-D single-pass kernel, both output transforms side by side */
+  MCI_VARIANT_LINE_PASS = 4,    /* 2-D fused line passes (columns, then rows) */
+  MCI_NUM_VARIANTS = 5
+} mci_variant;
+
+/* Bit v of *mask is set when variant v can run this plan.  1-D plans: MULTIPASS_R8/R4
+ * always, FUSED_T1/T2 when the single-pass kernel covers the descriptor (and fits the LDS).
+ * 2-D plans: MULTIPASS_R8 (rows then columns through the 1-D plans) always, LINE_PASS for
+ * FP32 plans with h, w in {64, 128, 256} and scale in {2, 4}. */
+mci_status mci_plan_variants(mci_plan_t plan, uint32_t* mask);
+
+/* Make variant v the one the plan runs.  MCI_E_UNSUPPORTED when bit v of the mask is clear.
+ * The workspace size (mci_workspace_size) follows the variant. */
+mci_status mci_plan_set_variant(mci_plan_t plan, int32_t variant);
+
+typedef struct {
+  int32_t variant;          /* chosen (and now active) variant */
+  int32_t from_cache;       /* 1: taken from the cache file without timing */
+  int64_t batch;            /* batch the times were taken at */
+  double ms[MCI_NUM_VARIANTS]; /* mean time per call of each variant tried, -1 if not tried */
+} mci_tune_result;
+
+/* mci_plan_autotune -- time every available variant on `batch` instances of this plan
+ * (zero-filled inputs: the arithmetic, and so the time, does not depend on the values),
+ * activate the fastest and record it in a JSON cache file keyed by the device (arch, CU
+ * count) and the plan's shape.  cache_path NULL => the path in $MCI_TUNE_CACHE, if set;
+ * no path => no cache.  With a cache entry for the key the entry is applied without
+ * timing.  Plans created while $MCI_TUNE_CACHE names a file take their variant from it.
+ * Allocates its own buffers and synchronises the device: call it at set-up, not inside
+ * graph capture.  Errors: MCI_E_INVALID_ARG, MCI_E_OUT_OF_MEMORY, MCI_E_DEVICE (a cache file
+ * that cannot be written is not an error: the result is still applied). */
+mci_status mci_plan_autotune(mci_plan_t plan, int64_t batch, const char* cache_path, mci_tune_result* result);
+
+/* ----------------------------------------------------------------------------------- */
+/* Uneven batches (not in the paper): thousands of instances of different plans -- 1-D    */
+/* lengths, channel counts, 2-D image sizes -- in one call on ragged packed buffers.      */
+/* ----------------------------------------------------------------------------------- */
+typedef struct {
+  mci_plan_t plan;   /* 1-D or 2-D plan reconstructing this instance */
+  int64_t in_off;    /* offset of the instance's input (g, or lr) in the packed input, in elements */
+  int64_t out_off;   /* offset of its output (y, or hr) in the packed output, in elements */
+} mci_batch_item;
+
+typedef struct mci_batch_s* mci_batch_t;
+
+/* mci_batch_create -- group the items by plan (one size class per distinct plan), upload
+ * one device table of (in_off, out_off) per class, and spread the classes over `lanes`
+ * streams (1..8; 0 => 4) by estimated bytes, largest first.  All plans must live on one
+ * device, share one element type (FP32, FP16 or FP64 storage) and outlive the batch.
+ * Offsets are >= 0 and multiples of 4 elements (vector access); output extents must not
+ * overlap.  Each instance's layout inside its extent is the single-instance layout of
+ * mci_reconstruct_1d / mci_upsample_2d.  Allocates (the tables, the lane streams and
+ * events): build batches at set-up.  Errors: MCI_E_INVALID_ARG, MCI_E_OUT_OF_MEMORY,
+ * MCI_E_DEVICE. */
+mci_status mci_batch_create(const mci_batch_item* items, int64_t n_items, int lanes, mci_batch_t* out);
+mci_status mci_batch_destroy(mci_batch_t batch);
+
+/* Element counts the packed input and output must hold (max over items of offset + size)
+ * and the workspace bytes mci_reconstruct_batch needs with the plans' current variants. */
+mci_status mci_batch_sizes(mci_batch_t batch, int64_t* in_elems, int64_t* out_elems, size_t* ws_bytes);
+
+/* mci_reconstruct_batch -- reconstruct every instance: each class runs its plan's kernels
+ * over its offset table; classes on different lanes run concurrently (the lanes fork from
+ * and join back into `stream` through events), so one call queues all of it and a stream
+ * capture of the call records it as one graph.  No allocation, no synchronisation, no
+ * memset: the call is graph-capturable.  in and out are device pointers to the packed
+ * buffers; workspace holds mci_batch_sizes' ws_bytes.  Calls sharing one batch must not
+ * overlap in time (the lanes are the batch's). */
+mci_status mci_reconstruct_batch(mci_batch_t batch, const void* in, void* out, void* workspace, size_t ws_bytes,
+                                 hipStream_t stream);
 
 /* ----------------------------------------------------------------------------------- */
 /* Learned residual refiner (not part of the paper; its closing remarks on Section 5.2   */

@@ -9,7 +9,9 @@ elimination per residue, direct trigonometric sum on the output grid) plus two p
 NumPy helpers that state closed formulas of the paper:
 
 * :func:`averaged_error` -- the exact phase-averaged squared error of Theorem 4.4
-  (eq. averageerror), and
+  (eq. averageerror),
+* :func:`evaluate_band` -- the reconstruction's trigonometric sum (eq. DFTexpression) at
+  arbitrary points, for sampled checks of outputs too long to evaluate in full, and
 * :func:`psnr` -- peak signal-to-noise ratio of an image in [0, 1].
 
 Multiplier kinds and output operators use the integer codes below; channel tables
@@ -274,6 +276,28 @@ def averaged_error(ch: Channels, coeff_n: np.ndarray, coeff_a: np.ndarray) -> fl
         eps2 += float((a2[outside] * np.abs(s[outside]) ** 2).sum())
     del k
     return float(np.sqrt(eps2))
+
+
+def evaluate_band(a: np.ndarray, n1: int, t: np.ndarray, op: int = OUT_IDENTITY, order: int = 0,
+                  real: bool = True) -> np.ndarray:
+    """sum_n o(n) a(n) e^{i n t} over the band n = n1 .. n1 + len(a) - 1 at real points t
+    (eq. DFTexpression with the output operator of the closing paragraph of Section 3);
+    the real part in real mode.  Direct sum, 64 points at a time."""
+    a = np.asarray(a, dtype=np.complex128).ravel()
+    n = np.arange(n1, n1 + a.size, dtype=np.float64)
+    if op == OUT_IDENTITY:
+        o = np.ones_like(n, dtype=np.complex128)
+    elif op == OUT_HILBERT:
+        o = -1j * np.sign(n)
+    else:
+        o = (1j * n) ** int(order)
+    c = a * o
+    t = np.asarray(t, dtype=np.float64).ravel()
+    out = np.empty(t.size, dtype=np.complex128)
+    for s0 in range(0, t.size, 64):
+        tt = t[s0:s0 + 64]
+        out[s0:s0 + 64] = np.exp(1j * np.outer(tt, n)) @ c
+    return out.real if real else out
 
 
 def psnr(img: np.ndarray, ref: np.ndarray, clip: bool = True) -> float:

@@ -20,7 +20,8 @@ import numpy as np
 from . import _lib
 from ._lib import (  # noqa: F401  (the C-ABI names, re-exported)
     MCIError, mci_plan, mci_plan_destroy, mci_plan_info, mci_workspace_size, mci_reconstruct_1d, mci_plan_2d,
-    mci_upsample_2d,
+    mci_upsample_2d, mci_plan_variants, mci_plan_set_variant, mci_plan_autotune, mci_batch_create,
+    mci_batch_destroy, mci_batch_sizes, mci_reconstruct_batch, VARIANT_NAMES,
 )
 
 _KINDS = {"deriv": _lib.MCI_MULT_DERIV, "hilbert": _lib.MCI_MULT_HILBERT, "table": _lib.MCI_MULT_TABLE}
@@ -39,7 +40,33 @@ def _stream_handle(device) -> int:
     return int(torch.cuda.current_stream(device).cuda_stream)
 
 
-class Plan1D:
+class _Variants:
+    """Kernel variants and the autotuner (``mci_plan_variants`` / ``mci_plan_set_variant`` /
+    ``mci_plan_autotune``), shared by 1-D and 2-D plans."""
+
+    def variants(self):
+        m = mci_plan_variants(self.handle)
+        return [VARIANT_NAMES[v] for v in range(len(VARIANT_NAMES)) if m >> v & 1]
+
+    @property
+    def variant(self) -> str:
+        return VARIANT_NAMES[mci_plan_info(self.handle).variant]
+
+    def set_variant(self, name: str) -> None:
+        mci_plan_set_variant(self.handle, VARIANT_NAMES.index(name))
+
+    def autotune(self, batch: int, cache_path: Optional[str] = None):
+        """Time every variant at this batch, keep the fastest; returns (name, {name: ms}, from_cache)."""
+        r = mci_plan_autotune(self.handle, batch, cache_path)
+        ms = {VARIANT_NAMES[v]: r.ms[v] for v in range(len(VARIANT_NAMES)) if r.ms[v] >= 0}
+        return VARIANT_NAMES[r.variant], ms, bool(r.from_cache)
+
+    def instance_sizes(self) -> Tuple[int, int]:
+        """Elements of one instance's input and output."""
+        raise NotImplementedError
+
+
+class Plan1D(_Variants):
     """A 1-D reconstruction plan (``mci_plan``).
 
     channels: list of ("deriv", order) | ("hilbert", 0) | ("table", complex array of
@@ -82,6 +109,10 @@ class Plan1D:
     @property
     def info(self):
         return mci_plan_info(self.handle)
+
+    def instance_sizes(self) -> Tuple[int, int]:
+        c = 1 if self.real else 2
+        return self.M * self.N * c, self.n_ops * self.n_out * c
 
     def io_dtype(self):
         torch = _torch()
@@ -128,7 +159,7 @@ class Plan1D:
             pass
 
 
-class Plan2D:
+class Plan2D(_Variants):
     """A 2-D separable upsampling plan (``mci_plan_2d``): lr [batch, h, w] -> hr [batch, s h, s w]."""
 
     def __init__(self, h: int, w: int, scale: int, precision: str = "f32", storage: str = "native", device: int = 0):
@@ -145,6 +176,9 @@ class Plan2D:
     @property
     def info(self):
         return mci_plan_info(self.handle)
+
+    def instance_sizes(self) -> Tuple[int, int]:
+        return self.h * self.w, self.scale * self.scale * self.h * self.w
 
     def io_dtype(self):
         torch = _torch()
@@ -168,6 +202,8 @@ class Plan2D:
         shape = (batch, self.scale * self.h, self.scale * self.w)
         if out is None:
             out = torch.empty(shape, dtype=self.io_dtype(), device=lr.device)
+        elif tuple(out.shape) != shape or out.dtype != self.io_dtype() or not out.is_contiguous():
+            raise ValueError("bad out tensor")
         ws, need = self.workspace(batch)
         mci_upsample_2d(self.handle, lr.data_ptr(), out.data_ptr(), batch, ws.data_ptr() if ws is not None else 0,
                         need, _stream_handle(lr.device))
@@ -176,6 +212,70 @@ class Plan2D:
     def close(self):
         if getattr(self, "handle", None):
             mci_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Uneven batch (``mci_batch_*``): instances of several plans (1-D lengths, channel counts,
+    2-D sizes) over ragged packed buffers, reconstructed by one call.
+
+    instances: sequence of plans, one per instance (a plan may repeat).  Instance k's input
+    and output sit at ``in_offsets[k]`` / ``out_offsets[k]`` of the flat packed buffers, each
+    rounded up to ``align`` elements, in the order given (or pass explicit offsets).
+    """
+
+    def __init__(self, instances: Sequence, lanes: int = 4, align: int = 64, offsets=None):
+        self.plans = list(instances)
+        if offsets is None:
+            ins, outs, i, o = [], [], 0, 0
+            for p in self.plans:
+                ni, no = p.instance_sizes()
+                ins.append(i)
+                outs.append(o)
+                i += -(-ni // align) * align
+                o += -(-no // align) * align
+            offsets = (ins, outs)
+        self.in_offsets, self.out_offsets = list(offsets[0]), list(offsets[1])
+        self.handle = mci_batch_create([(p.handle, i, o) for p, i, o in
+                                        zip(self.plans, self.in_offsets, self.out_offsets)], lanes)
+        self.in_elems, self.out_elems, self.ws_bytes = mci_batch_sizes(self.handle)
+        self.device = self.plans[0].device if self.plans else 0
+        self._ws = None
+
+    def dtype(self):
+        return self.plans[0].io_dtype()
+
+    def workspace(self):
+        torch = _torch()
+        _, _, need = mci_batch_sizes(self.handle)
+        if need and (self._ws is None or self._ws.numel() < need):
+            self._ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws if need else None, need
+
+    def run(self, packed_in, packed_out=None):
+        """packed_in: flat device tensor of >= in_elems elements; returns the packed output."""
+        torch = _torch()
+        if not packed_in.is_cuda or packed_in.dtype != self.dtype() or packed_in.numel() < self.in_elems \
+                or not packed_in.is_contiguous():
+            raise ValueError(f"packed input must be a contiguous device {self.dtype()} tensor of >= {self.in_elems}")
+        if packed_out is None:
+            packed_out = torch.empty(self.out_elems, dtype=self.dtype(), device=packed_in.device)
+        elif packed_out.numel() < self.out_elems or packed_out.dtype != self.dtype() or not packed_out.is_contiguous():
+            raise ValueError("bad packed output")
+        ws, need = self.workspace()
+        mci_reconstruct_batch(self.handle, packed_in.data_ptr(), packed_out.data_ptr(),
+                              ws.data_ptr() if ws is not None else 0, need, _stream_handle(packed_in.device))
+        return packed_out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mci_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

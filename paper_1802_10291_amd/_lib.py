@@ -44,7 +44,7 @@ class mci_plan_desc(ctypes.Structure):
 class mci_plan_info_t(ctypes.Structure):
     _fields_ = [("max_cond", ctypes.c_double), ("n_singular", ctypes.c_int64), ("first_singular", ctypes.c_int64),
                 ("n1", ctypes.c_int64), ("fft_len_fwd", ctypes.c_int64), ("fft_len_inv", ctypes.c_int64),
-                ("path", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("path", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
 class mci_plan2d_desc(ctypes.Structure):
@@ -52,9 +52,26 @@ class mci_plan2d_desc(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+MCI_VARIANT_MULTIPASS_R8, MCI_VARIANT_MULTIPASS_R4, MCI_VARIANT_FUSED_T1, MCI_VARIANT_FUSED_T2, \
+    MCI_VARIANT_LINE_PASS = range(5)
+MCI_NUM_VARIANTS = 5
+VARIANT_NAMES = ["multipass_r8", "multipass_r4", "fused_t1", "fused_t2", "line_pass"]
+
+
+class mci_tune_result(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("batch", ctypes.c_int64),
+                ("ms", ctypes.c_double * MCI_NUM_VARIANTS)]
+
+
+class mci_batch_item(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("in_off", ctypes.c_int64), ("out_off", ctypes.c_int64)]
+
+
 # every symbol the header declares
 EXPORTS = ["mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_workspace_size", "mci_reconstruct_1d",
-           "mci_plan_2d", "mci_upsample_2d", "mci_status_string", "mci_last_error"]
+           "mci_plan_2d", "mci_upsample_2d", "mci_status_string", "mci_last_error", "mci_plan_variants",
+           "mci_plan_set_variant", "mci_plan_autotune", "mci_batch_create", "mci_batch_destroy", "mci_batch_sizes",
+           "mci_reconstruct_batch"]
 
 _lib = None
 
@@ -91,8 +108,16 @@ def load(path: str = LIB_PATH):
     lib.mci_status_string.restype = ctypes.c_char_p
     lib.mci_last_error.argtypes = []
     lib.mci_last_error.restype = ctypes.c_char_p
+    lib.mci_plan_variants.argtypes = [vp, P(ctypes.c_uint32)]
+    lib.mci_plan_set_variant.argtypes = [vp, i32]
+    lib.mci_plan_autotune.argtypes = [vp, i64, ctypes.c_char_p, P(mci_tune_result)]
+    lib.mci_batch_create.argtypes = [P(mci_batch_item), i64, i32, P(vp)]
+    lib.mci_batch_destroy.argtypes = [vp]
+    lib.mci_batch_sizes.argtypes = [vp, P(i64), P(i64), P(sz)]
+    lib.mci_reconstruct_batch.argtypes = [vp, vp, vp, vp, sz, vp]
     for name in ("mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_workspace_size", "mci_reconstruct_1d",
-                 "mci_plan_2d", "mci_upsample_2d"):
+                 "mci_plan_2d", "mci_upsample_2d", "mci_plan_variants", "mci_plan_set_variant", "mci_plan_autotune",
+                 "mci_batch_create", "mci_batch_destroy", "mci_batch_sizes", "mci_reconstruct_batch"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -141,6 +166,47 @@ def mci_plan_2d(desc: mci_plan2d_desc, device: int = 0) -> int:
 def mci_upsample_2d(plan: int, lr_ptr: int, hr_ptr: int, batch: int, ws_ptr: int, ws_bytes: int,
                     stream: int) -> None:
     check(load().mci_upsample_2d(plan, lr_ptr, hr_ptr, batch, ws_ptr, ws_bytes, stream), "mci_upsample_2d")
+
+
+def mci_plan_variants(plan: int) -> int:
+    m = ctypes.c_uint32()
+    check(load().mci_plan_variants(plan, ctypes.byref(m)), "mci_plan_variants")
+    return m.value
+
+
+def mci_plan_set_variant(plan: int, variant: int) -> None:
+    check(load().mci_plan_set_variant(plan, variant), "mci_plan_set_variant")
+
+
+def mci_plan_autotune(plan: int, batch: int, cache_path: str | None = None) -> mci_tune_result:
+    r = mci_tune_result()
+    path = cache_path.encode() if cache_path else None
+    check(load().mci_plan_autotune(plan, batch, path, ctypes.byref(r)), "mci_plan_autotune")
+    return r
+
+
+def mci_batch_create(items, lanes: int = 0) -> int:
+    """items: sequence of (plan handle, in_off, out_off)."""
+    arr = (mci_batch_item * max(1, len(items)))()
+    for k, (p, i, o) in enumerate(items):
+        arr[k].plan, arr[k].in_off, arr[k].out_off = p, i, o
+    h = ctypes.c_void_p()
+    check(load().mci_batch_create(arr, len(items), lanes, ctypes.byref(h)), "mci_batch_create")
+    return h.value
+
+
+def mci_batch_destroy(batch: int) -> None:
+    check(load().mci_batch_destroy(batch), "mci_batch_destroy")
+
+
+def mci_batch_sizes(batch: int):
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+    check(load().mci_batch_sizes(batch, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "mci_batch_sizes")
+    return a.value, b.value, c.value
+
+
+def mci_reconstruct_batch(batch: int, in_ptr: int, out_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    check(load().mci_reconstruct_batch(batch, in_ptr, out_ptr, ws_ptr, ws_bytes, stream), "mci_reconstruct_batch")
 
 
 # ----------------------------------------------------------------------------- refiner

@@ -16,6 +16,10 @@ struct LinePassArgs {
   int64_t W;           // columns mode: columns per image (lines per image)
   const float2* H;     // [SC][N] polyphase windows
   const float2* tw;    // N entries e^{-2 pi i k / N}
+  // Optional per-image placement (device, 2 per image): columns mode reads image b at
+  // x + offs[2 b]; rows mode writes line l to image l / lines_per_img at y + offs[2 b + 1].
+  const int64_t* offs = nullptr;
+  int64_t lines_per_img = 1;
 };
 
 bool line_pass_supported(int N, int SC);

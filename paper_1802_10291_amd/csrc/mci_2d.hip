@@ -160,13 +160,14 @@ __global__ __launch_bounds__(N) void k_line_pass(LinePassArgs a) {
     line0 = (int64_t)blockIdx.x * LINES;
   }
   // ---- load 32 lines into the tile (line-major)
+  const int64_t xoff = COLS ? (a.offs ? a.offs[2 * img] : img * N * (int64_t)a.W) : 0;
   if constexpr (COLS) {
     // row n of image img, columns col0 .. col0 + 31: 32 contiguous values per row
     for (int e = tid; e < N * LINES; e += NT) {
       const int n = e / LINES, c = e % LINES;
       const int64_t col = col0 + c;
       float v = 0.f;
-      if (col < a.W) v = ld_as<float>(x, (img * N + n) * (int64_t)a.W + col);
+      if (col < a.W) v = ld_as<float>(x, xoff + n * (int64_t)a.W + col);
       tile[c * TS + n] = v;
     }
   } else {
@@ -203,7 +204,8 @@ __global__ __launch_bounds__(N) void k_line_pass(LinePassArgs a) {
     for (int h2 = 0; h2 < 2; ++h2) {
       const int64_t line = line0 + 2 * g + h2;
       if (line >= a.lines) continue;
-      TO* yl = y + line * (int64_t)(SC * N);
+      TO* yl = y + (a.offs ? a.offs[2 * (line / a.lines_per_img) + 1] + (line % a.lines_per_img) * (int64_t)(SC * N)
+                           : line * (int64_t)(SC * N));
 #pragma unroll
       for (int c = 0; c < E; ++c) {
         const int q = l + G * c;

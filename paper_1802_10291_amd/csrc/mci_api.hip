@@ -16,15 +16,18 @@
 #include "mci_fused.h"
 #include "mci_host_util.h"
 #include "mci_internal.h"
+#include "mci_plan.h"
 
 using namespace mci;
 
 static thread_local std::string g_last_error;
 
-static mci_status fail(mci_status s, const std::string& msg) {
+namespace mci {
+mci_status fail(mci_status s, const std::string& msg) {
   g_last_error = msg;
   return s;
 }
+}  // namespace mci
 
 #define HIP_TRY(expr)                                                                    \
   do {                                                                                   \
@@ -32,35 +35,13 @@ static mci_status fail(mci_status s, const std::string& msg) {
     if (_e != hipSuccess) return fail(MCI_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
   } while (0)
 
-struct mci_plan_s {
-  int dims = 1;  // 1: 1-D plan, 2: 2-D plan
-  int device = 0;
-  mci_plan_desc d{};
-  int64_t mu = 0;
-  int prec = MCI_F32;
-  int store = ST_F32;
-  void* tab = nullptr;      // [n_ops][M][M][N] complex in plan precision
-  FftSide fwd, inv;
-  double max_cond = 0.0;
-  int64_t n_sing = 0, first_sing = INT64_MIN;
-  FusedPlan fused;          // single-pass kernel choice (fused.kind == 0: none)
-  std::vector<std::complex<double>> tab_host;   // FP64 apply table [n_ops][M][M][N]
-  // 2-D fused line passes: windows H[SC][len] and twiddles per axis (cols, rows)
-  bool lp = false;
-  void* lp_H[2] = {nullptr, nullptr};
-  void* lp_tw[2] = {nullptr, nullptr};
-  // 2-D
-  mci_plan2d_desc d2{};
-  mci_plan_s* rows = nullptr;
-  mci_plan_s* cols = nullptr;
-};
-
 // ----------------------------------------------------------------- FFT planning (host)
-static bool factor_7smooth(int64_t n, std::vector<int>& radices) {
+static bool factor_7smooth(int64_t n, std::vector<int>& radices, int max_radix = 8) {
   radices.clear();
   if (n < 1) return false;
   int64_t m = n;
-  while (m % 8 == 0) { radices.push_back(8); m /= 8; }
+  while (max_radix >= 8 && m % 8 == 0) { radices.push_back(8); m /= 8; }
+  while (max_radix < 8 && m % 4 == 0) { radices.push_back(4); m /= 4; }
   if (m % 4 == 0) { radices.push_back(4); m /= 4; }
   if (m % 2 == 0) { radices.push_back(2); m /= 2; }
   for (int p : {3, 5, 7})
@@ -103,7 +84,9 @@ static mci_status build_side(FftSide& f, int64_t len, int sign, int prec) {
   f.sign = sign;
   f.blue = !factor_7smooth(len, f.radices);
   f.lexec = f.blue ? next_7smooth(2 * len - 1) : len;
-  if (f.blue) factor_7smooth(f.lexec, f.radices);
+  factor_7smooth(f.lexec, f.radices8, 8);
+  factor_7smooth(f.lexec, f.radices4, 4);
+  f.radices = f.radices8;
   std::vector<std::complex<double>> tw(f.lexec);
   for (int64_t k = 0; k < f.lexec; ++k) tw[k] = root_of_unity(k, f.lexec);
   hipError_t e;
@@ -288,8 +271,17 @@ static mci_status build_plan(const mci_plan_desc* desc, int device, mci_plan_s**
   if ((st = build_side(p->inv, desc->n_out, +1, p->prec)) != MCI_OK) { destroy_plan(p); return st; }
   if ((st = fused_select(p->d, p->prec, p->store, p->tab, p->fused)) != MCI_OK) { destroy_plan(p); return st; }
   HIP_TRY(hipDeviceSynchronize());
+  (void)plan_set_variant(p, p->fused.kind ? MCI_VARIANT_FUSED_T1 : MCI_VARIANT_MULTIPASS_R8);
   *out = p;
   return MCI_OK;
+}
+
+// variant recorded for this plan's shape in $MCI_TUNE_CACHE, applied when available
+static void apply_tune_cache(mci_plan_s* p) {
+  const char* path = std::getenv("MCI_TUNE_CACHE");
+  if (!path || !*path) return;
+  const int v = tune_cache_lookup(path, plan_tune_key(p));
+  if (v >= 0 && (plan_variant_mask(p) >> v & 1u)) (void)plan_set_variant(p, v);
 }
 
 static Generic1D generic_of(const mci_plan_s* p) {
@@ -302,7 +294,7 @@ static Generic1D generic_of(const mci_plan_s* p) {
 
 static size_t ws_1d(const mci_plan_s* p, int64_t batch) {
   if (batch <= 0) return 0;
-  if (p->fused.kind) return 0;
+  if (p->use_fused) return 0;
   return generic_1d_workspace(generic_of(p), p->prec, batch);
 }
 
@@ -321,6 +313,111 @@ static size_t ws_2d(const mci_plan_s* p, int64_t batch) {
   size_t w1 = std::max(ws_1d(p->rows, batch * h), ws_1d(p->cols, batch * s * w));
   return rows_in + mid + cols_in + cols_out + al(w1) + 256;
 }
+
+// ================================================================= internal entry points
+namespace mci {
+
+int store_bytes(int store) { return store == ST_F64 ? 8 : (store == ST_F16 ? 2 : 4); }
+
+int64_t instance_in_elems(const mci_plan_s* p) {
+  if (p->dims == 2) return (int64_t)p->d2.h * p->d2.w;
+  return p->mu * (p->d.real_io ? 1 : 2);
+}
+
+int64_t instance_out_elems(const mci_plan_s* p) {
+  if (p->dims == 2) return (int64_t)p->d2.scale * p->d2.h * p->d2.scale * p->d2.w;
+  return (int64_t)p->d.n_ops * p->d.n_out * (p->d.real_io ? 1 : 2);
+}
+
+size_t plan_workspace(const mci_plan_s* p, int64_t batch) { return p->dims == 2 ? ws_2d(p, batch) : ws_1d(p, batch); }
+
+static mci_status run_2d(const mci_plan_s* p, const void* lr, void* hr, int64_t batch, void* workspace,
+                         const int64_t* offs, hipStream_t stream) {
+  if (p->lp) {
+    // columns first: lr [B][h][w] -> mid [B][s h][w]; then rows: mid -> hr [B][s h][s w]
+    const int64_t h = p->d2.h, w = p->d2.w, sc = p->d2.scale;
+    float* mid = (float*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    const int64_t max_y = 65535;   // images per column-pass launch (grid y)
+    for (int64_t b0 = 0; b0 < batch; b0 += max_y) {
+      const int64_t nb = std::min(max_y, batch - b0);
+      const char* x0 = offs ? (const char*)lr : (const char*)lr + b0 * h * w * store_bytes(p->store);
+      LinePassArgs ac{x0, mid + b0 * sc * h * w, 0, w, (const float2*)p->lp_H[0], (const float2*)p->lp_tw[0],
+                      offs ? offs + 2 * b0 : nullptr, 1};
+      hipError_t err = run_line_pass((int)h, (int)sc, true, p->store, ST_F32, ac, nb, stream);
+      if (err != hipSuccess) return fail(MCI_E_DEVICE, std::string("column pass: ") + hipGetErrorString(err));
+    }
+    LinePassArgs ar{mid, hr, batch * sc * h, 0, (const float2*)p->lp_H[1], (const float2*)p->lp_tw[1], offs, sc * h};
+    hipError_t err = run_line_pass((int)w, (int)sc, false, ST_F32, p->store, ar, 0, stream);
+    if (err != hipSuccess) return fail(MCI_E_DEVICE, std::string("row pass: ") + hipGetErrorString(err));
+    return MCI_OK;
+  }
+  const int64_t h = p->d2.h, w = p->d2.w, s = p->d2.scale, H = s * h, W = s * w;
+  const size_t e = p->prec == MCI_F64 ? 8 : 4;
+  auto al = [](size_t n) { return (n + 255) & ~(size_t)255; };
+  char* base = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+  char* rows_in = base;
+  char* mid = rows_in + al((size_t)batch * h * 2 * w * e);
+  char* cols_in = mid + al((size_t)batch * h * W * e);
+  char* cols_out = cols_in + al((size_t)batch * W * 2 * h * e);
+  char* w1 = cols_out + al((size_t)batch * W * H * e);
+  hipError_t err;
+  if ((err = launch_fd_channels(p->prec, p->store, lr, rows_in, batch, h, w, 0, offs, stream)) != hipSuccess)
+    return fail(MCI_E_DEVICE, hipGetErrorString(err));
+  mci_status st = plan_run(p->rows, rows_in, mid, batch * h, w1, nullptr, stream);
+  if (st != MCI_OK) return st;
+  if ((err = launch_fd_channels(p->prec, p->prec == MCI_F64 ? ST_F64 : ST_F32, mid, cols_in, batch, h, W, 1, nullptr,
+                                stream)) != hipSuccess)
+    return fail(MCI_E_DEVICE, hipGetErrorString(err));
+  if ((st = plan_run(p->cols, cols_in, cols_out, batch * W, w1, nullptr, stream)) != MCI_OK) return st;
+  if ((err = launch_transpose_out(p->prec, p->store, cols_out, hr, batch, W, H, offs, stream)) != hipSuccess)
+    return fail(MCI_E_DEVICE, hipGetErrorString(err));
+  return MCI_OK;
+}
+
+mci_status plan_run(const mci_plan_s* p, const void* in, void* out, int64_t batch, void* ws, const int64_t* offs,
+                    hipStream_t s) {
+  if (batch <= 0) return MCI_OK;
+  if (p->dims == 2) return run_2d(p, in, out, batch, ws, offs, s);
+  hipError_t e;
+  if (p->use_fused) e = fused_run(p->fused, in, out, batch, offs, s);
+  else e = run_generic_1d(generic_of(p), p->prec, p->store, in, out, batch, ws, offs, s);
+  if (e != hipSuccess) return fail(MCI_E_DEVICE, std::string("reconstruct: ") + hipGetErrorString(e));
+  return MCI_OK;
+}
+
+uint32_t plan_variant_mask(const mci_plan_s* p) {
+  uint32_t m = 1u << MCI_VARIANT_MULTIPASS_R8;
+  if (p->dims == 2) {
+    if (p->lp_avail) m |= 1u << MCI_VARIANT_LINE_PASS;
+    return m;
+  }
+  m |= 1u << MCI_VARIANT_MULTIPASS_R4;
+  if (p->fused.kind) {
+    m |= 1u << MCI_VARIANT_FUSED_T1;
+    if (p->fused.n_ti == 2) m |= 1u << MCI_VARIANT_FUSED_T2;
+  }
+  return m;
+}
+
+mci_status plan_set_variant(mci_plan_s* p, int v) {
+  if (v < 0 || v >= MCI_NUM_VARIANTS || !(plan_variant_mask(p) >> v & 1u))
+    return fail(MCI_E_UNSUPPORTED, "variant " + std::to_string(v) + " is not available for this plan");
+  if (p->dims == 2) {
+    p->lp = v == MCI_VARIANT_LINE_PASS;
+  } else if (v == MCI_VARIANT_FUSED_T1 || v == MCI_VARIANT_FUSED_T2) {
+    p->use_fused = true;
+    fused_set_ti(p->fused, v == MCI_VARIANT_FUSED_T2 ? 2 : 1);
+  } else {
+    p->use_fused = false;
+    const bool r4 = v == MCI_VARIANT_MULTIPASS_R4;
+    p->fwd.radices = r4 ? p->fwd.radices4 : p->fwd.radices8;
+    p->inv.radices = r4 ? p->inv.radices4 : p->inv.radices8;
+  }
+  p->variant = v;
+  return MCI_OK;
+}
+
+}  // namespace mci
 
 // ================================================================= C ABI
 extern "C" {
@@ -345,8 +442,10 @@ mci_status mci_plan(const mci_plan_desc* desc, int device, mci_plan_t* out) {
   *out = nullptr;
   mci_plan_s* p = nullptr;
   mci_status st = build_plan(desc, device, &p);
-  if (st == MCI_OK) *out = p;
-  return st;
+  if (st != MCI_OK) return st;
+  apply_tune_cache(p);
+  *out = p;
+  return MCI_OK;
 }
 
 mci_status mci_plan_destroy(mci_plan_t plan) {
@@ -365,8 +464,8 @@ mci_status mci_plan_info(mci_plan_t p, mci_plan_info_t* info) {
   info->n1 = q->d.n1;
   info->fft_len_fwd = q->fwd.lexec;
   info->fft_len_inv = q->inv.lexec;
-  info->path = p->dims == 2 ? (p->lp ? 1 : 0) : (p->fused.kind ? 1 : 0);
-  info->reserved = 0;
+  info->path = p->dims == 2 ? (p->lp ? 1 : 0) : (p->use_fused ? 1 : 0);
+  info->variant = p->variant;
   return MCI_OK;
 }
 
@@ -388,11 +487,7 @@ mci_status mci_reconstruct_1d(mci_plan_t p, const void* g, void* y, int64_t batc
   if (need && (!workspace || ws_bytes < need))
     return fail(MCI_E_INVALID_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
   HIP_TRY(hipSetDevice(p->device));
-  hipError_t e;
-  if (p->fused.kind) e = fused_run(p->fused, g, y, batch, stream);
-  else e = run_generic_1d(generic_of(p), p->prec, p->store, g, y, batch, workspace, stream);
-  if (e != hipSuccess) return fail(MCI_E_DEVICE, std::string("reconstruct: ") + hipGetErrorString(e));
-  return MCI_OK;
+  return plan_run(p, g, y, batch, workspace, nullptr, stream);
 }
 
 mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out) {
@@ -441,8 +536,10 @@ mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out)
       p->lp_tw[axis] = upload<float2>(tw, e);
       if (!p->lp_tw[axis] || e != hipSuccess) { destroy_plan(p); return fail(MCI_E_DEVICE, "twiddle upload"); }
     }
-    p->lp = true;
+    p->lp_avail = true;
   }
+  (void)plan_set_variant(p, p->lp_avail ? MCI_VARIANT_LINE_PASS : MCI_VARIANT_MULTIPASS_R8);
+  apply_tune_cache(p);
   *out = p;
   return MCI_OK;
 }
@@ -453,48 +550,23 @@ mci_status mci_upsample_2d(mci_plan_t p, const void* lr, void* hr, int64_t batch
   if (batch < 0) return fail(MCI_E_INVALID_ARG, "batch < 0");
   if (batch == 0) return MCI_OK;
   if (!lr || !hr) return fail(MCI_E_INVALID_ARG, "NULL data pointer");
+  if (batch > ((int64_t)1 << 40) / instance_out_elems(p)) return fail(MCI_E_INVALID_ARG, "batch too large");
   const size_t need = ws_2d(p, batch);
   if (!workspace || ws_bytes < need) return fail(MCI_E_INVALID_ARG, "workspace too small: need " + std::to_string(need));
   HIP_TRY(hipSetDevice(p->device));
-  if (p->lp) {
-    // columns first: lr [B][h][w] -> mid [B][s h][w]; then rows: mid -> hr [B][s h][s w]
-    const int64_t h = p->d2.h, w = p->d2.w, sc = p->d2.scale;
-    float* mid = (float*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
-    LinePassArgs ac{lr, mid, 0, w, (const float2*)p->lp_H[0], (const float2*)p->lp_tw[0]};
-    hipError_t err = run_line_pass((int)h, (int)sc, true, p->store, ST_F32, ac, batch, stream);
-    if (err != hipSuccess) return fail(MCI_E_DEVICE, std::string("column pass: ") + hipGetErrorString(err));
-    LinePassArgs ar{mid, hr, batch * sc * h, 0, (const float2*)p->lp_H[1], (const float2*)p->lp_tw[1]};
-    err = run_line_pass((int)w, (int)sc, false, ST_F32, p->store, ar, 0, stream);
-    if (err != hipSuccess) return fail(MCI_E_DEVICE, std::string("row pass: ") + hipGetErrorString(err));
-    return MCI_OK;
-  }
-  const int64_t h = p->d2.h, w = p->d2.w, s = p->d2.scale, H = s * h, W = s * w;
-  const size_t e = p->prec == MCI_F64 ? 8 : 4;
-  auto al = [](size_t n) { return (n + 255) & ~(size_t)255; };
-  char* base = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
-  char* rows_in = base;
-  char* mid = rows_in + al((size_t)batch * h * 2 * w * e);
-  char* cols_in = mid + al((size_t)batch * h * W * e);
-  char* cols_out = cols_in + al((size_t)batch * W * 2 * h * e);
-  char* w1 = cols_out + al((size_t)batch * W * H * e);
-  const size_t w1_bytes = ws_bytes - (size_t)(w1 - (char*)workspace);
-  const int st_native = p->prec == MCI_F64 ? ST_F64 : ST_F32;
-  hipError_t err;
-  if ((err = launch_fd_channels(p->prec, p->store, lr, rows_in, batch, h, w, 0, stream)) != hipSuccess)
-    return fail(MCI_E_DEVICE, hipGetErrorString(err));
-  mci_status st = MCI_OK;
-  if (p->rows->fused.kind) err = fused_run(p->rows->fused, rows_in, mid, batch * h, stream);
-  else err = run_generic_1d(generic_of(p->rows), p->prec, st_native, rows_in, mid, batch * h, w1, stream);
-  if (err != hipSuccess) return fail(MCI_E_DEVICE, hipGetErrorString(err));
-  if ((err = launch_fd_channels(p->prec, st_native, mid, cols_in, batch, h, W, 1, stream)) != hipSuccess)
-    return fail(MCI_E_DEVICE, hipGetErrorString(err));
-  if (p->cols->fused.kind) err = fused_run(p->cols->fused, cols_in, cols_out, batch * W, stream);
-  else err = run_generic_1d(generic_of(p->cols), p->prec, st_native, cols_in, cols_out, batch * W, w1, stream);
-  if (err != hipSuccess) return fail(MCI_E_DEVICE, hipGetErrorString(err));
-  if ((err = launch_transpose_out(p->prec, p->store, cols_out, hr, batch, W, H, stream)) != hipSuccess)
-    return fail(MCI_E_DEVICE, hipGetErrorString(err));
-  (void)w1_bytes;
-  return st;
+  return plan_run(p, lr, hr, batch, workspace, nullptr, stream);
+}
+
+mci_status mci_plan_variants(mci_plan_t p, uint32_t* mask) {
+  if (!p || !mask) return fail(MCI_E_INVALID_ARG, "NULL argument");
+  *mask = plan_variant_mask(p);
+  return MCI_OK;
+}
+
+mci_status mci_plan_set_variant(mci_plan_t p, int32_t v) {
+  if (!p) return fail(MCI_E_INVALID_ARG, "NULL plan");
+  if (v < 0 || v >= MCI_NUM_VARIANTS) return fail(MCI_E_INVALID_ARG, "unknown variant");
+  return plan_set_variant(p, v);
 }
 
 }  // extern "C"

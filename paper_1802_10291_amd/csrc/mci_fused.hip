@@ -40,6 +40,7 @@ constexpr int NT = 256;
 struct FusedArgs {
   const void* g;
   void* y;
+  const int64_t* offs;  // per-signal (input, output) element offsets, or null for a dense batch
   int64_t batch;
   int M, N, H, n1;
   int Nout, K;        // K = max |k| over the band
@@ -213,8 +214,28 @@ __host__ __device__ constexpr int fused_slots(int PF, int P, int TI, int Q, int 
   return fwd > mid ? (fwd > inv ? fwd : inv) : (mid > inv ? mid : inv);
 }
 
-// TI: how many of the Q/2 output transforms run side by side (1 or Q/2).
-template <int PF, bool BLUE, int P, int Q, int M, int TI>
+// Storage access: two consecutive real samples as one complex value, and four consecutive
+// outputs as one vector store (FP32, or FP16 with round-to-nearest conversion).
+__device__ __forceinline__ float2 ld_pair(const float* r, int p) { return ((const float2*)r)[p]; }
+__device__ __forceinline__ float2 ld_pair(const __half* r, int p) {
+  return __half22float2(((const __half2*)r)[p]);
+}
+__device__ __forceinline__ void st_pair(float* y, int q, float2 v) { ((float2*)y)[q] = v; }
+__device__ __forceinline__ void st_pair(__half* y, int q, float2 v) { ((__half2*)y)[q] = __float22half2_rn(v); }
+__device__ __forceinline__ void st_quad(float* y, int q, float2 lo, float2 hi) {
+  ((float4*)y)[q] = make_float4(lo.x, lo.y, hi.x, hi.y);
+}
+__device__ __forceinline__ void st_quad(__half* y, int q, float2 lo, float2 hi) {
+  const __half2 a = __float22half2_rn(lo), b = __float22half2_rn(hi);
+  uint2 u;
+  __builtin_memcpy(&u.x, &a, 4);
+  __builtin_memcpy(&u.y, &b, 4);
+  ((uint2*)y)[q] = u;
+}
+
+// TI: how many of the Q/2 output transforms run side by side (1 or Q/2).  TS: storage type
+// of the samples and outputs (float or __half); all arithmetic is FP32.
+template <int PF, bool BLUE, int P, int Q, int M, int TI, typename TS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
 void k_mci1d_fused(FusedArgs a) {
   extern __shared__ float2 sm[];
@@ -232,18 +253,18 @@ void k_mci1d_fused(FusedArgs a) {
     // one signal per workgroup: a persistent loop would keep the loop invariants of every
     // phase live across the whole body and cut the occupancy
     const int64_t sig = blockIdx.x;
-    const float* gs = (const float*)a.g + sig * (int64_t)M * N;
+    const TS* gs = (const TS*)a.g + (a.offs ? a.offs[2 * sig] : sig * (int64_t)M * N);
     // ---------------- 1. channel DFTs, all M channels side by side
     {
       float2 v[M][EF];
 #pragma unroll
       for (int m = 0; m < M; ++m) {
-        const float2* zin = (const float2*)(gs + (int64_t)m * N);
+        const TS* zin = gs + (int64_t)m * N;
 #pragma unroll
         for (int c = 0; c < EF; ++c) {
           const int p = tid + NT * c;
           float2 z = make_float2(0.f, 0.f);
-          if (p < H) z = zin[p];
+          if (p < H) z = ld_pair(zin, p);
           v[m][c] = z;
         }
       }
@@ -345,7 +366,7 @@ void k_mci1d_fused(FusedArgs a) {
     }
     __syncthreads();
     // ---------------- 3. output grid: Q/2 complex inverse FFTs of length P, TI at a time
-    float* ys = (float*)a.y + sig * (int64_t)a.Nout;
+    TS* ys = (TS*)a.y + (a.offs ? a.offs[2 * sig + 1] : sig * (int64_t)a.Nout);
     float2 keep[(Q / 2 - TI > 0 ? Q / 2 - TI : 1)][EI];   // earlier transforms' outputs
 #pragma unroll
     for (int pc0 = 0; pc0 < Q / 2; pc0 += TI) {
@@ -378,9 +399,9 @@ void k_mci1d_fused(FusedArgs a) {
         if constexpr (Q == 4) {
           const float2 lo = TI == 2 ? v[0][c] : keep[0][c];
           const float2 hi = TI == 2 ? v[TI - 1][c] : v[0][c];
-          *(float4*)(ys + 4 * q) = make_float4(lo.x, lo.y, hi.x, hi.y);
+          st_quad(ys, q, lo, hi);
         } else {
-          *(float2*)(ys + 2 * q) = v[0][c];
+          st_pair(ys, q, v[0][c]);
         }
       }
     }
@@ -393,63 +414,92 @@ struct FusedTables {
   float2 *twF, *chirp, *bhat, *wN, *twI, *wout;
 };
 
-template <int PF, bool BLUE, int P, int Q, int M, int TI>
-static hipError_t launch_mt(const FusedPlan& fp, const void* g, void* y, int64_t batch, hipStream_t s) {
+template <int PF, bool BLUE, int P, int Q, int M, int TI, typename TS>
+static hipError_t launch_mt(const FusedPlan& fp, const void* g, void* y, int64_t batch, const int64_t* offs,
+                            hipStream_t s) {
   FusedArgs a = *(const FusedArgs*)fp.args;
   a.g = g;
   a.y = y;
+  a.offs = offs;
   a.batch = batch;
   const size_t lds = (size_t)fp.lds_bytes;
   const int64_t grid = batch;   // one signal per workgroup
-  auto kern = k_mci1d_fused<PF, BLUE, P, Q, M, TI>;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), lds, s, a);
+  hipLaunchKernelGGL((k_mci1d_fused<PF, BLUE, P, Q, M, TI, TS>), dim3((unsigned)grid), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 
-template <int PF, bool BLUE, int P, int Q, int M>
-static hipError_t launch_m(const FusedPlan& fp, const void* g, void* y, int64_t batch, hipStream_t s) {
-  if (fp.ti == 2) return launch_mt<PF, BLUE, P, Q, M, 2>(fp, g, y, batch, s);
-  return launch_mt<PF, BLUE, P, Q, M, 1>(fp, g, y, batch, s);
+// Raise the kernels' dynamic LDS limit once, at plan time (not while a launch may be captured).
+template <int PF, bool BLUE, int P, int Q, int M, typename TS>
+static hipError_t prep_m(const int* lds_ti) {
+  if (lds_ti[0] > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_mci1d_fused<PF, BLUE, P, Q, M, 1, TS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_ti[0]);
+    if (e != hipSuccess) return e;
+  }
+  if (lds_ti[1] > 64 * 1024)
+    return hipFuncSetAttribute((const void*)k_mci1d_fused<PF, BLUE, P, Q, M, 2, TS>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_ti[1]);
+  return hipSuccess;
 }
 
 template <int PF, bool BLUE, int P, int Q>
-static hipError_t launch_t(const FusedPlan& fp, const void* g, void* y, int64_t batch, hipStream_t s) {
-  switch (((const FusedArgs*)fp.args)->M) {
-    case 1: return launch_m<PF, BLUE, P, Q, 1>(fp, g, y, batch, s);
-    case 2: return launch_m<PF, BLUE, P, Q, 2>(fp, g, y, batch, s);
-    case 3: return launch_m<PF, BLUE, P, Q, 3>(fp, g, y, batch, s);
-    default: return launch_m<PF, BLUE, P, Q, 4>(fp, g, y, batch, s);
+static hipError_t prep_t(int M, int store, const int* lds_ti) {
+  const bool h = store == ST_F16;
+  switch (M) {
+    case 1: return h ? prep_m<PF, BLUE, P, Q, 1, __half>(lds_ti) : prep_m<PF, BLUE, P, Q, 1, float>(lds_ti);
+    case 2: return h ? prep_m<PF, BLUE, P, Q, 2, __half>(lds_ti) : prep_m<PF, BLUE, P, Q, 2, float>(lds_ti);
+    case 3: return h ? prep_m<PF, BLUE, P, Q, 3, __half>(lds_ti) : prep_m<PF, BLUE, P, Q, 3, float>(lds_ti);
+    default: return h ? prep_m<PF, BLUE, P, Q, 4, __half>(lds_ti) : prep_m<PF, BLUE, P, Q, 4, float>(lds_ti);
   }
 }
 
-using LaunchFn = hipError_t (*)(const FusedPlan&, const void*, void*, int64_t, hipStream_t);
+template <int PF, bool BLUE, int P, int Q, int M>
+static hipError_t launch_m(const FusedPlan& fp, const void* g, void* y, int64_t batch, const int64_t* offs,
+                           hipStream_t s) {
+  if (fp.store == ST_F16) {
+    if (fp.ti == 2) return launch_mt<PF, BLUE, P, Q, M, 2, __half>(fp, g, y, batch, offs, s);
+    return launch_mt<PF, BLUE, P, Q, M, 1, __half>(fp, g, y, batch, offs, s);
+  }
+  if (fp.ti == 2) return launch_mt<PF, BLUE, P, Q, M, 2, float>(fp, g, y, batch, offs, s);
+  return launch_mt<PF, BLUE, P, Q, M, 1, float>(fp, g, y, batch, offs, s);
+}
+
+template <int PF, bool BLUE, int P, int Q>
+static hipError_t launch_t(const FusedPlan& fp, const void* g, void* y, int64_t batch, const int64_t* offs,
+                           hipStream_t s) {
+  switch (((const FusedArgs*)fp.args)->M) {
+    case 1: return launch_m<PF, BLUE, P, Q, 1>(fp, g, y, batch, offs, s);
+    case 2: return launch_m<PF, BLUE, P, Q, 2>(fp, g, y, batch, offs, s);
+    case 3: return launch_m<PF, BLUE, P, Q, 3>(fp, g, y, batch, offs, s);
+    default: return launch_m<PF, BLUE, P, Q, 4>(fp, g, y, batch, offs, s);
+  }
+}
+
+using LaunchFn = hipError_t (*)(const FusedPlan&, const void*, void*, int64_t, const int64_t*, hipStream_t);
+
+using PrepFn = hipError_t (*)(int, int, const int*);
 
 struct Variant {
   int PF;
   bool blue;
   int P, Q;
   LaunchFn fn;
+  PrepFn prep;
 };
 
+#define MCI_FV(PF, B, P, Q) {PF, B, P, Q, launch_t<PF, B, P, Q>, prep_t<PF, B, P, Q>}
 static const Variant kVariants[] = {
-    {2048, true, 4096, 4, launch_t<2048, true, 4096, 4>},
-    {1024, true, 4096, 4, launch_t<1024, true, 4096, 4>},
-    {1024, false, 4096, 4, launch_t<1024, false, 4096, 4>},
-    {2048, false, 4096, 4, launch_t<2048, false, 4096, 4>},
-    {2048, true, 2048, 4, launch_t<2048, true, 2048, 4>},
-    {1024, false, 1024, 4, launch_t<1024, false, 1024, 4>},
-    {2048, false, 2048, 4, launch_t<2048, false, 2048, 4>},
+    MCI_FV(2048, true, 4096, 4), MCI_FV(1024, true, 4096, 4), MCI_FV(1024, false, 4096, 4),
+    MCI_FV(2048, false, 4096, 4), MCI_FV(2048, true, 2048, 4), MCI_FV(1024, false, 1024, 4),
+    MCI_FV(2048, false, 2048, 4),
 };
+#undef MCI_FV
 
 static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void* tab, FusedPlan& fp) {
   fp.kind = 0;
-  if (prec != MCI_F32 || store != ST_F32 || !d.real_io || d.n_ops != 1 || d.M > MCI_MAX_CHANNELS) return MCI_OK;
+  if (prec != MCI_F32 || (store != ST_F32 && store != ST_F16) || !d.real_io || d.n_ops != 1 || d.M > MCI_MAX_CHANNELS) return MCI_OK;
   if (std::getenv("MCI_DISABLE_FUSED")) return MCI_OK;
   const int64_t N = d.N, M = d.M, n1 = d.n1, mu = M * N;
   if (N % 2 || N < 4 || N > (1 << 15) || d.n_out > (1 << 20)) return MCI_OK;
@@ -468,14 +518,19 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0) max_lds = v;
   }
-  const char* ti_env = std::getenv("MCI_FUSED_TI");
-  int ti = (ti_env && std::atoi(ti_env) == 2) ? pick->Q / 2 : 1;
-  int64_t lds = (int64_t)fused_slots(pick->PF, pick->P, ti, pick->Q, (int)M, (int)H, (int)K) * (int64_t)sizeof(float2);
-  if (lds > max_lds && ti > 1) {
-    ti = 1;
-    lds = (int64_t)fused_slots(pick->PF, pick->P, ti, pick->Q, (int)M, (int)H, (int)K) * (int64_t)sizeof(float2);
+  // LDS of the two output-transform groupings: one transform at a time (TI = 1), or all Q/2
+  // side by side (TI = 2), which needs more LDS and registers but one FFT pass sequence less
+  int64_t lds_ti[2];
+  for (int t = 0; t < 2; ++t)
+    lds_ti[t] = (int64_t)fused_slots(pick->PF, pick->P, t + 1, pick->Q, (int)M, (int)H, (int)K) * (int64_t)sizeof(float2);
+  if (lds_ti[0] > max_lds) return MCI_OK;
+  const int n_ti = lds_ti[1] <= max_lds ? 2 : 1;
+  {
+    const int lt[2] = {(int)lds_ti[0], n_ti == 2 ? (int)lds_ti[1] : 0};
+    if (pick->prep((int)M, store, lt) != hipSuccess) return MCI_OK;   // no fused kernel then
   }
-  if (lds > max_lds) return MCI_OK;
+  const int ti = 1;
+  const int64_t lds = lds_ti[0];
 
   // tables (FP64 on the host, stored FP32)
   const int PF = pick->PF, P = pick->P;
@@ -532,6 +587,10 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   fp.args = a;
   fp.lds_bytes = (int)lds;
   fp.ti = ti;
+  fp.n_ti = n_ti;
+  fp.lds_ti[0] = (int)lds_ti[0];
+  fp.lds_ti[1] = (int)lds_ti[1];
+  fp.store = store;
   fp.launch = (void*)pick->fn;
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -551,8 +610,14 @@ void fused_release(FusedPlan& fp) {
   fp.kind = 0;
 }
 
-hipError_t fused_run(const FusedPlan& fp, const void* g, void* y, int64_t batch, hipStream_t s) {
-  return ((LaunchFn)fp.launch)(fp, g, y, batch, s);
+void fused_set_ti(FusedPlan& fp, int ti) {
+  fp.ti = (ti == 2 && fp.n_ti == 2) ? 2 : 1;
+  fp.lds_bytes = fp.lds_ti[fp.ti - 1];
+}
+
+hipError_t fused_run(const FusedPlan& fp, const void* g, void* y, int64_t batch, const int64_t* offs,
+                     hipStream_t s) {
+  return ((LaunchFn)fp.launch)(fp, g, y, batch, offs, s);
 }
 
 }  // namespace mci

@@ -19,7 +19,9 @@ struct FftSide {
   int sign = -1;          // -1: e^{-2 pi i k n / len} (forward), +1: inverse
   bool blue = false;
   int64_t lexec = 0;
-  std::vector<int> radices;   // radices of lexec
+  std::vector<int> radices;   // radices of lexec run by the kernels (one of the two below)
+  std::vector<int> radices8;  // radix-8 passes first, then at most one 4 and one 2, then 3, 5, 7
+  std::vector<int> radices4;  // radix-4 passes, at most one 2, then 3, 5, 7
   void* tw = nullptr;         // e^{-2 pi i k / lexec}, lexec entries, plan precision
   void* chirp = nullptr;      // Bluestein: e^{sign i pi k^2 / len}, len entries
   void* bhat = nullptr;       // Bluestein: forward DFT_P of the conjugate chirp, divided by P
@@ -53,15 +55,17 @@ enum StoreKind { ST_F32 = 0, ST_F64 = 1, ST_F16 = 2 };
 // Launchers (mci_kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_plan_tables(const PlanKernelArgs& a, hipStream_t s);
 size_t generic_1d_workspace(const Generic1D& g, int prec, int64_t batch);
+// offs: per-signal (input, output) element offsets (device, 2 per signal) or null (dense)
 hipError_t run_generic_1d(const Generic1D& g, int prec, int store, const void* in, void* out, int64_t batch,
-                          void* ws, hipStream_t s);
+                          void* ws, const int64_t* offs, hipStream_t s);
 // 2-D helpers: build the two channels {x, centred difference} of every line.
 //   rows: x [B][h][w] -> G [B*h][2][w];  cols: x [B][H][W] (column c is a line of length H)
 //   -> G [B*W][2][H].  `deriv_scale` = len / (4 pi).
 hipError_t launch_fd_channels(int prec, int store_in, const void* x, void* G, int64_t B, int64_t h, int64_t w,
-                              int along_cols, hipStream_t s);
+                              int along_cols, const int64_t* offs, hipStream_t s);
 // transpose [B][W][H] -> [B][H][W] with storage conversion to the output type
+// (offs: image b's input at x + offs[2 b], output at dst + offs[2 b + 1]; null: dense)
 hipError_t launch_transpose_out(int prec, int store_out, const void* src, void* dst, int64_t B, int64_t W,
-                                int64_t H, hipStream_t s);
+                                int64_t H, const int64_t* offs, hipStream_t s);
 
 }  // namespace mci

@@ -163,17 +163,21 @@ static inline unsigned grid_for(int64_t total, int bs) {
 }
 
 // (1) samples -> complex buffer of length L per channel (zero padded, pre-chirped)
+//     Row t is channel t % rows of signal t / rows; with offs, signal b's samples start at
+//     element offs[2 b] of g, otherwise the rows are dense.
 template <typename T, typename St>
 __global__ void k_load(const St* __restrict__ g, cx<T>* __restrict__ x, int64_t count, int64_t len, int64_t L,
-                       int real_io, const cx<T>* __restrict__ chirp) {
+                       int real_io, const cx<T>* __restrict__ chirp, const int64_t* __restrict__ offs, int rows) {
   const int64_t total = count * L;
+  const int64_t cw = real_io ? 1 : 2;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t t = e / L, k = e - t * L;
     cx<T> v = cmake<cx<T>>((T)0, (T)0);
     if (k < len) {
-      const int64_t src = t * len + k;
+      const int64_t row = offs ? offs[2 * (t / rows)] + (t % rows) * len * cw : t * len * cw;
+      const int64_t src = row + k * cw;
       if (real_io) v.x = ld_as<T>(g, src);
-      else { v.x = ld_as<T>(g, 2 * src); v.y = ld_as<T>(g, 2 * src + 1); }
+      else { v.x = ld_as<T>(g, src); v.y = ld_as<T>(g, src + 1); }
       if (chirp) v = cmul(v, chirp[k]);
     }
     x[e] = v;
@@ -249,16 +253,20 @@ __global__ void k_apply(const cx<T>* __restrict__ X, int64_t Lx, const cx<T>* __
 }
 
 // (5) output: real part (real mode) or complex, optional Bluestein post-chirp
+//     Row t is output op t % rows of signal t / rows (signal b's outputs start at element
+//     offs[2 b + 1] of y with offs, otherwise dense).
 template <typename T, typename St>
 __global__ void k_store(const cx<T>* __restrict__ F, int64_t Lf, St* __restrict__ y, int64_t count, int64_t n_out,
-                        int real_io, const cx<T>* __restrict__ post) {
+                        int real_io, const cx<T>* __restrict__ post, const int64_t* __restrict__ offs, int rows) {
   const int64_t total = count * n_out;
+  const int64_t cw = real_io ? 1 : 2;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t t = e / n_out, j = e - t * n_out;
     cx<T> v = F[t * Lf + j];
     if (post) v = cmul(v, post[j]);
-    if (real_io) st_as<T>(y, e, v.x);
-    else { st_as<T>(y, 2 * e, v.x); st_as<T>(y, 2 * e + 1, v.y); }
+    const int64_t dst = (offs ? offs[2 * (t / rows) + 1] + (t % rows) * n_out * cw : t * n_out * cw) + j * cw;
+    if (real_io) st_as<T>(y, dst, v.x);
+    else { st_as<T>(y, dst, v.x); st_as<T>(y, dst + 1, v.y); }
   }
 }
 
@@ -321,7 +329,8 @@ size_t generic_1d_workspace(const Generic1D& g, int prec, int64_t batch) {
 }
 
 template <typename T, typename St>
-static hipError_t generic_1d_t(const Generic1D& g, const void* in, void* out, int64_t batch, void* ws, hipStream_t s) {
+static hipError_t generic_1d_t(const Generic1D& g, const void* in, void* out, int64_t batch, void* ws,
+                               const int64_t* offs, hipStream_t s) {
   const FftSide& fw = *g.fwd;
   const FftSide& iv = *g.inv;
   cx<T>* base = (cx<T>*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
@@ -333,7 +342,7 @@ static hipError_t generic_1d_t(const Generic1D& g, const void* in, void* out, in
   hipError_t e;
   // (1) load
   hipLaunchKernelGGL((k_load<T, St>), dim3(grid_for(batch * g.M * fw.lexec, bs)), dim3(bs), 0, s, (const St*)in,
-                     X[0], batch * g.M, g.N, fw.lexec, g.real_io, fw.blue ? (const cx<T>*)fw.chirp : nullptr);
+                     X[0], batch * g.M, g.N, fw.lexec, g.real_io, fw.blue ? (const cx<T>*)fw.chirp : nullptr, offs, g.M);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // (2) channel DFTs
   int cx_ = 0;
@@ -349,15 +358,15 @@ static hipError_t generic_1d_t(const Generic1D& g, const void* in, void* out, in
   // (5) store
   hipLaunchKernelGGL((k_store<T, St>), dim3(grid_for(batch * g.n_ops * g.n_out, bs)), dim3(bs), 0, s, F[cf],
                      iv.lexec, (St*)out, batch * g.n_ops, g.n_out, g.real_io,
-                     iv.blue ? (const cx<T>*)iv.chirp : nullptr);
+                     iv.blue ? (const cx<T>*)iv.chirp : nullptr, offs, g.n_ops);
   return hipGetLastError();
 }
 
 hipError_t run_generic_1d(const Generic1D& g, int prec, int store, const void* in, void* out, int64_t batch,
-                          void* ws, hipStream_t s) {
-  if (prec == MCI_F64) return generic_1d_t<double, double>(g, in, out, batch, ws, s);
-  if (store == ST_F16) return generic_1d_t<float, __half>(g, in, out, batch, ws, s);
-  return generic_1d_t<float, float>(g, in, out, batch, ws, s);
+                          void* ws, const int64_t* offs, hipStream_t s) {
+  if (prec == MCI_F64) return generic_1d_t<double, double>(g, in, out, batch, ws, offs, s);
+  if (store == ST_F16) return generic_1d_t<float, __half>(g, in, out, batch, ws, offs, s);
+  return generic_1d_t<float, float>(g, in, out, batch, ws, offs, s);
 }
 
 // ================================================================= 2-D helpers
@@ -365,7 +374,7 @@ hipError_t run_generic_1d(const Generic1D& g, int prec, int store, const void* i
 // h = 2 pi / len, circular.  Output G[line][2][len] in the compute type.
 template <typename T, typename St>
 __global__ void k_fd_channels(const St* __restrict__ x, T* __restrict__ G, int64_t B, int64_t h, int64_t w,
-                              int along_cols) {
+                              int along_cols, const int64_t* __restrict__ offs) {
   const int64_t len = along_cols ? h : w;
   const int64_t lines_per_img = along_cols ? w : h;
   const int64_t total = B * lines_per_img * len;
@@ -377,10 +386,10 @@ __global__ void k_fd_channels(const St* __restrict__ x, T* __restrict__ G, int64
     const int64_t pn = (p + 1 == len) ? 0 : p + 1, pp = (p == 0) ? len - 1 : p - 1;
     T v, vn, vp;
     if (!along_cols) {
-      const int64_t r0 = (b * h + l) * w;
+      const int64_t r0 = (offs ? offs[2 * b] : b * h * w) + l * w;
       v = ld_as<T>(x, r0 + p); vn = ld_as<T>(x, r0 + pn); vp = ld_as<T>(x, r0 + pp);
     } else {
-      const int64_t c0 = b * h * w + l;
+      const int64_t c0 = (offs ? offs[2 * b] : b * h * w) + l;
       v = ld_as<T>(x, c0 + p * w); vn = ld_as<T>(x, c0 + pn * w); vp = ld_as<T>(x, c0 + pp * w);
     }
     G[(line * 2) * len + p] = v;
@@ -389,45 +398,46 @@ __global__ void k_fd_channels(const St* __restrict__ x, T* __restrict__ G, int64
 }
 
 hipError_t launch_fd_channels(int prec, int store_in, const void* x, void* G, int64_t B, int64_t h, int64_t w,
-                              int along_cols, hipStream_t s) {
+                              int along_cols, const int64_t* offs, hipStream_t s) {
   const int64_t total = B * h * w;
   const int bs = 256;
   if (prec == MCI_F64)
     hipLaunchKernelGGL((k_fd_channels<double, double>), dim3(grid_for(total, bs)), dim3(bs), 0, s,
-                       (const double*)x, (double*)G, B, h, w, along_cols);
+                       (const double*)x, (double*)G, B, h, w, along_cols, offs);
   else if (store_in == ST_F16)
     hipLaunchKernelGGL((k_fd_channels<float, __half>), dim3(grid_for(total, bs)), dim3(bs), 0, s,
-                       (const __half*)x, (float*)G, B, h, w, along_cols);
+                       (const __half*)x, (float*)G, B, h, w, along_cols, offs);
   else
     hipLaunchKernelGGL((k_fd_channels<float, float>), dim3(grid_for(total, bs)), dim3(bs), 0, s,
-                       (const float*)x, (float*)G, B, h, w, along_cols);
+                       (const float*)x, (float*)G, B, h, w, along_cols, offs);
   return hipGetLastError();
 }
 
 template <typename T, typename St>
-__global__ void k_transpose_out(const T* __restrict__ src, St* __restrict__ dst, int64_t B, int64_t W, int64_t H) {
+__global__ void k_transpose_out(const T* __restrict__ src, St* __restrict__ dst, int64_t B, int64_t W, int64_t H,
+                                const int64_t* __restrict__ offs) {
   const int64_t total = B * W * H;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = e % W;
     const int64_t r = (e / W) % H;
     const int64_t b = e / (W * H);
-    st_as<T>(dst, e, src[(b * W + c) * H + r]);
+    st_as<T>(dst, (offs ? offs[2 * b + 1] : b * W * H) + r * W + c, src[(b * W + c) * H + r]);
   }
 }
 
 hipError_t launch_transpose_out(int prec, int store_out, const void* src, void* dst, int64_t B, int64_t W,
-                                int64_t H, hipStream_t s) {
+                                int64_t H, const int64_t* offs, hipStream_t s) {
   const int64_t total = B * W * H;
   const int bs = 256;
   if (prec == MCI_F64)
     hipLaunchKernelGGL((k_transpose_out<double, double>), dim3(grid_for(total, bs)), dim3(bs), 0, s,
-                       (const double*)src, (double*)dst, B, W, H);
+                       (const double*)src, (double*)dst, B, W, H, offs);
   else if (store_out == ST_F16)
     hipLaunchKernelGGL((k_transpose_out<float, __half>), dim3(grid_for(total, bs)), dim3(bs), 0, s,
-                       (const float*)src, (__half*)dst, B, W, H);
+                       (const float*)src, (__half*)dst, B, W, H, offs);
   else
     hipLaunchKernelGGL((k_transpose_out<float, float>), dim3(grid_for(total, bs)), dim3(bs), 0, s,
-                       (const float*)src, (float*)dst, B, W, H);
+                       (const float*)src, (float*)dst, B, W, H, offs);
   return hipGetLastError();
 }
 

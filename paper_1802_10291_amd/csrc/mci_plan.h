@@ -1,0 +1,61 @@
+// mci_plan.h -- the plan object behind mci_plan_t and the internal entry points shared by
+// the plan API, the uneven-batch runner and the autotuner.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "mci_fused.h"
+#include "mci_internal.h"
+
+struct mci_plan_s {
+  int dims = 1;  // 1: 1-D plan, 2: 2-D plan
+  int device = 0;
+  mci_plan_desc d{};
+  int64_t mu = 0;
+  int prec = MCI_F32;
+  int store = mci::ST_F32;
+  void* tab = nullptr;      // [n_ops][M][M][N] complex in plan precision
+  mci::FftSide fwd, inv;
+  double max_cond = 0.0;
+  int64_t n_sing = 0, first_sing = INT64_MIN;
+  mci::FusedPlan fused;     // single-pass kernel choice (fused.kind == 0: none)
+  bool use_fused = false;   // the fused kernel is the active variant
+  int variant = MCI_VARIANT_MULTIPASS_R8;
+  std::vector<std::complex<double>> tab_host;   // FP64 apply table [n_ops][M][M][N]
+  // 2-D fused line passes: windows H[SC][len] and twiddles per axis (cols, rows)
+  bool lp = false;          // active
+  bool lp_avail = false;    // built
+  void* lp_H[2] = {nullptr, nullptr};
+  void* lp_tw[2] = {nullptr, nullptr};
+  // 2-D
+  mci_plan2d_desc d2{};
+  mci_plan_s* rows = nullptr;
+  mci_plan_s* cols = nullptr;
+};
+
+namespace mci {
+
+mci_status fail(mci_status s, const std::string& msg);
+
+// bytes of one storage element, and per-instance input / output sizes in elements
+int store_bytes(int store);
+int64_t instance_in_elems(const mci_plan_s* p);
+int64_t instance_out_elems(const mci_plan_s* p);
+
+size_t plan_workspace(const mci_plan_s* p, int64_t batch);
+// Queue `batch` instances.  offs (device, 2 per instance): element offsets of each
+// instance's input and output, or null for a dense batch.  Arguments are not validated.
+mci_status plan_run(const mci_plan_s* p, const void* in, void* out, int64_t batch, void* ws, const int64_t* offs,
+                    hipStream_t s);
+
+uint32_t plan_variant_mask(const mci_plan_s* p);
+mci_status plan_set_variant(mci_plan_s* p, int v);
+// cache key of the plan's shape on the current device
+std::string plan_tune_key(const mci_plan_s* p);
+// variant recorded for `key` in the cache file, or -1
+int tune_cache_lookup(const std::string& path, const std::string& key);
+
+}  // namespace mci

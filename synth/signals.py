@@ -90,13 +90,14 @@ def smooth_noisy_spectrum(rng: np.random.Generator, n_max: int, decay: float = 0
 
 
 def smooth_noisy_batch(first: int, count: int, M: int, N: int, n_max: int, seed_base: int = 2_000_000,
-                       dtype=np.float32) -> np.ndarray:
+                       dtype=np.float32, deriv_scale: float = 1.0) -> np.ndarray:
     """Samples [count][M][N] of signals first .. first+count-1.
 
     Signal s draws its spectrum from ``numpy.random.default_rng(seed_base + s)``
     (:func:`smooth_noisy_spectrum`) and is sampled with the derivative channels
-    b_m(n) = (i n)^m, m = 0 .. M-1, at t_p = 2 pi p / N.  The FP64 samples are rounded
-    once to ``dtype``."""
+    b_m(n) = (i n / deriv_scale)^m, m = 0 .. M-1, at t_p = 2 pi p / N (deriv_scale = N
+    keeps every channel within a small factor of the signal's own size, which FP16
+    storage needs).  The FP64 samples are rounded once to ``dtype``."""
     out = np.empty((count, M, N), dtype=dtype)
     n = np.arange(-n_max, n_max + 1)
     k = np.mod(n, N)
@@ -104,7 +105,7 @@ def smooth_noisy_batch(first: int, count: int, M: int, N: int, n_max: int, seed_
     lo = -n_max - np.mod(-n_max, N)          # first multiple of N at or below -n_max
     span = ((n_max - lo) // N + 1) * N
     pad_start = -n_max - lo
-    powers = [(1j * n.astype(np.float64)) ** m for m in range(M)]
+    powers = [(1j * n.astype(np.float64) / deriv_scale) ** m for m in range(M)]
     for s in range(count):
         rng = np.random.default_rng(seed_base + first + s)
         _, c = smooth_noisy_spectrum(rng, n_max)

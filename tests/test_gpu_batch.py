@@ -1,0 +1,306 @@
+"""Uneven batches, kernel variants, the autotuner, FP16 storage in the single-pass kernel,
+and graph capture -- on the GPU, against the FP64 oracle and against single-plan calls.
+
+Tolerances as in test_gpu_parity: 1e-5 relative L2 for FP32 storage, 1e-3 for FP16
+storage (the output's own rounding, 2^-11, dominates).  A batch runs each instance
+through the same kernels as a single-plan call, only at other addresses, so the two must
+agree bit for bit.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import images as SI
+from synth import signals as S
+from synth import uneven as U
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1802_10291_amd  # noqa: F401
+    return torch
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def deriv_channels(M):
+    return [("deriv", m) for m in range(M)]
+
+
+def scaled_deriv_tables(M, N):
+    """b_m(n) = (i n / N)^m on the default band: derivative channels in units that keep the
+    samples of every channel near the signal's own size (FP16 range)."""
+    mu = M * N
+    n = np.arange(-((mu - 1) // 2), -((mu - 1) // 2) + mu)
+    return [(1j * n / N) ** m for m in range(M)]
+
+
+def oracle_1d(g, M, N, n_out, scaled=False):
+    if scaled:
+        ch = O.Channels(N=N, kinds=[O.MULT_TABLE] * M, orders=[0] * M, tables=np.stack(scaled_deriv_tables(M, N)))
+    else:
+        ch = O.Channels(N=N, kinds=[O.MULT_DERIV] * M, orders=list(range(M)))
+    return O.reconstruct_1d(ch, g.astype(np.float64), n_out)
+
+
+# ------------------------------------------------------------------ FP16 single-pass kernel
+@pytest.mark.parametrize("N,n_out,M", [(1366, 16384, 3), (2048, 16384, 2), (1022, 8192, 4)])
+def test_fused_f16_storage_parity(torch_cuda, N, n_out, M):
+    from paper_1802_10291_amd import Plan1D
+    g = S.smooth_noisy_batch(0, 3, M, N, 2 * N, dtype=np.float16, deriv_scale=N)
+    assert np.isfinite(g).all()
+    plan = Plan1D(N=N, n_out=n_out, channels=[("table", t) for t in scaled_deriv_tables(M, N)], storage="f16")
+    assert plan.info.path == 1 and plan.variant == "fused_t1"
+    y = plan.reconstruct(torch_cuda.from_numpy(g).cuda()).cpu().numpy().astype(np.float64)
+    want = oracle_1d(g, M, N, n_out, scaled=True)
+    for b in range(3):
+        assert rel(y[b], want[b]) <= 1e-3
+
+
+# ------------------------------------------------------------------ variants
+def test_every_1d_variant_matches_oracle(torch_cuda):
+    from paper_1802_10291_amd import Plan1D
+    M, N, n_out = 3, 1366, 16384
+    g = S.smooth_noisy_batch(40, 3, M, N, 8192)
+    want = oracle_1d(g, M, N, n_out)
+    plan = Plan1D(N=N, n_out=n_out, channels=deriv_channels(M))
+    names = plan.variants()
+    assert names[:3] == ["multipass_r8", "multipass_r4", "fused_t1"]
+    gd = torch_cuda.from_numpy(g).cuda()
+    for v in names:
+        plan.set_variant(v)
+        assert plan.variant == v and plan.info.path == (1 if v.startswith("fused") else 0)
+        y = plan.reconstruct(gd).cpu().numpy().astype(np.float64)
+        for b in range(3):
+            assert rel(y[b], want[b]) <= 1e-5, (v, b)
+    with pytest.raises(Exception):
+        plan.set_variant("line_pass")
+
+
+@pytest.mark.parametrize("N", [86, 96])      # Bluestein (86 = 2 * 43) and 7-smooth
+def test_multipass_radix_variants(torch_cuda, N):
+    from paper_1802_10291_amd import Plan1D
+    g = S.smooth_noisy_batch(50, 2, 3, N, 4 * N)
+    want = oracle_1d(g, 3, N, 4 * 3 * N)
+    plan = Plan1D(N=N, n_out=12 * N, channels=deriv_channels(3))
+    assert plan.variants() == ["multipass_r8", "multipass_r4"]
+    for v in plan.variants():
+        plan.set_variant(v)
+        y = plan.reconstruct(torch_cuda.from_numpy(g).cuda()).cpu().numpy()
+        assert max(rel(y[b], want[b]) for b in range(2)) <= 1e-5, v
+
+
+def test_2d_variants_match_oracle(torch_cuda):
+    from paper_1802_10291_amd import Plan2D
+    lr = SI.random_field_images(3, 2, 64, 64)
+    want = O.upsample_2d(lr.astype(np.float64), 2)
+    plan = Plan2D(64, 64, 2)
+    assert plan.variants() == ["multipass_r8", "line_pass"] and plan.variant == "line_pass"
+    for v in plan.variants():
+        plan.set_variant(v)
+        hr = plan.upsample(torch_cuda.from_numpy(lr).cuda()).cpu().numpy()
+        assert rel(hr, want) <= 1e-5, v
+
+
+# ------------------------------------------------------------------ autotuner
+def test_autotune_picks_fastest_and_caches(torch_cuda, tmp_path, monkeypatch):
+    from paper_1802_10291_amd import Plan1D
+    cache = str(tmp_path / "tune.json")
+    plan = Plan1D(N=1366, n_out=16384, channels=deriv_channels(3))
+    name, ms, cached = plan.autotune(256, cache)
+    assert not cached and name in plan.variants() and plan.variant == name
+    assert set(ms) == set(plan.variants()) and all(v > 0 for v in ms.values())
+    assert ms[name] == min(ms.values())
+    doc = json.load(open(cache))
+    assert len(doc["entries"]) == 1 and doc["entries"][0]["variant"] == plan.info.variant
+    name2, _, cached2 = plan.autotune(256, cache)
+    assert cached2 and name2 == name
+    # a second shape adds an entry; the file stays valid JSON
+    other = Plan1D(N=96, n_out=1152, channels=deriv_channels(3))
+    other.autotune(64, cache)
+    assert len(json.load(open(cache))["entries"]) == 2
+    # plans created with the cache in the environment start on the recorded variant
+    monkeypatch.setenv("MCI_TUNE_CACHE", cache)
+    for forced in ("multipass_r4", "fused_t1"):
+        plan.set_variant(forced)
+        doc = json.load(open(cache))
+        for e in doc["entries"]:
+            if "|N1366|" in e["key"]:
+                e["variant"] = plan.info.variant
+        with open(cache, "w") as f:
+            f.write('{"version": 1, "entries": [\n' + ",\n".join(json.dumps(e) for e in doc["entries"]) + "\n]}\n")
+        fresh = Plan1D(N=1366, n_out=16384, channels=deriv_channels(3))
+        assert fresh.variant == forced
+
+
+def test_autotune_2d_plan(torch_cuda, tmp_path):
+    from paper_1802_10291_amd import Plan2D
+    plan = Plan2D(128, 128, 2)
+    name, ms, cached = plan.autotune(8, str(tmp_path / "t.json"))
+    assert set(ms) == {"multipass_r8", "line_pass"} and name == min(ms, key=ms.get)
+
+
+# ------------------------------------------------------------------ uneven batches
+# (kind, args): 1-D (N, M, n_out) with single-pass and multi-pass classes, Bluestein and
+# smooth lengths; 2-D (side, scale) with line-pass and multi-pass classes
+MIX = [("1d", (1366, 3, 16384)), ("1d", (1000, 3, 16384)), ("1d", (86, 3, 1024)), ("1d", (64, 4, 1024)),
+       ("1d", (128, 2, 1024)), ("2d", (64, 2)), ("2d", (48, 2)), ("2d", (32, 2))]
+
+
+def _mixed_batch(torch, storage="native", lanes=4, seed=0, per_class=3):
+    from paper_1802_10291_amd import Batch, Plan1D, Plan2D
+    np_dt = np.float16 if storage == "f16" else np.float32
+    f16 = storage == "f16"
+    plans, data = [], []
+    for c, (kind, a) in enumerate(MIX):
+        if kind == "1d":
+            N, M, n_out = a
+            chans = [("table", t) for t in scaled_deriv_tables(M, N)] if f16 else deriv_channels(M)
+            plans.append(Plan1D(N=N, n_out=n_out, channels=chans, storage=storage))
+            data.append(S.smooth_noisy_batch(100 * c, per_class, M, N, 2 * M * N, dtype=np_dt,
+                                             deriv_scale=N if f16 else 1.0))
+        else:
+            side, s = a
+            plans.append(Plan2D(side, side, s, storage=storage))
+            data.append(SI.random_field_images(100 * c, per_class, side, side).astype(np_dt))
+    order = [(c, k) for c in range(len(MIX)) for k in range(per_class)]
+    np.random.default_rng(seed).shuffle(order)
+    batch = Batch([plans[c] for c, _ in order], lanes=lanes)
+    packed = np.zeros(batch.in_elems, dtype=np_dt)
+    for (c, k), off in zip(order, batch.in_offsets):
+        x = data[c][k].ravel()
+        packed[off:off + x.size] = x
+    return batch, plans, data, order, packed
+
+
+def _unpack(batch, plans, order, out_host):
+    res = []
+    for (c, k), off in zip(order, batch.out_offsets):
+        n = plans[c].instance_sizes()[1]
+        res.append(out_host[off:off + n])
+    return res
+
+
+@pytest.mark.parametrize("storage,lanes", [("native", 4), ("native", 1), ("f16", 4)])
+def test_uneven_batch_matches_single_calls_and_oracle(torch_cuda, storage, lanes):
+    torch = torch_cuda
+    batch, plans, data, order, packed = _mixed_batch(torch, storage, lanes)
+    dev_in = torch.from_numpy(packed).cuda()
+    out = torch.full((batch.out_elems,), float("nan"), dtype=dev_in.dtype, device="cuda")
+    batch.run(dev_in, out)
+    host = out.cpu().numpy().astype(np.float64)
+    # everything outside the instances' extents is untouched
+    mask = np.ones(batch.out_elems, dtype=bool)
+    for (c, k), off in zip(order, batch.out_offsets):
+        mask[off:off + plans[c].instance_sizes()[1]] = False
+    assert np.isnan(host[mask]).all()
+    # bit-identical to single-plan calls, and within tolerance of the oracle
+    singles = []
+    for c, (kind, a) in enumerate(MIX):
+        x = torch.from_numpy(data[c]).cuda()
+        y = plans[c].reconstruct(x) if kind == "1d" else plans[c].upsample(x)
+        singles.append(y.cpu().numpy().astype(np.float64).reshape(len(data[c]), -1))
+    tol = 1e-3 if storage == "f16" else 1e-5
+    oracle_cache = {}
+    for (c, k), got in zip(order, _unpack(batch, plans, order, host)):
+        assert np.array_equal(got, singles[c][k]), (MIX[c], k)
+        kind, a = MIX[c]
+        if c not in oracle_cache:
+            if kind == "1d":
+                N, M, n_out = a
+                oracle_cache[c] = oracle_1d(data[c], M, N, n_out, scaled=storage == "f16").reshape(len(data[c]), -1)
+            else:
+                oracle_cache[c] = O.upsample_2d(data[c].astype(np.float64), a[1]).reshape(len(data[c]), -1)
+        assert rel(got, oracle_cache[c][k]) <= tol, (MIX[c], k)
+
+
+def test_uneven_batch_graph_capture_replays(torch_cuda):
+    """The whole mixed batch (four lanes forked from and joined into the capture stream) is
+    captured as one graph; each replay, with eager work and new input values in between,
+    reproduces the eager result for the current input."""
+    torch = torch_cuda
+    batch, plans, data, order, packed = _mixed_batch(torch, "native", 4)
+    dev_in = torch.from_numpy(packed).cuda()
+    out = torch.zeros(batch.out_elems, dtype=torch.float32, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batch.run(dev_in, out)          # warm-up; allocates the workspace outside capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.run(dev_in, out)
+    for r in range(3):
+        scale = 1.0 + 0.5 * r
+        dev_in.copy_(torch.from_numpy(packed).cuda() * scale)
+        ref = batch.run(dev_in, torch.empty_like(out))
+        torch.cuda.synchronize()
+        out.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"replay {r}"
+
+
+def test_uneven_batch_rejects_bad_layouts(torch_cuda):
+    from paper_1802_10291_amd import Batch, MCIError, Plan1D, Plan2D
+    p = Plan1D(N=64, n_out=512, channels=deriv_channels(2))
+    q = Plan2D(32, 32, 2, storage="f16")
+    n_in, n_out = p.instance_sizes()
+    with pytest.raises(MCIError):       # overlapping outputs
+        Batch([p, p], offsets=([0, n_in], [0, n_out - 4]))
+    with pytest.raises(MCIError):       # misaligned offset
+        Batch([p], offsets=([2], [0]))
+    with pytest.raises(MCIError):       # mixed element types
+        Batch([p, q])
+    b = Batch([p, p], offsets=([0, 0], [0, n_out]))   # shared input is allowed
+    assert b.in_elems == n_in and b.out_elems == 2 * n_out
+
+
+@pytest.mark.parametrize("key", [("1d", 65536, 2), ("1d", 49152, 3), ("1d", 65536, 4), ("2d", 1024)])
+def test_uneven_workload_largest_classes_sampled_parity(torch_cuda, key):
+    """The mixed workload's largest classes at full size, in one batch with a small class:
+    1-D outputs checked at 48 sampled grid points each (relative L2 over the sample) against
+    the oracle's recovered band evaluated there directly; 2-D images against the full oracle."""
+    from paper_1802_10291_amd import Batch, Plan1D, Plan2D
+    torch = torch_cuda
+    pool = U.class_pool(key, 99, 2)
+    if key[0] == "1d":
+        _, L, M = key
+        N = -(-L // M)
+        plan = Plan1D(N=N, n_out=4 * L, channels=deriv_channels(M))
+    else:
+        plan = Plan2D(key[1] // 2, key[1] // 2, 2)
+    small = Plan1D(N=64, n_out=1024, channels=deriv_channels(2))
+    small_in = S.smooth_noisy_batch(0, 1, 2, 64, 256)
+    batch = Batch([plan, small, plan])
+    packed = np.zeros(batch.in_elems, dtype=np.float32)
+    for x, off in zip([pool[0], small_in[0], pool[1]], batch.in_offsets):
+        packed[off:off + x.size] = x.ravel()
+    out = batch.run(torch.from_numpy(packed).cuda()).cpu().numpy().astype(np.float64)
+    n_out_elems = plan.instance_sizes()[1]
+    got = [out[batch.out_offsets[i]:batch.out_offsets[i] + n_out_elems] for i in (0, 2)]
+    if key[0] == "1d":
+        ch = O.Channels(N=N, kinds=[O.MULT_DERIV] * M, orders=list(range(M)))
+        band = O.recover_band(ch, pool.astype(np.float64))
+        idx = np.random.default_rng(L + M).choice(4 * L, 48, replace=False)
+        for b in range(2):
+            want = O.evaluate_band(band[b], ch.n1, 2 * np.pi * idx / (4 * L))
+            assert rel(got[b][idx], want) <= 1e-5
+    else:
+        want = O.upsample_2d(pool.astype(np.float64), 2)
+        for b in range(2):
+            assert rel(got[b], want[b].ravel()) <= 1e-5
+    small_want = oracle_1d(small_in, 2, 64, 1024)[0, 0]
+    assert rel(out[batch.out_offsets[1]:batch.out_offsets[1] + 1024], small_want) <= 1e-5

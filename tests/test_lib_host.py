@@ -102,3 +102,34 @@ def test_null_arguments_rejected():
     assert lib.mci_reconstruct_1d(None, None, None, 1, None, 0, None) == 1
     n = ctypes.c_size_t()
     assert lib.mci_workspace_size(None, 1, ctypes.byref(n)) == 1
+
+
+def test_batch_and_tuner_structs_match_c_layout():
+    L = _lib()
+    # mci_batch_item: pointer + 2 int64; mci_tune_result: 2 int32 + int64 + 5 doubles
+    assert ctypes.sizeof(L.mci_batch_item) == 24
+    assert ctypes.sizeof(L.mci_tune_result) == 16 + 8 * L.MCI_NUM_VARIANTS
+    assert L.mci_tune_result.ms.offset == 16
+    assert L.mci_plan_info_t.variant.offset == 52
+
+
+def test_batch_and_variant_arguments_rejected_without_device():
+    L = _lib()
+    lib = L.load()
+    h = ctypes.c_void_p()
+    items = (L.mci_batch_item * 1)()
+    items[0].plan, items[0].in_off, items[0].out_off = None, 0, 0
+    assert lib.mci_batch_create(items, 1, 0, ctypes.byref(h)) == 1       # NULL plan
+    assert lib.mci_batch_create(items, -1, 0, ctypes.byref(h)) == 1      # negative count
+    assert lib.mci_batch_create(items, 0, 9, ctypes.byref(h)) == 1       # lanes out of range
+    assert lib.mci_batch_create(items, 0, 0, None) == 1
+    assert lib.mci_plan_set_variant(None, 0) == 1
+    assert lib.mci_plan_autotune(None, 1, None, None) == 1
+    assert lib.mci_reconstruct_batch(None, None, None, None, 0, None) == 1
+    # an empty batch needs no device: it is created, sized and run as a no-op
+    assert lib.mci_batch_create(items, 0, 0, ctypes.byref(h)) == 0
+    a, b, c = ctypes.c_int64(7), ctypes.c_int64(7), ctypes.c_size_t(7)
+    assert lib.mci_batch_sizes(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) == 0
+    assert (a.value, b.value, c.value) == (0, 0, 0)
+    assert lib.mci_reconstruct_batch(h, None, None, None, 0, None) == 0
+    assert lib.mci_batch_destroy(h) == 0

@@ -545,3 +545,41 @@ def test_psnr_helper():
     ref = np.zeros((4, 4))
     img = np.full((4, 4), 0.1)
     assert O.psnr(img, ref) == pytest.approx(20.0)
+
+
+# ---------------------------------------------------------------- sampled evaluation
+def test_evaluate_band_exact_recovery_off_grid():
+    """A real trigonometric polynomial in the band, recovered from {f, f', f''} samples, is
+    evaluated exactly at arbitrary (off-grid) points; so are its Hilbert transform and its
+    derivative, whose closed forms are the coefficient-wise multipliers -i sgn n and i n."""
+    N = 12
+    ch = O.Channels(N=N, kinds=[O.MULT_DERIV] * 3, orders=[0, 1, 2])
+    deg = (ch.mu - 1) // 2 - 1
+    g, n, a = S.single_signal_fp64(seed=3, degree=deg, N=N)
+    g = S.sample_channels(n, a, [S.deriv_multiplier(m) for m in range(3)], N, real=True)
+    band = O.recover_band(ch, g)
+    t = np.random.default_rng(4).uniform(0, 2 * np.pi, 37)
+    E = np.exp(1j * np.outer(t, n))
+    for op, order, mult in ((O.OUT_IDENTITY, 0, 1.0), (O.OUT_HILBERT, 0, -1j * np.sign(n)),
+                            (O.OUT_DERIV, 1, 1j * n)):
+        want = (E @ (mult * a)).real
+        got = O.evaluate_band(band, ch.n1, t, op, order)
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_evaluate_band_cos_to_sin_and_grid_equals_reconstruction():
+    """Closed form: the band {cos 3t} gives H -> sin 3t and d/dt -> -3 sin 3t; on the output
+    grid the sum is the reconstruction itself, including a grid coarser than the band."""
+    n1 = -5
+    a = np.zeros(11, dtype=complex)
+    a[3 - n1] = a[-3 - n1] = 0.5
+    t = np.linspace(0.1, 6.0, 29)
+    assert np.abs(O.evaluate_band(a, n1, t, O.OUT_HILBERT) - np.sin(3 * t)).max() < 1e-14
+    assert np.abs(O.evaluate_band(a, n1, t, O.OUT_DERIV, 1) + 3 * np.sin(3 * t)).max() < 1e-13
+    rng = np.random.default_rng(8)
+    ch = O.Channels(N=9, kinds=[O.MULT_DERIV, O.MULT_DERIV], orders=[0, 1])
+    g = rng.standard_normal((2, 9))
+    band = O.recover_band(ch, g)
+    for n_out in (40, 7):
+        tj = 2 * np.pi * np.arange(n_out) / n_out
+        assert np.allclose(O.evaluate_band(band, ch.n1, tj), O.reconstruct_1d(ch, g, n_out)[0], atol=1e-12)
