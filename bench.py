@@ -13,7 +13,8 @@ one JSON line with throughput (reconstructed output samples/s), the roofline of 
 dominant kernel (timed with HIP events on its stream) and the FP64 CPU oracle on a
 bounded sample of the same workload, plus the relative error of that sample.
 
-  python bench.py [--steps K] [--warmup W] [--workload batched1d|sisr2|sisr4] [--no-cpu]
+  python bench.py [--steps K] [--warmup W] [--workload batched1d|sisr2|sisr4|refiner|uneven] [--no-cpu]
+                  [--storage f32|f16] [--lanes 4]
 """
 import argparse
 import json
@@ -40,7 +41,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batched1d", choices=["batched1d", "sisr2", "sisr4", "refiner"])
+    ap.add_argument("--workload", default="batched1d", choices=["batched1d", "sisr2", "sisr4", "refiner", "uneven"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16"], help="uneven: storage of the packed buffers")
+    ap.add_argument("--lanes", type=int, default=4, help="uneven: concurrent lanes of the batch")
     ap.add_argument("--pairs", type=int, default=20000, help="refiner: training pairs")
     ap.add_argument("--epochs", type=int, default=3, help="refiner: training epochs")
     ap.add_argument("--batch", type=int, default=0, help="override the batch size (0 = workload default)")
@@ -237,6 +240,169 @@ def bench_sisr(args, torch, s):
     return result
 
 
+def scaled_deriv_tables(M, N):
+    """(i n / N)^m on the default band of M N coefficients."""
+    mu = M * N
+    n = np.arange(-((mu - 1) // 2), -((mu - 1) // 2) + mu)
+    return [(1j * n / N) ** m for m in range(M)]
+
+
+def bench_uneven(args, torch):
+    """The mixed workload: 4096 instances (3584 1-D signals of 17 lengths x 3 channel counts,
+    512 images of 9 sizes) in one uneven batch, captured as one graph."""
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_1802_10291_amd import Batch, Plan1D, Plan2D
+    from synth import uneven as U
+
+    f16 = args.storage == "f16"
+    np_dt = np.float16 if f16 else np.float32
+    esz = 2 if f16 else 4
+    storage = "f16" if f16 else "native"
+    items = U.instances()
+    cls = U.classes(items)
+    keys = list(cls)
+    log(f"{len(items)} instances in {len(keys)} size classes; storage {storage}")
+    plans, pools = {}, {}
+    pool_n = 4
+
+    def make_pool(ci):
+        k = keys[ci]
+        pools[k] = U.class_pool(k, ci, min(pool_n, len(cls[k])), dtype=np_dt, scaled=f16)
+
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        list(ex.map(make_pool, range(len(keys))))
+    for k in keys:
+        if k[0] == "1d":
+            _, L, M = k
+            N = -(-L // M)
+            chans = [("table", t) for t in scaled_deriv_tables(M, N)] if f16 else [("deriv", m) for m in range(M)]
+            plans[k] = Plan1D(N=N, n_out=4 * L, channels=chans, storage=storage)
+        else:
+            plans[k] = Plan2D(k[1] // 2, k[1] // 2, 2, storage=storage)
+    # autotune every class at its own instance count (cache: $MCI_TUNE_CACHE if set)
+    cache = os.environ.get("MCI_TUNE_CACHE") or os.path.join("/tmp", f"mci_tune_{os.getpid()}.json")
+    t0 = time.perf_counter()
+    tuned = {k: plans[k].autotune(len(cls[k]), cache) for k in keys}
+    log(f"autotuned {len(keys)} classes in {time.perf_counter() - t0:.1f} s")
+    batch = Batch([plans[it.key()] for it in items], lanes=args.lanes)
+    packed = np.zeros(batch.in_elems, dtype=np_dt)
+    pos = {i: j for k in keys for j, i in enumerate(cls[k])}    # instance -> position in its class
+    for i, (it, off) in enumerate(zip(items, batch.in_offsets)):
+        k = it.key()
+        x = pools[k][pos[i] % len(pools[k])].ravel()             # the class's first instance is pool entry 0
+        packed[off:off + x.size] = x
+    dev_in = torch.from_numpy(packed).cuda()
+    dev_out = torch.zeros(batch.out_elems, dtype=dev_in.dtype, device="cuda")
+    stream = torch.cuda.current_stream()
+    in_bytes = sum(plans[it.key()].instance_sizes()[0] for it in items) * esz
+    out_elems = sum(plans[it.key()].instance_sizes()[1] for it in items)
+    alg_bytes = in_bytes + out_elems * esz
+    log(f"packed input {batch.in_elems * esz / 2**30:.2f} GiB, output {batch.out_elems * esz / 2**30:.2f} GiB, "
+        f"workspace {batch.ws_bytes / 2**30:.2f} GiB")
+
+    def eager():
+        batch.run(dev_in, dev_out)
+
+    # eager timing, then one graph holding the whole batch
+    _, per_eager = time_steps(torch, eager, max(3, args.steps // 2), args.warmup, stream)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        eager()
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        eager()
+    wall, per = time_steps(torch, graph.replay, args.steps, args.warmup, stream)
+    ms = float(np.mean(per))
+    value = out_elems * args.steps / (sum(per) * 1e-3)
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    host_out = dev_out.cpu().numpy()
+
+    # per class: time alone (dense batch of its instance count), bytes, error vs the oracle
+    from oracle import oracle as O
+    rows = []
+    first_out = {}
+    for i, (it, off) in enumerate(zip(items, batch.out_offsets)):
+        if it.key() not in first_out:
+            first_out[it.key()] = (i, off)
+    per_class_err = {}
+
+    def class_err(k):
+        _, off = first_out[k]
+        x = pools[k][0].astype(np.float64)
+        n_o = plans[k].instance_sizes()[1]
+        got = host_out[off:off + n_o].astype(np.float64)
+        if k[0] == "2d":
+            want = O.upsample_2d(x[None], 2)[0].ravel()
+            return k, float(np.linalg.norm(got - want) / np.linalg.norm(want)), "full"
+        _, L, M = k
+        N = -(-L // M)
+        if f16:
+            ch = O.Channels(N=N, kinds=[O.MULT_TABLE] * M, orders=[0] * M, tables=np.stack(scaled_deriv_tables(M, N)))
+        else:
+            ch = O.Channels(N=N, kinds=[O.MULT_DERIV] * M, orders=list(range(M)))
+        if L <= 4096:
+            want = O.reconstruct_1d(ch, x[None], 4 * L)[0, 0]
+            return k, float(np.linalg.norm(got - want) / np.linalg.norm(want)), "full"
+        band = O.recover_band(ch, x[None])[0]
+        idx = np.random.default_rng(L + M).choice(4 * L, 32, replace=False)
+        want = O.evaluate_band(band, ch.n1, 2 * np.pi * idx / (4 * L))
+        return k, float(np.linalg.norm(got[idx] - want) / np.linalg.norm(want)), "32 sampled points"
+
+    cpu = None
+    if not args.no_cpu:
+        # CPU baseline: the oracle in full on the first instance of each small class, timed serially
+        small = [k for k in keys if (k[0] == "1d" and k[1] <= 4096) or (k[0] == "2d" and k[1] <= 256)]
+        t0 = time.perf_counter()
+        for k in small:
+            per_class_err[k] = class_err(k)[1:]
+        dt = time.perf_counter() - t0
+        n_s = sum(plans[k].instance_sizes()[1] for k in small)
+        cpu = {"value": n_s / dt, "unit": "samples/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"one instance of each of the {len(small)} classes with L <= 4096 or side <= 256, "
+                         f"every output; {dt:.1f} s"}
+        log(f"oracle on the large classes (sampled 1-D points, full 2-D images)")
+        with ThreadPoolExecutor(max_workers=4) as ex:
+            for k, e, how in ex.map(class_err, [k for k in keys if k not in per_class_err]):
+                per_class_err[k] = (e, how)
+    for k in keys:
+        p = plans[k]
+        n = len(cls[k])
+        ni, no = p.instance_sizes()
+        x = torch.from_numpy(np.stack([pools[k][j % len(pools[k])] for j in range(n)])).cuda()
+        fn = (lambda: p.reconstruct(x)) if k[0] == "1d" else (lambda: p.upsample(x))
+        _, pc = time_steps(torch, fn, 5, 2, stream)
+        t = float(np.median(pc))
+        name = f"1d L={k[1]} M={k[2]}" if k[0] == "1d" else f"2d {k[1] // 2}->{k[1]}"
+        row = {"class": name, "instances": n, "variant": tuned[k][0], "ms": round(t, 4),
+               "GBps": round(n * (ni + no) * esz / (t * 1e-3) / 1e9, 1)}
+        if k in per_class_err:
+            row["rel_err"], row["check"] = per_class_err[k][0], per_class_err[k][1]
+        rows.append(row)
+    result = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"uneven batch, {'FP16' if f16 else 'FP32'} storage: {len(items)} instances "
+                               f"({sum(1 for i in items if i.kind == '1d')} 1-D with L in 256..65536, M in 2..4, "
+                               f"n_out = 4L; {sum(1 for i in items if i.kind == '2d')} 2-D x2 with sides 64..1024) "
+                               f"in one graph launch", "classes": len(keys), "lanes": args.lanes,
+                   "storage": storage},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "whole uneven-batch graph",
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "eager_ms_per_step": float(np.mean(per_eager)),
+        "max_rel_err": max((r.get("rel_err", 0.0) for r in rows), default=None),
+        "classes": rows,
+        "wall_s": wall,
+    }
+    if cpu:
+        result["cpu_baseline"] = cpu
+    return result
+
+
 def bench_refiner(args, torch):
     """Refiner workload: train on method-generated pairs, then time MCI alone and MCI + CNN on
     RGB 512 x 512 images upsampled x2 from 256 x 256, and report the PSNR gain."""
@@ -296,6 +462,8 @@ def main():
         res = bench_batched1d(args, torch)
     elif args.workload == "refiner":
         res = bench_refiner(args, torch)
+    elif args.workload == "uneven":
+        res = bench_uneven(args, torch)
     else:
         res = bench_sisr(args, torch, 2 if args.workload == "sisr2" else 4)
     print(json.dumps(res), flush=True)

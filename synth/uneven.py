@@ -8,6 +8,7 @@ output points, and the batched workload's spectrum model (e^{-0.01 |n|} CN(0,1) 
 white noise out to |n| = 2 L: not bandlimited); and 512 images with high-resolution side
 drawn from {64, 96, ..., 1024} (2^k and 3 2^k), field images decimated by 2 and upsampled
 back by 2 with M = 2 channels per axis.  The instance order is a seeded permutation.
+The FP16-storage variant measures derivatives in units of N (channels (i n / N)^m).
 
 Inputs are drawn per size class from a pool of distinct seeds (class c, pool entry k uses
 seed 4_000_000 + 1000 c + k for signals, 4_500_000 + 1000 c + k for images); the pool
@@ -69,13 +70,16 @@ def classes(items: List[Instance]) -> Dict[Tuple, List[int]]:
     return out
 
 
-def class_pool(key: Tuple, class_id: int, count: int, dtype=np.float32) -> np.ndarray:
+def class_pool(key: Tuple, class_id: int, count: int, dtype=np.float32, scaled: bool = False) -> np.ndarray:
     """`count` distinct inputs of one class: samples [count][M][N] or low-resolution
-    images [count][side / 2][side / 2], rounded once to dtype."""
+    images [count][side / 2][side / 2], rounded once to dtype.  scaled: derivative
+    channels (i n / N)^m instead of (i n)^m (the FP16-storage variant; unscaled high
+    derivatives leave FP16's range)."""
     if key[0] == "1d":
         _, L, M = key
         N = -(-L // M)
-        return smooth_noisy_batch(0, count, M, N, 2 * L, seed_base=4_000_000 + 1000 * class_id, dtype=dtype)
+        return smooth_noisy_batch(0, count, M, N, 2 * L, seed_base=4_000_000 + 1000 * class_id, dtype=dtype,
+                                  deriv_scale=float(N) if scaled else 1.0)
     side = key[1]
     hr = random_field_images(0, count, side, side, seed_base=4_500_000 + 1000 * class_id, dtype=np.float64)
     return decimate(hr, 2).astype(dtype)
