@@ -29,6 +29,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 FP32_VALU_PEAK_TFLOPS = 157.3   # vendor figure (packed FP32); 78.6 without packed instructions
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz: the FP32 vector peak without packed
+# FP32 instructions, which this build does not emit
+FP32_VALU_UNPACKED_TFLOPS = 78.6
+
+
+def mci1d_flops(M, N, n_out):
+    """Algorithmic flops of one real-mode 1-D reconstruction: M real-input DFTs of length N
+    (2.5 N log2 N each), the per-coefficient M-term apply (8 flops per complex multiply-add
+    over the M N band coefficients), and one real-output inverse DFT of length n_out."""
+    import math
+    return M * 2.5 * N * math.log2(N) + 8.0 * M * (M * N) + 2.5 * n_out * math.log2(n_out)
 METRIC = "reconstructed samples/s (1-D batch, 2-D ×2/×4) vs HBM roofline; rel err vs FP64"
 
 
@@ -161,12 +172,16 @@ def bench_batched1d(args, torch):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "mci1d fused" if info.path else "whole multi-pass step",
                      "algorithmic_bytes_per_launch": alg_bytes, "kernel_source_hash": khash},
+        "alu_algorithmic": {"achieved": B * mci1d_flops(M, N, n_out) / (ms * 1e-3) / 1e12,
+                            "peak": FP32_VALU_UNPACKED_TFLOPS, "unit": "TFLOP/s",
+                            "frac": B * mci1d_flops(M, N, n_out) / (ms * 1e-3) / 1e12 / FP32_VALU_UNPACKED_TFLOPS,
+                            "flops_per_signal": mci1d_flops(M, N, n_out)},
         "wall_s": wall,
     }
     # CPU oracle on a bounded sample of the same workload
     if not args.no_cpu:
         from oracle import oracle as O
-        ns = args.cpu_sample or 128
+        ns = args.cpu_sample or 512
         idx = np.linspace(0, B - 1, ns).astype(np.int64)
         g_s = g[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
         y_s = y[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
