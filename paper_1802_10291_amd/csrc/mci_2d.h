@@ -27,5 +27,7 @@ std::vector<std::complex<double>> line_windows(const std::vector<std::complex<do
                                                int SC);
 hipError_t run_line_pass(int N, int SC, bool cols, int store_in, int store_out, const LinePassArgs& a,
                          int64_t images, hipStream_t s);
+// set the dynamic-LDS limit of the pass's kernel where it exceeds 64 KB (once, at plan time)
+hipError_t prepare_line_pass(int N, int SC, bool cols, int store_in, int store_out);
 
 }  // namespace mci

@@ -46,6 +46,7 @@ __device__ __forceinline__ void dft_r(float2* u) {
   if constexpr (R == 2) dft2<S>(u[0], u[1]);
   else if constexpr (R == 4) dft4<S>(u[0], u[1], u[2], u[3]);
   else if constexpr (R == 8) dft8<S>(u);
+  else if constexpr (R == 12) dft12<S>(u);
   else {
     static_assert(R == 16, "radix");
     constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, h = 0.70710678118654752440f;
@@ -116,9 +117,16 @@ __device__ __forceinline__ void gfft_passes(float2* __restrict__ buf, int l, flo
 #pragma unroll
     for (int b = 0; b < BPT; ++b) {
       const int j = l + G * b;
-      const int pb = pad((j / NS) * NS * R + (j % NS));
+      const int base = (j / NS) * NS * R + (j % NS);
+      // for power-of-two NS and R, base % 16 + (r NS) % 16 < 16, so pad(base + r NS) =
+      // pad(base) + r NS + (r NS) / 16 (one address per butterfly); otherwise pad each
+      constexpr bool pow2 = (NS & (NS - 1)) == 0 && (R & (R - 1)) == 0;
+      const int pb = pad(base);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[pb + r * NS + (r * NS) / 16] = u[b][r];
+      for (int r = 0; r < R; ++r) {
+        if constexpr (pow2) buf[pb + r * NS + (r * NS) / 16] = u[b][r];
+        else buf[pad(base + r * NS)] = u[b][r];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -127,24 +135,36 @@ __device__ __forceinline__ void gfft_passes(float2* __restrict__ buf, int l, flo
   }
 }
 
-template <int L> struct Radices16;   // E = 16 elements per lane
-template <> struct Radices16<64> { using type = RList<16, 4>; };
-template <> struct Radices16<128> { using type = RList<16, 8>; };
-template <> struct Radices16<256> { using type = RList<16, 16>; };
+// Per line length: E elements per lane (G = L / E lanes per line pair) and the radices of
+// the Stockham passes, each dividing E.
+template <int L> struct LineFFT;
+template <> struct LineFFT<32> { static constexpr int E = 8; using type = RList<8, 4>; };
+template <> struct LineFFT<48> { static constexpr int E = 12; using type = RList<12, 4>; };
+template <> struct LineFFT<64> { static constexpr int E = 16; using type = RList<16, 4>; };
+template <> struct LineFFT<96> { static constexpr int E = 12; using type = RList<12, 4, 2>; };
+template <> struct LineFFT<128> { static constexpr int E = 16; using type = RList<16, 8>; };
+template <> struct LineFFT<192> { static constexpr int E = 12; using type = RList<12, 4, 4>; };
+template <> struct LineFFT<256> { static constexpr int E = 16; using type = RList<16, 16>; };
+template <> struct LineFFT<384> { static constexpr int E = 12; using type = RList<12, 4, 4, 2>; };
+template <> struct LineFFT<512> { static constexpr int E = 16; using type = RList<16, 8, 4>; };
 
 template <int L, int S>
-__device__ __forceinline__ void gfft(float2* buf, int l, float2 (&v)[16], const float2* tw) {
-  gfft_passes<L, L / 16, S, 1>(buf, l, v, tw, typename Radices16<L>::type{});
+__device__ __forceinline__ void gfft(float2* buf, int l, float2 (&v)[LineFFT<L>::E], const float2* tw) {
+  gfft_passes<L, L / LineFFT<L>::E, S, 1>(buf, l, v, tw, typename LineFFT<L>::type{});
 }
 
 // COLS: lines are the columns of x [B][N][W] (blockIdx.x = block of 32 columns, blockIdx.y =
 // image); output [B][SC N][W].  Rows: lines are the rows of x [lines][N], output [lines][SC N].
+template <int N> constexpr int line_threads() { return PAIRS * (N / LineFFT<N>::E); }
+// output row blocks that go through the LDS tile in the columns pass
+template <int N, int SC> constexpr int out_parts() { return SC * N > 1024 ? 4 : 2; }
+
 template <int N, int SC, bool COLS, typename TI, typename TO>
-__global__ __launch_bounds__(N) void k_line_pass(LinePassArgs a) {
-  constexpr int G = N / 16, E = 16, NT = N;
+__global__ __launch_bounds__(line_threads<N>()) void k_line_pass(LinePassArgs a) {
+  constexpr int E = LineFFT<N>::E, G = N / E, NT = line_threads<N>();
   extern __shared__ float2 sm2[];
   float* tile = (float*)sm2;                   // input [32][N + 1] floats
-  float* otile = (float*)sm2;                  // output half tile [SC N / 2][32 + 1] floats (columns)
+  float* otile = (float*)sm2;                  // output block [SC N / OP][32 + 1] floats (columns)
   const int tid = threadIdx.x;
   const int g = tid / G, l = tid % G;          // pair g = lines 2g, 2g + 1
   float2* buf = sm2 + g * padded(N);           // FFT scratch of pair g
@@ -223,57 +243,81 @@ __global__ __launch_bounds__(N) void k_line_pass(LinePassArgs a) {
       }
     }
   } else {
-    // columns: output rows SC q + r; two halves (q < N/2, q >= N/2) through an LDS tile
+    // columns: output rows SC q + r; OP blocks of q (element c of a lane is q = l + G c, so
+    // block p holds c in [p E / OP, (p + 1) E / OP)) through an LDS tile
     constexpr int OT = LINES + 1;
+    constexpr int OP = out_parts<N, SC>();
+    static_assert(E % OP == 0, "output blocks must split the elements per lane");
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
+    for (int part = 0; part < OP; ++part) {
       __syncthreads();
 #pragma unroll
-      for (int c = half * (E / 2); c < (half + 1) * (E / 2); ++c) {
+      for (int c = part * (E / OP); c < (part + 1) * (E / OP); ++c) {
         const int q = l + G * c;
 #pragma unroll
         for (int r = 0; r < SC; ++r) {
-          const int row = SC * q + r - half * (SC * N / 2);
+          const int row = SC * q + r - part * (SC * N / OP);
           otile[row * OT + 2 * g] = out[r][c].x;
           otile[row * OT + 2 * g + 1] = out[r][c].y;
         }
       }
       __syncthreads();
-      for (int e = tid; e < (SC * N / 2) * LINES; e += NT) {
+      for (int e = tid; e < (SC * N / OP) * LINES; e += NT) {
         const int row = e / LINES, c = e % LINES;
         const int64_t col = col0 + c;
         if (col < a.W)
-          st_as<float>(y, (img * (SC * N) + half * (SC * N / 2) + row) * (int64_t)a.W + col, otile[row * OT + c]);
+          st_as<float>(y, (img * (SC * N) + part * (SC * N / OP) + row) * (int64_t)a.W + col, otile[row * OT + c]);
       }
     }
   }
 }
 
-template <int N, int SC, bool COLS, typename TI, typename TO>
-static hipError_t launch(const LinePassArgs& a, int64_t images, hipStream_t s) {
+template <int N, int SC, bool COLS>
+static size_t lds_bytes() {
   const size_t tile = (size_t)LINES * (N + 1) * sizeof(float);
   const size_t scratch = (size_t)PAIRS * padded(N) * sizeof(float2);
-  const size_t otile = COLS ? (size_t)(SC * N / 2) * (LINES + 1) * sizeof(float) : 0;
-  const size_t lds = std::max(tile, std::max(scratch, otile));
+  const size_t otile = COLS ? (size_t)(SC * N / out_parts<N, SC>()) * (LINES + 1) * sizeof(float) : 0;
+  return std::max(tile, std::max(scratch, otile));
+}
+
+template <int N, int SC, bool COLS, typename TI, typename TO>
+static hipError_t launch(const LinePassArgs& a, int64_t images, hipStream_t s) {
   dim3 grid;
   if constexpr (COLS) grid = dim3((unsigned)((a.W + LINES - 1) / LINES), (unsigned)images);
   else grid = dim3((unsigned)((a.lines + LINES - 1) / LINES));
-  hipLaunchKernelGGL((k_line_pass<N, SC, COLS, TI, TO>), grid, dim3(N), lds, s, a);
+  const size_t lds = lds_bytes<N, SC, COLS>();
+  const dim3 block(line_threads<N>());
+  hipLaunchKernelGGL((k_line_pass<N, SC, COLS, TI, TO>), grid, block, lds, s, a);
   return hipGetLastError();
 }
 
+// raise the dynamic-LDS limit of a kernel that needs more than 64 KB (at plan time)
+template <int N, int SC, bool COLS, typename TI, typename TO>
+static hipError_t prepare(const LinePassArgs&, int64_t, hipStream_t) {
+  const size_t lds = lds_bytes<N, SC, COLS>();
+  if (lds <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute((const void*)k_line_pass<N, SC, COLS, TI, TO>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
+
 template <bool COLS, typename TI, typename TO>
-static hipError_t dispatch(int N, int SC, const LinePassArgs& a, int64_t images, hipStream_t s) {
-#define MCI_LP(NN, SS) \
-  if (N == NN && SC == SS) return launch<NN, SS, COLS, TI, TO>(a, images, s);
-  MCI_LP(64, 2) MCI_LP(64, 4) MCI_LP(128, 2) MCI_LP(128, 4) MCI_LP(256, 2) MCI_LP(256, 4)
+static hipError_t dispatch(int N, int SC, const LinePassArgs& a, int64_t images, hipStream_t s, bool prep) {
+#define MCI_LP(NN, SS)                                                                  \
+  if (N == NN && SC == SS)                                                              \
+    return prep ? prepare<NN, SS, COLS, TI, TO>(a, images, s) : launch<NN, SS, COLS, TI, TO>(a, images, s);
+  MCI_LP(32, 2) MCI_LP(32, 4) MCI_LP(48, 2) MCI_LP(48, 4) MCI_LP(64, 2) MCI_LP(64, 4) MCI_LP(96, 2) MCI_LP(96, 4)
+  MCI_LP(128, 2) MCI_LP(128, 4) MCI_LP(192, 2) MCI_LP(192, 4) MCI_LP(256, 2) MCI_LP(256, 4) MCI_LP(384, 2)
+  MCI_LP(384, 4) MCI_LP(512, 2) MCI_LP(512, 4)
 #undef MCI_LP
   return hipErrorInvalidValue;
 }
 
 }  // namespace l2d
 
-bool line_pass_supported(int N, int SC) { return (N == 64 || N == 128 || N == 256) && (SC == 2 || SC == 4); }
+bool line_pass_supported(int N, int SC) {
+  const bool n_ok = N == 32 || N == 48 || N == 64 || N == 96 || N == 128 || N == 192 || N == 256 || N == 384 || N == 512;
+  return n_ok && (SC == 2 || SC == 4);
+}
 
 // Polyphase windows of one axis from the FP64 apply table Tab[2][2][N] (identity output,
 // channels {x, Dx}, multipliers {1, i n}).  Returns H[SC][N] (FP64).
@@ -302,14 +346,23 @@ std::vector<std::complex<double>> line_windows(const std::vector<std::complex<do
   return H;
 }
 
+static hipError_t line_pass(int N, int SC, bool cols, int store_in, int store_out, const LinePassArgs& a,
+                            int64_t images, hipStream_t s, bool prep) {
+  if (cols) {
+    if (store_in == ST_F16) return l2d::dispatch<true, __half, float>(N, SC, a, images, s, prep);
+    return l2d::dispatch<true, float, float>(N, SC, a, images, s, prep);
+  }
+  if (store_out == ST_F16) return l2d::dispatch<false, float, __half>(N, SC, a, images, s, prep);
+  return l2d::dispatch<false, float, float>(N, SC, a, images, s, prep);
+}
+
 hipError_t run_line_pass(int N, int SC, bool cols, int store_in, int store_out, const LinePassArgs& a,
                          int64_t images, hipStream_t s) {
-  if (cols) {
-    if (store_in == ST_F16) return l2d::dispatch<true, __half, float>(N, SC, a, images, s);
-    return l2d::dispatch<true, float, float>(N, SC, a, images, s);
-  }
-  if (store_out == ST_F16) return l2d::dispatch<false, float, __half>(N, SC, a, images, s);
-  return l2d::dispatch<false, float, float>(N, SC, a, images, s);
+  return line_pass(N, SC, cols, store_in, store_out, a, images, s, false);
+}
+
+hipError_t prepare_line_pass(int N, int SC, bool cols, int store_in, int store_out) {
+  return line_pass(N, SC, cols, store_in, store_out, LinePassArgs{}, 0, nullptr, true);
 }
 
 }  // namespace mci

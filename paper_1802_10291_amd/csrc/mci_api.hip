@@ -536,6 +536,11 @@ mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out)
       p->lp_tw[axis] = upload<float2>(tw, e);
       if (!p->lp_tw[axis] || e != hipSuccess) { destroy_plan(p); return fail(MCI_E_DEVICE, "twiddle upload"); }
     }
+    if (prepare_line_pass(desc->h, desc->scale, true, p->store, ST_F32) != hipSuccess ||
+        prepare_line_pass(desc->w, desc->scale, false, ST_F32, p->store) != hipSuccess) {
+      destroy_plan(p);
+      return fail(MCI_E_DEVICE, "line-pass LDS attribute");
+    }
     p->lp_avail = true;
   }
   (void)plan_set_variant(p, p->lp_avail ? MCI_VARIANT_LINE_PASS : MCI_VARIANT_MULTIPASS_R8);

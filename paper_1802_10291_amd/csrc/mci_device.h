@@ -88,6 +88,36 @@ template <int S, typename C> __device__ __forceinline__ void dft8(C* v) {
   v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
 }
 
+// 3 points: X1,2 = a - (b + c)/2 +- S i (sqrt 3 / 2)(b - c)
+template <int S, typename C> __device__ __forceinline__ void dft3(C& a, C& b, C& c) {
+  using T = decltype(C::x);
+  const T h = (T)0.86602540378443864676372317075294;  // sqrt(3)/2
+  const C s = cadd(b, c);
+  const C m = cmake<C>(a.x - (T)0.5 * s.x, a.y - (T)0.5 * s.y);
+  const C d = cmul_si<S>(csub(b, c));
+  a = cadd(a, s);
+  b = cmake<C>(m.x + h * d.x, m.y + h * d.y);
+  c = cmake<C>(m.x - h * d.x, m.y - h * d.y);
+}
+
+// 12 = 3 x 4 by the prime-factor (Good-Thomas) mapping, no twiddles: input n = (4 n1 + 3 n2)
+// mod 12, output k = (4 k1 + 9 k2) mod 12, so that e^{2 pi i n k / 12} = w3^{n1 k1} w4^{n2 k2}.
+template <int S, typename C> __device__ __forceinline__ void dft12(C* v) {
+  C a[3][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1) a[n1][n2] = v[(4 * n1 + 3 * n2) % 12];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft3<S>(a[0][n2], a[1][n2], a[2][n2]);
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1) dft4<S>(a[k1][0], a[k1][1], a[k1][2], a[k1][3]);
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[(4 * k1 + 9 * k2) % 12] = a[k1][k2];
+}
+
 template <int R, int S, typename C>
 __device__ __forceinline__ void dft_odd(C* v, const C* __restrict__ tw, int64_t len) {
   C out[R];

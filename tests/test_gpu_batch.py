@@ -155,7 +155,7 @@ def test_autotune_2d_plan(torch_cuda, tmp_path):
 # (kind, args): 1-D (N, M, n_out) with single-pass and multi-pass classes, Bluestein and
 # smooth lengths; 2-D (side, scale) with line-pass and multi-pass classes
 MIX = [("1d", (1366, 3, 16384)), ("1d", (1000, 3, 16384)), ("1d", (86, 3, 1024)), ("1d", (64, 4, 1024)),
-       ("1d", (128, 2, 1024)), ("2d", (64, 2)), ("2d", (48, 2)), ("2d", (32, 2))]
+       ("1d", (128, 2, 1024)), ("2d", (64, 2)), ("2d", (48, 2)), ("2d", (40, 2))]   # 40: no line pass, multi-pass 2-D
 
 
 def _mixed_batch(torch, storage="native", lanes=4, seed=0, per_class=3):
