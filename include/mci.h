@@ -185,13 +185,19 @@ typedef enum {
   MCI_VARIANT_FUSED_T1 = 2,     /* 1-D single-pass kernel, output transforms one at a time */
   MCI_VARIANT_FUSED_T2 = 3,     /* 1-D single-pass kernel, both output transforms side by side */
   MCI_VARIANT_LINE_PASS = 4,    /* 2-D fused line passes (columns, then rows) */
-  MCI_NUM_VARIANTS = 5
+  MCI_VARIANT_TWO_PASS = 5,     /* multi-pass path with each transform of length A B (A, B in
+                                   {32, 48, 64, 96, 128, 192, 256, 384, 512}) in two LDS passes
+                                   (one for a single such length); other lengths radix-8 */
+  MCI_NUM_VARIANTS = 6
 } mci_variant;
 
 /* Bit v of *mask is set when variant v can run this plan.  1-D plans: MULTIPASS_R8/R4
- * always, FUSED_T1/T2 when the single-pass kernel covers the descriptor (and fits the LDS).
- * 2-D plans: MULTIPASS_R8 (rows then columns through the 1-D plans) always, LINE_PASS for
- * FP32 plans with h, w in {64, 128, 256} and scale in {2, 4}. */
+ * always, TWO_PASS for FP32 plans where a transform length factors as above (the Bluestein
+ * lengths of FP32 plans are chosen so), FUSED_T1/T2 when the single-pass kernel covers the
+ * descriptor (and fits the LDS).  New 1-D plans start on FUSED_T1, else TWO_PASS, else
+ * MULTIPASS_R8.  2-D plans: MULTIPASS_R8 (rows then columns through the 1-D plans) always,
+ * LINE_PASS for FP32 plans with h, w in {32, 48, 64, 96, 128, 192, 256, 384, 512} and scale
+ * in {2, 4} (the default when available). */
 mci_status mci_plan_variants(mci_plan_t plan, uint32_t* mask);
 
 /* Make variant v the one the plan runs.  MCI_E_UNSUPPORTED when bit v of the mask is clear.

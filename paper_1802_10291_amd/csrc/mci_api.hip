@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "mci_2d.h"
+#include "mci_fftlines.h"
 #include "mci_fused.h"
 #include "mci_host_util.h"
 #include "mci_internal.h"
@@ -76,7 +77,9 @@ static void free_side(FftSide& f) {
   if (f.tw) (void)hipFree(f.tw);
   if (f.chirp) (void)hipFree(f.chirp);
   if (f.bhat) (void)hipFree(f.bhat);
-  f.tw = f.chirp = f.bhat = nullptr;
+  if (f.twA) (void)hipFree(f.twA);
+  if (f.twB) (void)hipFree(f.twB);
+  f.tw = f.chirp = f.bhat = f.twA = f.twB = nullptr;
 }
 
 static mci_status build_side(FftSide& f, int64_t len, int sign, int prec) {
@@ -84,6 +87,11 @@ static mci_status build_side(FftSide& f, int64_t len, int sign, int prec) {
   f.sign = sign;
   f.blue = !factor_7smooth(len, f.radices);
   f.lexec = f.blue ? next_7smooth(2 * len - 1) : len;
+  if (f.blue && prec == MCI_F32) {
+    // a Bluestein length the one- or two-pass LDS transform takes (2^a 3^b, also 7-smooth)
+    const int64_t m = next_two_pass_length(2 * len - 1);
+    if (m > 0) f.lexec = m;
+  }
   factor_7smooth(f.lexec, f.radices8, 8);
   factor_7smooth(f.lexec, f.radices4, 4);
   f.radices = f.radices8;
@@ -93,6 +101,20 @@ static mci_status build_side(FftSide& f, int64_t len, int sign, int prec) {
   f.tw = prec == MCI_F64 ? upload<double2>(tw, e) : upload<float2>(tw, e);
   if (!f.tw) return fail(MCI_E_OUT_OF_MEMORY, "twiddle table");
   if (e != hipSuccess) return fail(MCI_E_DEVICE, "twiddle upload");
+  if (prec == MCI_F32 && two_pass_factors(f.lexec, f.fa, f.fb)) {
+    for (int which = 0; which < 2; ++which) {
+      const int n = which ? f.fb : f.fa;
+      if (n <= 1) continue;
+      std::vector<std::complex<double>> t(n);
+      for (int k = 0; k < n; ++k) t[k] = root_of_unity(k, n);
+      void* d = upload<float2>(t, e);
+      if (!d || e != hipSuccess) return fail(MCI_E_DEVICE, "line twiddle upload");
+      (which ? f.twB : f.twA) = d;
+    }
+    if ((e = prepare_two_pass(f.fa, f.fb)) != hipSuccess) return fail(MCI_E_DEVICE, "two-pass LDS attribute");
+  } else {
+    f.fa = f.fb = 0;
+  }
   if (!f.blue) return MCI_OK;
   // chirp c[k] = e^{sign i pi k^2 / len}; k^2 reduced modulo 2 len exactly
   std::vector<std::complex<double>> c(len), b(f.lexec, 0.0);
@@ -271,7 +293,9 @@ static mci_status build_plan(const mci_plan_desc* desc, int device, mci_plan_s**
   if ((st = build_side(p->inv, desc->n_out, +1, p->prec)) != MCI_OK) { destroy_plan(p); return st; }
   if ((st = fused_select(p->d, p->prec, p->store, p->tab, p->fused)) != MCI_OK) { destroy_plan(p); return st; }
   HIP_TRY(hipDeviceSynchronize());
-  (void)plan_set_variant(p, p->fused.kind ? MCI_VARIANT_FUSED_T1 : MCI_VARIANT_MULTIPASS_R8);
+  (void)plan_set_variant(p, p->fused.kind ? MCI_VARIANT_FUSED_T1
+                            : (plan_variant_mask(p) >> MCI_VARIANT_TWO_PASS & 1u) ? MCI_VARIANT_TWO_PASS
+                                                                                : MCI_VARIANT_MULTIPASS_R8);
   *out = p;
   return MCI_OK;
 }
@@ -392,6 +416,7 @@ uint32_t plan_variant_mask(const mci_plan_s* p) {
     return m;
   }
   m |= 1u << MCI_VARIANT_MULTIPASS_R4;
+  if (p->fwd.fa || p->inv.fa) m |= 1u << MCI_VARIANT_TWO_PASS;
   if (p->fused.kind) {
     m |= 1u << MCI_VARIANT_FUSED_T1;
     if (p->fused.n_ti == 2) m |= 1u << MCI_VARIANT_FUSED_T2;
@@ -412,6 +437,8 @@ mci_status plan_set_variant(mci_plan_s* p, int v) {
     const bool r4 = v == MCI_VARIANT_MULTIPASS_R4;
     p->fwd.radices = r4 ? p->fwd.radices4 : p->fwd.radices8;
     p->inv.radices = r4 ? p->inv.radices4 : p->inv.radices8;
+    p->fwd.two_pass = v == MCI_VARIANT_TWO_PASS && p->fwd.fa;
+    p->inv.two_pass = v == MCI_VARIANT_TWO_PASS && p->inv.fa;
   }
   p->variant = v;
   return MCI_OK;

@@ -1,0 +1,23 @@
+// mci_fftlines.h -- FP32 transforms of the multi-pass path in one or two LDS passes.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mci {
+
+// a line length of the register-staged line FFT: 32, 48, 64, 96, 128, 192, 256, 384, 512
+bool line_length_ok(int64_t n);
+// L = A B with A, B line lengths (most balanced), or A = 1 and B = L for a line length
+bool two_pass_factors(int64_t L, int& A, int& B);
+// smallest length >= n that two_pass_factors accepts, or -1
+int64_t next_two_pass_length(int64_t n);
+// raise the dynamic-LDS limit of the kernels of an A x B transform (plan time)
+hipError_t prepare_two_pass(int A, int B);
+// count transforms of length A B (contiguous, complex) from in to out with sign `sign`;
+// tmp (count A B complex) holds the pass-1 result; twA, twB, twL: e^{-2 pi i k / n} tables of
+// n = A, B, A B entries (twA unused when A = 1).  in may equal out; tmp must differ from both.
+hipError_t fft_two_pass(const float2* in, float2* out, float2* tmp, int64_t count, int A, int B, int sign,
+                        const float2* twA, const float2* twB, const float2* twL, hipStream_t s);
+
+}  // namespace mci

@@ -23,6 +23,12 @@ struct FftSide {
   std::vector<int> radices8;  // radix-8 passes first, then at most one 4 and one 2, then 3, 5, 7
   std::vector<int> radices4;  // radix-4 passes, at most one 2, then 3, 5, 7
   void* tw = nullptr;         // e^{-2 pi i k / lexec}, lexec entries, plan precision
+  // FP32 plans: lexec = fa fb for the one- or two-pass LDS transform (fa = 1: one pass),
+  // with line twiddles twA (fa entries) and twB (fb entries); two_pass selects it
+  int fa = 0, fb = 0;
+  void* twA = nullptr;
+  void* twB = nullptr;
+  bool two_pass = false;
   void* chirp = nullptr;      // Bluestein: e^{sign i pi k^2 / len}, len entries
   void* bhat = nullptr;       // Bluestein: forward DFT_P of the conjugate chirp, divided by P
 };

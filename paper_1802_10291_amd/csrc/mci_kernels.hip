@@ -9,8 +9,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "mci_device.h"
+#include "mci_fftlines.h"
 #include "mci_internal.h"
 
 namespace mci {
@@ -301,24 +303,32 @@ static hipError_t run_passes(cx<T>* buf[2], int& cur, int64_t count, int64_t len
   return hipSuccess;
 }
 
+// One direction of a transform over buf[cur]: radix passes, or (FP32, two_pass) the one- or
+// two-pass LDS transform, which leaves its result in buf[cur] with buf[1 - cur] as scratch.
+template <typename T>
+static hipError_t direction(const FftSide& f, int sign, cx<T>* buf[2], int& cur, int64_t count, hipStream_t s) {
+  const cx<T>* tw = (const cx<T>*)f.tw;
+  if constexpr (std::is_same<T, float>::value) {
+    if (f.two_pass)
+      return fft_two_pass(buf[cur], buf[cur], buf[1 - cur], count, f.fa, f.fb, sign, (const float2*)f.twA,
+                          (const float2*)f.twB, (const float2*)f.tw, s);
+  }
+  if (sign < 0) return run_passes<T, -1>(buf, cur, count, f.lexec, f.radices, tw, s);
+  return run_passes<T, +1>(buf, cur, count, f.lexec, f.radices, tw, s);
+}
+
 // A full DFT of one FftSide over buf[cur]; the input must already be loaded (and
 // pre-chirped and zero padded for Bluestein).  Leaves the result in buf[cur] (before the
 // Bluestein post-chirp, which the consumer applies).
 template <typename T>
 static hipError_t run_side(const FftSide& f, cx<T>* buf[2], int& cur, int64_t count, hipStream_t s) {
-  const cx<T>* tw = (const cx<T>*)f.tw;
   hipError_t e;
-  if (!f.blue) {
-    if (f.sign < 0) e = run_passes<T, -1>(buf, cur, count, f.lexec, f.radices, tw, s);
-    else e = run_passes<T, +1>(buf, cur, count, f.lexec, f.radices, tw, s);
-    return e;
-  }
-  e = run_passes<T, -1>(buf, cur, count, f.lexec, f.radices, tw, s);
-  if (e != hipSuccess) return e;
+  if (!f.blue) return direction<T>(f, f.sign, buf, cur, count, s);
+  if ((e = direction<T>(f, -1, buf, cur, count, s)) != hipSuccess) return e;
   hipLaunchKernelGGL((k_pointwise<T>), dim3(grid_for(count * f.lexec, 256)), dim3(256), 0, s, buf[cur], count,
                      f.lexec, (const cx<T>*)f.bhat);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  return run_passes<T, +1>(buf, cur, count, f.lexec, f.radices, tw, s);
+  return direction<T>(f, +1, buf, cur, count, s);
 }
 
 size_t generic_1d_workspace(const Generic1D& g, int prec, int64_t batch) {

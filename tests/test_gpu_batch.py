@@ -94,11 +94,28 @@ def test_multipass_radix_variants(torch_cuda, N):
     g = S.smooth_noisy_batch(50, 2, 3, N, 4 * N)
     want = oracle_1d(g, 3, N, 4 * 3 * N)
     plan = Plan1D(N=N, n_out=12 * N, channels=deriv_channels(3))
-    assert plan.variants() == ["multipass_r8", "multipass_r4"]
+    assert plan.variants() == ["multipass_r8", "multipass_r4", "two_pass"]
     for v in plan.variants():
         plan.set_variant(v)
         y = plan.reconstruct(torch_cuda.from_numpy(g).cuda()).cpu().numpy()
         assert max(rel(y[b], want[b]) for b in range(2)) <= 1e-5, v
+
+
+@pytest.mark.parametrize("N,n_out,M", [(1024, 4096, 2), (1536, 6144, 2), (96, 1152, 3), (86, 1032, 3),
+                                       (4096, 65536, 4), (683, 8192, 3)])
+def test_two_pass_transforms_match_oracle(torch_cuda, N, n_out, M):
+    """Multi-pass path with its transforms in one or two LDS passes (four-step): lengths that
+    factor into line lengths directly (1024 = 32 x 32, 6144 = 96 x 64, 65536 = 256 x 256),
+    single-pass lines (96), Bluestein lengths chosen to factor (86 -> 192, 683 -> 1536), and
+    a side left on radix passes (1152)."""
+    from paper_1802_10291_amd import Plan1D
+    g = S.smooth_noisy_batch(60, 3, M, N, 2 * M * N)
+    want = oracle_1d(g, M, N, n_out)
+    plan = Plan1D(N=N, n_out=n_out, channels=deriv_channels(M))
+    assert plan.variant == "two_pass"
+    y = plan.reconstruct(torch_cuda.from_numpy(g).cuda()).cpu().numpy()
+    for b in range(3):
+        assert rel(y[b], want[b]) <= 1e-5, b
 
 
 def test_2d_variants_match_oracle(torch_cuda):
