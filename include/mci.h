@@ -188,14 +188,19 @@ typedef enum {
   MCI_VARIANT_TWO_PASS = 5,     /* multi-pass path with each transform of length A B (A, B in
                                    {32, 48, 64, 96, 128, 192, 256, 384, 512}) in two LDS passes
                                    (one for a single such length); other lengths radix-8 */
-  MCI_NUM_VARIANTS = 6
+  MCI_VARIANT_REAL_TWO_PASS = 6, /* real mode, FP32 storage, even N and n_out with n_out/2 as
+                                   above: channel DFTs of the sample rows read as N/2 complex
+                                   pairs, apply, real part and a 2-phase polyphase gather in one
+                                   kernel, one inverse transform of length n_out/2 written as
+                                   the output row */
+  MCI_NUM_VARIANTS = 7
 } mci_variant;
 
 /* Bit v of *mask is set when variant v can run this plan.  1-D plans: MULTIPASS_R8/R4
  * always, TWO_PASS for FP32 plans where a transform length factors as above (the Bluestein
  * lengths of FP32 plans are chosen so), FUSED_T1/T2 when the single-pass kernel covers the
- * descriptor (and fits the LDS).  New 1-D plans start on FUSED_T1, else TWO_PASS, else
- * MULTIPASS_R8.  2-D plans: MULTIPASS_R8 (rows then columns through the 1-D plans) always,
+ * descriptor (and fits the LDS), REAL_TWO_PASS as described above.  New 1-D plans start on
+ * FUSED_T1, else REAL_TWO_PASS, else TWO_PASS, else MULTIPASS_R8.  2-D plans: MULTIPASS_R8 (rows then columns through the 1-D plans) always,
  * LINE_PASS for FP32 plans with h, w in {32, 48, 64, 96, 128, 192, 256, 384, 512} and scale
  * in {2, 4} (the default when available). */
 mci_status mci_plan_variants(mci_plan_t plan, uint32_t* mask);

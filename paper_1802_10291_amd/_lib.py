@@ -53,9 +53,9 @@ class mci_plan2d_desc(ctypes.Structure):
 
 
 MCI_VARIANT_MULTIPASS_R8, MCI_VARIANT_MULTIPASS_R4, MCI_VARIANT_FUSED_T1, MCI_VARIANT_FUSED_T2, \
-    MCI_VARIANT_LINE_PASS, MCI_VARIANT_TWO_PASS = range(6)
-MCI_NUM_VARIANTS = 6
-VARIANT_NAMES = ["multipass_r8", "multipass_r4", "fused_t1", "fused_t2", "line_pass", "two_pass"]
+    MCI_VARIANT_LINE_PASS, MCI_VARIANT_TWO_PASS, MCI_VARIANT_REAL_TWO_PASS = range(7)
+MCI_NUM_VARIANTS = 7
+VARIANT_NAMES = ["multipass_r8", "multipass_r4", "fused_t1", "fused_t2", "line_pass", "two_pass", "real_two_pass"]
 
 
 class mci_tune_result(ctypes.Structure):

@@ -82,10 +82,10 @@ static void free_side(FftSide& f) {
   f.tw = f.chirp = f.bhat = f.twA = f.twB = nullptr;
 }
 
-static mci_status build_side(FftSide& f, int64_t len, int sign, int prec) {
+static mci_status build_side(FftSide& f, int64_t len, int sign, int prec, bool force_blue = false) {
   f.len = len;
   f.sign = sign;
-  f.blue = !factor_7smooth(len, f.radices);
+  f.blue = !factor_7smooth(len, f.radices) || force_blue;
   f.lexec = f.blue ? next_7smooth(2 * len - 1) : len;
   if (f.blue && prec == MCI_F32) {
     // a Bluestein length the one- or two-pass LDS transform takes (2^a 3^b, also 7-smooth)
@@ -175,6 +175,10 @@ static void destroy_plan(mci_plan_s* p) {
   if (p->tab) (void)hipFree(p->tab);
   free_side(p->fwd);
   free_side(p->inv);
+  free_side(p->rfwd);
+  free_side(p->rinv);
+  if (p->r_wN) (void)hipFree(p->r_wN);
+  if (p->r_Wo) (void)hipFree(p->r_Wo);
   fused_release(p->fused);
   destroy_plan(p->rows);
   destroy_plan(p->cols);
@@ -194,6 +198,42 @@ struct DevBufs {
     return e == hipSuccess ? p : nullptr;
   }
 };
+
+// Tables of the real-mode multi-kernel path, when the plan qualifies (FP32 storage and
+// arithmetic, real mode, even N and n_out, n_out / 2 a one- or two-pass length).
+static mci_status build_real_path(mci_plan_s* p) {
+  const mci_plan_desc& d = p->d;
+  int fa, fb;
+  if (p->prec != MCI_F32 || p->store != ST_F32 || !d.real_io || d.N % 2 || d.n_out % 2 ||
+      !two_pass_factors(d.n_out / 2, fa, fb))
+    return MCI_OK;
+  const int64_t N = d.N, H = N / 2, P = d.n_out / 2, mu = p->mu;
+  mci_status st;
+  if ((st = build_side(p->rfwd, H, -1, MCI_F32)) != MCI_OK) return st;
+  if (!p->rfwd.fa) {   // H neither factors nor needs Bluestein: take Bluestein at a length that factors
+    free_side(p->rfwd);
+    p->rfwd = FftSide();
+    if ((st = build_side(p->rfwd, H, -1, MCI_F32, true)) != MCI_OK) return st;
+  }
+  if ((st = build_side(p->rinv, P, +1, MCI_F32)) != MCI_OK) return st;
+  if (!p->rfwd.fa || !p->rinv.fa || p->rinv.blue) return MCI_OK;
+  const int64_t K = std::max<int64_t>(std::llabs(d.n1), std::llabs(d.n1 + mu - 1));
+  std::vector<std::complex<double>> wN(H), Wo(2 * K + 1);
+  for (int64_t k = 0; k < H; ++k) wN[k] = root_of_unity(k, N);
+  for (int64_t k = -K; k <= K; ++k)
+    Wo[k + K] = 1.0 + std::complex<double>(0.0, 1.0) * std::conj(root_of_unity(k, d.n_out));
+  hipError_t e;
+  p->r_wN = upload<float2>(wN, e);
+  if (!p->r_wN || e != hipSuccess) return fail(MCI_E_DEVICE, "real-path table upload");
+  p->r_Wo = upload<float2>(Wo, e);
+  if (!p->r_Wo || e != hipSuccess) return fail(MCI_E_DEVICE, "real-path table upload");
+  RealPath& r = p->real;
+  r.M = d.M; r.n_ops = d.n_ops; r.N = N; r.H = H; r.n1 = d.n1; r.n_out = d.n_out; r.P = P; r.K = K;
+  r.fwd = &p->rfwd; r.inv = &p->rinv;
+  r.tab = (const float2*)p->tab; r.wN = (const float2*)p->r_wN; r.Wo = (const float2*)p->r_Wo;
+  r.ok = true;
+  return MCI_OK;
+}
 
 static mci_status build_plan(const mci_plan_desc* desc, int device, mci_plan_s** out) {
   mci_status st = validate(desc);
@@ -292,10 +332,15 @@ static mci_status build_plan(const mci_plan_desc* desc, int device, mci_plan_s**
   if ((st = build_side(p->fwd, N, -1, p->prec)) != MCI_OK) { destroy_plan(p); return st; }
   if ((st = build_side(p->inv, desc->n_out, +1, p->prec)) != MCI_OK) { destroy_plan(p); return st; }
   if ((st = fused_select(p->d, p->prec, p->store, p->tab, p->fused)) != MCI_OK) { destroy_plan(p); return st; }
+  if ((st = build_real_path(p)) != MCI_OK) { destroy_plan(p); return st; }
   HIP_TRY(hipDeviceSynchronize());
-  (void)plan_set_variant(p, p->fused.kind ? MCI_VARIANT_FUSED_T1
-                            : (plan_variant_mask(p) >> MCI_VARIANT_TWO_PASS & 1u) ? MCI_VARIANT_TWO_PASS
-                                                                                : MCI_VARIANT_MULTIPASS_R8);
+  {
+    const uint32_t m = plan_variant_mask(p);
+    (void)plan_set_variant(p, p->fused.kind                               ? MCI_VARIANT_FUSED_T1
+                              : (m >> MCI_VARIANT_REAL_TWO_PASS & 1u) ? MCI_VARIANT_REAL_TWO_PASS
+                              : (m >> MCI_VARIANT_TWO_PASS & 1u)      ? MCI_VARIANT_TWO_PASS
+                                                                        : MCI_VARIANT_MULTIPASS_R8);
+  }
   *out = p;
   return MCI_OK;
 }
@@ -319,6 +364,7 @@ static Generic1D generic_of(const mci_plan_s* p) {
 static size_t ws_1d(const mci_plan_s* p, int64_t batch) {
   if (batch <= 0) return 0;
   if (p->use_fused) return 0;
+  if (p->use_real) return real_path_workspace(p->real, batch);
   return generic_1d_workspace(generic_of(p), p->prec, batch);
 }
 
@@ -404,6 +450,7 @@ mci_status plan_run(const mci_plan_s* p, const void* in, void* out, int64_t batc
   if (p->dims == 2) return run_2d(p, in, out, batch, ws, offs, s);
   hipError_t e;
   if (p->use_fused) e = fused_run(p->fused, in, out, batch, offs, s);
+  else if (p->use_real) e = run_real_1d(p->real, in, out, batch, ws, offs, s);
   else e = run_generic_1d(generic_of(p), p->prec, p->store, in, out, batch, ws, offs, s);
   if (e != hipSuccess) return fail(MCI_E_DEVICE, std::string("reconstruct: ") + hipGetErrorString(e));
   return MCI_OK;
@@ -417,6 +464,7 @@ uint32_t plan_variant_mask(const mci_plan_s* p) {
   }
   m |= 1u << MCI_VARIANT_MULTIPASS_R4;
   if (p->fwd.fa || p->inv.fa) m |= 1u << MCI_VARIANT_TWO_PASS;
+  if (p->real.ok) m |= 1u << MCI_VARIANT_REAL_TWO_PASS;
   if (p->fused.kind) {
     m |= 1u << MCI_VARIANT_FUSED_T1;
     if (p->fused.n_ti == 2) m |= 1u << MCI_VARIANT_FUSED_T2;
@@ -429,11 +477,16 @@ mci_status plan_set_variant(mci_plan_s* p, int v) {
     return fail(MCI_E_UNSUPPORTED, "variant " + std::to_string(v) + " is not available for this plan");
   if (p->dims == 2) {
     p->lp = v == MCI_VARIANT_LINE_PASS;
+  } else if (v == MCI_VARIANT_REAL_TWO_PASS) {
+    p->use_fused = false;
+    p->use_real = true;
   } else if (v == MCI_VARIANT_FUSED_T1 || v == MCI_VARIANT_FUSED_T2) {
     p->use_fused = true;
+    p->use_real = false;
     fused_set_ti(p->fused, v == MCI_VARIANT_FUSED_T2 ? 2 : 1);
   } else {
     p->use_fused = false;
+    p->use_real = false;
     const bool r4 = v == MCI_VARIANT_MULTIPASS_R4;
     p->fwd.radices = r4 ? p->fwd.radices4 : p->fwd.radices8;
     p->inv.radices = r4 ? p->inv.radices4 : p->inv.radices8;

@@ -14,6 +14,30 @@ bool two_pass_factors(int64_t L, int& A, int& B);
 int64_t next_two_pass_length(int64_t n);
 // raise the dynamic-LDS limit of the kernels of an A x B transform (plan time)
 hipError_t prepare_two_pass(int A, int B);
+// A general one- or two-pass transform: count transforms of length A B (A = 1: one pass of
+// length B).  Transform t reads from in + base_in(t) and writes to out + base_out(t), where
+// base = offs ? offs[2 (t / per) + side] / 2 + (t % per) tr : (t / per) sig + (t % per) tr, in
+// complex elements (offs: per-instance element offsets of real data, side 0 input / 1 output).
+// pre (optional): input position p < len_in is multiplied by pre[p], positions >= len_in
+// read as zero (chirp and zero padding).  post (optional): output position k is multiplied
+// by post[k].  tmp holds count A B complex (two passes only).
+struct LineXform {
+  const float2* in = nullptr;
+  float2* out = nullptr;
+  float2* tmp = nullptr;
+  int64_t count = 0;
+  int A = 1, B = 0, sign = -1;
+  const float2 *twA = nullptr, *twB = nullptr, *twL = nullptr;
+  const int64_t* in_offs = nullptr;
+  int64_t in_per = 1, in_sig = 0, in_tr = 0;
+  const int64_t* out_offs = nullptr;
+  int64_t out_per = 1, out_sig = 0, out_tr = 0;
+  const float2* pre = nullptr;
+  int64_t len_in = 0;
+  const float2* post = nullptr;
+};
+hipError_t fft_lines(const LineXform& x, hipStream_t s);
+
 // count transforms of length A B (contiguous, complex) from in to out with sign `sign`;
 // tmp (count A B complex) holds the pass-1 result; twA, twB, twL: e^{-2 pi i k / n} tables of
 // n = A, B, A B entries (twA unused when A = 1).  in may equal out; tmp must differ from both.

@@ -27,20 +27,38 @@ constexpr int FL = 16;   // lines per workgroup
 
 template <int N> constexpr int threads() { return FL * (N / LineFFT<N>::E); }
 
+// Where transform t of a side (input or output) starts, in complex elements: with a table,
+// offs[2 (t / per) + side] / 2 + (t % per) tr (offs in real elements, even); else
+// (t / per) sig + (t % per) tr.
+struct Side {
+  const int64_t* offs = nullptr;
+  int side = 0;        // 0: input offsets, 1: output offsets
+  int64_t per = 1, sig = 0, tr = 0;
+  __device__ __forceinline__ int64_t base(int64_t t) const {
+    const int64_t q = t / per, r = t - q * per;
+    return offs ? offs[2 * q + side] / 2 + r * tr : q * sig + r * tr;
+  }
+};
+
 struct LinesArgs {
   const float2* in;
   float2* out;
   int64_t n_lines;          // count * U
   int64_t U;                // lines per transform
-  int64_t sig_in, u_in, e_in;     // complex strides: transform, line, element
-  int64_t sig_out, u_out, e_out;
+  Side si, so;              // transform bases
+  int64_t u_in, e_in;       // complex strides of a line and of its elements (input)
+  int64_t u_out, e_out;     // (output)
   const float2* tw;         // N entries e^{-2 pi i k / N}
   const float2* twL;        // L entries e^{-2 pi i m / L} (pass 1 of two), or null
+  const float2* pre;        // input position p: p < len_in ? in * pre[p] : 0 (if pre), else in
+  int64_t len_in;           // with pre: input positions at or beyond it read as zero
+  const float2* post;       // output position k multiplied by post[k], or null
 };
 
 // IN_T / OUT_T: the 16 lines of the workgroup are interleaved (line stride 1, element stride
 // e); they then share one transform and U is a multiple of 16.  Otherwise lines are rows
-// (element stride 1).
+// (element stride 1).  Positions inside a transform: input u u_in + n e_in, output
+// u u_out + k e_out.
 template <int N, int S, bool IN_T, bool OUT_T>
 __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
   constexpr int E = LineFFT<N>::E, G = N / E, NT = threads<N>();
@@ -50,11 +68,15 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
   const int g = tid / G, l = tid % G;
   const int64_t t0 = (int64_t)blockIdx.x * FL;
   if constexpr (IN_T) {
-    const int64_t sig = t0 / a.U, u0 = t0 - sig * a.U;
-    const float2* base = a.in + sig * a.sig_in + u0;
+    const int64_t tr = t0 / a.U, u0 = t0 - tr * a.U;
+    const float2* base = a.in + a.si.base(tr);
     for (int e = tid; e < N * FL; e += NT) {
       const int n = e / FL, c = e % FL;
-      sml[c * TS + n] = base[c + n * a.e_in];
+      const int64_t p = u0 + c + n * a.e_in;
+      float2 v = make_float2(0.f, 0.f);
+      if (!a.pre) v = base[p];
+      else if (p < a.len_in) v = cmul(base[p], a.pre[p]);
+      sml[c * TS + n] = v;
     }
   } else {
     for (int e = tid; e < N * FL; e += NT) {
@@ -62,8 +84,11 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
       const int64_t t = t0 + c;
       float2 v = make_float2(0.f, 0.f);
       if (t < a.n_lines) {
-        const int64_t sig = t / a.U, u = t - sig * a.U;
-        v = a.in[sig * a.sig_in + u * a.u_in + n];
+        const int64_t tr = t / a.U, u = t - tr * a.U;
+        const int64_t p = u * a.u_in + n;
+        const float2* base = a.in + a.si.base(tr);
+        if (!a.pre) v = base[p];
+        else if (p < a.len_in) v = cmul(base[p], a.pre[p]);
       }
       sml[c * TS + n] = v;
     }
@@ -75,7 +100,7 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
   // the tile and the scratch share LDS: the line FFT's first store waits on a barrier
   gfft<N, S>(sml + g * padded(N), l, v, a.tw);
   const int64_t t = t0 + g;
-  const int64_t sig = t / a.U, u = t - sig * a.U;
+  const int64_t tr = t / a.U, u = t - tr * a.U;
   if (a.twL) {
 #pragma unroll
     for (int c = 0; c < E; ++c) {
@@ -90,17 +115,23 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
 #pragma unroll
     for (int c = 0; c < E; ++c) sml[(l + G * c) * OS + g] = v[c];
     __syncthreads();
-    const int64_t sig0 = t0 / a.U, u0 = t0 - sig0 * a.U;
-    float2* base = a.out + sig0 * a.sig_out + u0;
+    const int64_t tr0 = t0 / a.U, u0 = t0 - tr0 * a.U;
+    float2* base = a.out + a.so.base(tr0);
     for (int e = tid; e < N * FL; e += NT) {
       const int k = e / FL, c = e % FL;
-      base[c + k * a.e_out] = sml[k * OS + c];
+      const int64_t q = u0 + c + k * a.e_out;
+      float2 w = sml[k * OS + c];
+      if (a.post) w = cmul(w, a.post[q]);
+      base[q] = w;
     }
   } else {
     if (t < a.n_lines) {
-      float2* o = a.out + sig * a.sig_out + u * a.u_out;
+      float2* o = a.out + a.so.base(tr);
 #pragma unroll
-      for (int c = 0; c < E; ++c) o[l + G * c] = v[c];
+      for (int c = 0; c < E; ++c) {
+        const int64_t q = u * a.u_out + l + G * c;
+        o[q] = a.post ? cmul(v[c], a.post[q]) : v[c];
+      }
     }
   }
 }
@@ -194,19 +225,35 @@ hipError_t prepare_two_pass(int A, int B) {
   return e;
 }
 
-hipError_t fft_two_pass(const float2* in, float2* out, float2* tmp, int64_t count, int A, int B, int sign,
-                        const float2* twA, const float2* twB, const float2* twL, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
+hipError_t fft_lines(const LineXform& x, hipStream_t s) {
+  if (x.count <= 0) return hipSuccess;
+  const int A = x.A, B = x.B;
+  fl::Side si, so;
+  si.offs = x.in_offs; si.side = 0; si.per = x.in_per; si.sig = x.in_sig; si.tr = x.in_tr;
+  so.offs = x.out_offs; so.side = 1; so.per = x.out_per; so.sig = x.out_sig; so.tr = x.out_tr;
   if (A == 1) {
-    fl::LinesArgs a{in, out, count, 1, B, 0, 1, B, 0, 1, twB, nullptr};
-    return fl::run(B, sign, 0, a, s, false);
+    fl::LinesArgs a{x.in, x.out, x.count, 1, si, so, 0, 1, 0, 1, x.twB, nullptr, x.pre, x.len_in, x.post};
+    return fl::run(B, x.sign, 0, a, s, false);
   }
   const int64_t L = (int64_t)A * B;
-  fl::LinesArgs p1{in, tmp, count * A, A, L, 1, A, L, 1, A, twB, twL};
-  hipError_t e = fl::run(B, sign, 1, p1, s, false);
+  fl::Side dense;
+  dense.per = 1; dense.sig = L;
+  // pass 1: A lines x[a + A b] of length B, twiddled, to tmp[k_b A + a]
+  fl::LinesArgs p1{x.in, x.tmp, x.count * A, A, si, dense, 1, A, 1, A, x.twB, x.twL, x.pre, x.len_in, nullptr};
+  hipError_t e = fl::run(B, x.sign, 1, p1, s, false);
   if (e != hipSuccess) return e;
-  fl::LinesArgs p2{tmp, out, count * B, B, L, A, 1, L, 1, B, twA, nullptr};
-  return fl::run(A, sign, 2, p2, s, false);
+  // pass 2: B contiguous lines tmp[k_b A + a] of length A, to out[k_b + B k_a]
+  fl::LinesArgs p2{x.tmp, x.out, x.count * B, B, dense, so, A, 1, 1, B, x.twA, nullptr, nullptr, 0, x.post};
+  return fl::run(A, x.sign, 2, p2, s, false);
+}
+
+hipError_t fft_two_pass(const float2* in, float2* out, float2* tmp, int64_t count, int A, int B, int sign,
+                        const float2* twA, const float2* twB, const float2* twL, hipStream_t s) {
+  LineXform x;
+  x.in = in; x.out = out; x.tmp = tmp; x.count = count; x.A = A; x.B = B; x.sign = sign;
+  x.twA = twA; x.twB = twB; x.twL = twL;
+  x.in_sig = x.out_sig = (int64_t)A * B;
+  return fft_lines(x, s);
 }
 
 }  // namespace mci

@@ -9,6 +9,7 @@
 
 #include "mci_fused.h"
 #include "mci_internal.h"
+#include "mci_realpath.h"
 
 struct mci_plan_s {
   int dims = 1;  // 1: 1-D plan, 2: 2-D plan
@@ -23,6 +24,13 @@ struct mci_plan_s {
   int64_t n_sing = 0, first_sing = INT64_MIN;
   mci::FusedPlan fused;     // single-pass kernel choice (fused.kind == 0: none)
   bool use_fused = false;   // the fused kernel is the active variant
+  // real-mode multi-kernel path (FP32, real_io, even N and n_out): transforms of length N/2
+  // and n_out/2, and its tables
+  mci::FftSide rfwd, rinv;
+  void* r_wN = nullptr;
+  void* r_Wo = nullptr;
+  mci::RealPath real;
+  bool use_real = false;
   int variant = MCI_VARIANT_MULTIPASS_R8;
   std::vector<std::complex<double>> tab_host;   // FP64 apply table [n_ops][M][M][N]
   // 2-D fused line passes: windows H[SC][len] and twiddles per axis (cols, rows)

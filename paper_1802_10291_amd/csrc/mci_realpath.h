@@ -1,0 +1,25 @@
+// mci_realpath.h -- multi-kernel real-mode 1-D path for lengths no single workgroup holds.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mci_internal.h"
+
+namespace mci {
+
+struct RealPath {
+  bool ok = false;
+  int M = 0, n_ops = 0;
+  int64_t N = 0, H = 0, n1 = 0, n_out = 0, P = 0, K = 0;
+  const FftSide* fwd = nullptr;   // length H, sign -1 (Bluestein when H does not factor)
+  const FftSide* inv = nullptr;   // length P = n_out / 2, sign +1, one or two passes
+  const float2* tab = nullptr;    // [n_ops][M][M][N] FP32 apply table
+  const float2* wN = nullptr;     // H entries e^{-2 pi i k / N}
+  const float2* Wo = nullptr;     // 2K + 1 entries 1 + i e^{2 pi i k / n_out}, k = -K..K
+};
+
+size_t real_path_workspace(const RealPath& r, int64_t batch);
+// g: FP32 [batch][M][N] (or per-instance offsets), y: FP32 [batch][n_ops][n_out]
+hipError_t run_real_1d(const RealPath& r, const void* g, void* y, int64_t batch, void* ws, const int64_t* offs,
+                       hipStream_t s);
+
+}  // namespace mci

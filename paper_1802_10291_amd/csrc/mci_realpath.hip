@@ -1,0 +1,143 @@
+// mci_realpath.hip -- real-mode 1-D reconstruction in a few LDS-pass kernels, for lengths no
+// single workgroup holds.  The steps are those of the single-pass kernel, each a pass over HBM:
+//
+//  1. channel DFTs (Lemma 3.1): row m of the real samples, read as H = N/2 complex pairs
+//     z[p] = g[2p] + i g[2p+1], goes through a one- or two-pass transform of length H (through
+//     Bluestein's chirp convolution when H does not factor: the chirp is applied as the
+//     first pass loads, the filter spectrum as the second one stores);
+//  2. apply (eq. matrixeqn1) and the real part: X_m[r] = E[r'] + e^{-2 pi i r / N} O[r'],
+//     r' = r mod H, with E, O the even/odd-sample DFTs recovered from Z; a(k) = sum_m
+//     X_m[k mod N] Tab[m][j][i] for k = n1 + i + jN; S(k) = (a(k) + conj a(-k)) / 2;
+//  3. output: with P = n_out / 2 and w = e^{2 pi i / n_out}, the two polyphase components
+//     y[2q] and y[2q + 1] are the real and imaginary parts of
+//       z[q] = sum_b Zc[b] e^{2 pi i b q / P},  Zc[b] = sum_{k = b mod P} S(k) (1 + i w^k),
+//     so one complex inverse transform of length P yields the whole real output, and its
+//     complex result, stored as it is, is the output row.
+// A thread of step 2 owns the bins b and P - b, which receive S(k) and S(-k) = conj S(k).
+#include <hip/hip_runtime.h>
+
+#include "mci_device.h"
+#include "mci_fftlines.h"
+#include "mci_realpath.h"
+
+namespace mci {
+
+__device__ __forceinline__ float2 conj2(float2 a) { return make_float2(a.x, -a.y); }
+
+// a(k) of signal Zs for output op `op`; zero outside the band
+__device__ __forceinline__ float2 band_coeff(int64_t k, const float2* __restrict__ Zs, int64_t Lz,
+                                             const float2* __restrict__ post, const float2* __restrict__ wN,
+                                             const float2* __restrict__ tab, int op, int M, int64_t N, int64_t H,
+                                             int64_t n1) {
+  const int64_t d = k - n1;
+  float2 acc = make_float2(0.f, 0.f);
+  if (d < 0 || d >= (int64_t)M * N) return acc;
+  const int64_t j = d / N, i = d - j * N;
+  const int64_t r = ((k % N) + N) % N;
+  const int64_t rh = r < H ? r : r - H;
+  const int64_t rr = rh == 0 ? 0 : H - rh;
+  const float sg = r < H ? 1.f : -1.f;
+  const float2 w = wN[rh];
+  for (int m = 0; m < M; ++m) {
+    float2 z1 = Zs[m * Lz + rh], z2 = Zs[m * Lz + rr];
+    if (post) {
+      z1 = cmul(z1, post[rh]);
+      z2 = cmul(z2, post[rr]);
+    }
+    z2 = conj2(z2);
+    const float2 e = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
+    const float2 o = make_float2(0.5f * (z1.y - z2.y), -0.5f * (z1.x - z2.x));   // (z1 - z2) / (2i)
+    const float2 wo = cmul(w, o);
+    const float2 x = make_float2(e.x + sg * wo.x, e.y + sg * wo.y);
+    acc = cadd(acc, cmul(x, tab[(((int64_t)op * M + m) * M + j) * N + i]));
+  }
+  return acc;
+}
+
+__global__ void k_apply_real(const float2* __restrict__ Z, int64_t Lz, const float2* __restrict__ post,
+                             const float2* __restrict__ wN, const float2* __restrict__ tab,
+                             const float2* __restrict__ Wo, float2* __restrict__ Zc, int M, int n_ops, int64_t N,
+                             int64_t H, int64_t n1, int64_t K, int64_t P, int64_t batch) {
+  const int64_t half = P / 2 + 1;   // bin pairs {b, P - b}, b = 0 .. P/2
+  const int64_t total = batch * n_ops * half;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e % half, bo = e / half;
+    const int op = (int)(bo % n_ops);
+    const int64_t sig = bo / n_ops;
+    const float2* Zs = Z + sig * M * Lz;
+    const bool self = b == 0 || 2 * b == P;
+    float2 acc_b = make_float2(0.f, 0.f), acc_m = make_float2(0.f, 0.f);
+    for (int64_t k = b - ((b + K) / P) * P; k <= K; k += P) {   // k = b mod P, |k| <= K
+      const float2 ak = band_coeff(k, Zs, Lz, post, wN, tab, op, M, N, H, n1);
+      const float2 amk = conj2(band_coeff(-k, Zs, Lz, post, wN, tab, op, M, N, H, n1));
+      const float2 S = make_float2(0.5f * (ak.x + amk.x), 0.5f * (ak.y + amk.y));
+      acc_b = cadd(acc_b, cmul(S, Wo[k + K]));
+      if (!self) acc_m = cadd(acc_m, cmul(conj2(S), Wo[K - k]));
+    }
+    Zc[bo * P + b] = acc_b;
+    if (!self) Zc[bo * P + (P - b)] = acc_m;
+  }
+}
+
+static size_t al(size_t n) { return (n + 255) & ~(size_t)255; }
+
+size_t real_path_workspace(const RealPath& r, int64_t batch) {
+  if (batch <= 0) return 0;
+  const size_t nz = (size_t)batch * r.M * r.fwd->lexec * sizeof(float2);
+  const size_t nc = (size_t)batch * r.n_ops * r.P * sizeof(float2);
+  return 2 * al(nz) + 2 * al(nc) + 256;
+}
+
+hipError_t run_real_1d(const RealPath& r, const void* g, void* y, int64_t batch, void* ws, const int64_t* offs,
+                       hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const FftSide& f = *r.fwd;
+  const FftSide& v = *r.inv;
+  const int64_t Lz = f.lexec;
+  char* base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+  const size_t nz = al((size_t)batch * r.M * Lz * sizeof(float2));
+  const size_t nc = al((size_t)batch * r.n_ops * r.P * sizeof(float2));
+  float2* Zf = (float2*)base;
+  float2* T1 = (float2*)(base + nz);
+  float2* Zc = (float2*)(base + 2 * nz);
+  float2* T2 = (float2*)(base + 2 * nz + nc);
+  // 1. channel DFTs straight from the sample rows (row m of signal b: complex offset
+  //    (b M + m) H, or offs[2 b] / 2 + m H)
+  LineXform x;
+  x.in = (const float2*)g; x.out = Zf; x.tmp = T1; x.count = batch * r.M;
+  x.A = f.fa; x.B = f.fb; x.sign = -1;
+  x.twA = (const float2*)f.twA; x.twB = (const float2*)f.twB; x.twL = (const float2*)f.tw;
+  x.in_offs = offs; x.in_per = r.M; x.in_sig = r.M * r.H; x.in_tr = r.H;
+  x.out_sig = Lz;
+  if (f.blue) {
+    x.pre = (const float2*)f.chirp;
+    x.len_in = r.H;
+    x.post = (const float2*)f.bhat;
+  }
+  hipError_t e = fft_lines(x, s);
+  if (e != hipSuccess) return e;
+  if (f.blue) {
+    LineXform u;
+    u.in = Zf; u.out = Zf; u.tmp = T1; u.count = batch * r.M;
+    u.A = f.fa; u.B = f.fb; u.sign = +1;
+    u.twA = (const float2*)f.twA; u.twB = (const float2*)f.twB; u.twL = (const float2*)f.tw;
+    u.in_sig = u.out_sig = Lz;
+    if ((e = fft_lines(u, s)) != hipSuccess) return e;
+  }
+  // 2. apply, real part, polyphase gather
+  const int64_t total = batch * r.n_ops * (r.P / 2 + 1);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1 << 20));
+  hipLaunchKernelGGL(k_apply_real, dim3(grid), dim3(256), 0, s, Zf, Lz, f.blue ? (const float2*)f.chirp : nullptr,
+                     r.wN, r.tab, r.Wo, Zc, r.M, r.n_ops, r.N, r.H, r.n1, r.K, r.P, batch);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 3. one inverse transform of length P per (signal, op), written as the output row
+  LineXform o;
+  o.in = Zc; o.out = (float2*)y; o.tmp = T2; o.count = batch * r.n_ops;
+  o.A = v.fa; o.B = v.fb; o.sign = +1;
+  o.twA = (const float2*)v.twA; o.twB = (const float2*)v.twB; o.twL = (const float2*)v.tw;
+  o.in_sig = r.P;
+  o.out_offs = offs; o.out_per = r.n_ops; o.out_sig = r.n_ops * r.P; o.out_tr = r.P;
+  return fft_lines(o, s);
+}
+
+}  // namespace mci

@@ -112,10 +112,41 @@ def test_two_pass_transforms_match_oracle(torch_cuda, N, n_out, M):
     g = S.smooth_noisy_batch(60, 3, M, N, 2 * M * N)
     want = oracle_1d(g, M, N, n_out)
     plan = Plan1D(N=N, n_out=n_out, channels=deriv_channels(M))
-    assert plan.variant == "two_pass"
+    plan.set_variant("two_pass")
     y = plan.reconstruct(torch_cuda.from_numpy(g).cuda()).cpu().numpy()
     for b in range(3):
         assert rel(y[b], want[b]) <= 1e-5, b
+
+
+@pytest.mark.parametrize("N,n_out,M,n1", [(1024, 4096, 2, None), (1536, 6144, 2, None), (86, 1024, 3, None),
+                                          (4096, 65536, 4, None), (1366, 16384, 3, 100), (2048, 8192, 3, -5000),
+                                          (512, 2048, 2, None), (21846, 262144, 3, None)])
+def test_real_two_pass_matches_oracle(torch_cuda, N, n_out, M, n1):
+    """Real-mode multi-kernel path: rows read as N/2 complex pairs (one pass for 256 and 512,
+    two for 1024 and 2048, Bluestein for 43, 683 and 10923, Bluestein forced for 768, which
+    neither factors into line lengths nor needs it), a band not containing 0, a band far off
+    centre that folds several coefficients into each output bin, and the largest
+    mixed-workload length (64 sampled points)."""
+    from paper_1802_10291_amd import Plan1D
+    cnt = 2 if N > 8192 else 3
+    g = S.smooth_noisy_batch(70, cnt, M, N, 2 * M * N)
+    chans = deriv_channels(M)
+    plan = Plan1D(N=N, n_out=n_out, channels=chans, n1=n1)
+    if plan.info.path == 1:
+        plan.set_variant("real_two_pass")
+    assert plan.variant == "real_two_pass"
+    y = plan.reconstruct(torch_cuda.from_numpy(g).cuda()).cpu().numpy().astype(np.float64)
+    ch = O.Channels(N=N, kinds=[O.MULT_DERIV] * M, orders=list(range(M)), n1=n1)
+    if N > 8192:
+        band = O.recover_band(ch, g.astype(np.float64))
+        idx = np.random.default_rng(1).choice(n_out, 64, replace=False)
+        for b in range(cnt):
+            want = O.evaluate_band(band[b], ch.n1, 2 * np.pi * idx / n_out)
+            assert rel(y[b, 0, idx], want) <= 1e-5, b
+    else:
+        want = O.reconstruct_1d(ch, g.astype(np.float64), n_out)
+        for b in range(cnt):
+            assert rel(y[b], want[b]) <= 1e-5, b
 
 
 def test_2d_variants_match_oracle(torch_cuda):
