@@ -91,6 +91,7 @@ struct ConvArgs {
   const float* base;     // EPI_RESID: float [B][3][H][W] added to the result
   const bf16* mask;      // EPI_MASK: bf16 [B][H][W][32]; output *= (mask > 0)
   void* out;             // EPI_RELU / EPI_MASK: bf16 [B][H][W][32]; EPI_RESID: float [B][3][H][W]
+  float* rpart;          // EPI_RESID, optional: per-tile sums (residual^2, base^2), [B][tiles][2]
   int H, W;
 };
 
@@ -178,12 +179,34 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
     __syncthreads();
     float* out = (float*)a.out + (size_t)b * 3 * H * W;
     const float* base = a.base ? a.base + (size_t)b * 3 * H * W : nullptr;
+    float sr = 0.f, su = 0.f;   // this thread's share of ||residual||^2 and ||base||^2
     for (int e = tid; e < 3 * T * T; e += NT) {
       const int co = e / (T * T), r = (e / T) % T, c = e % T;
       const int y = ty0 + r, x = tx0 + c;
       if (y < H && x < W) {
         const size_t o = ((size_t)co * H + y) * W + x;
-        out[o] = tout[e] + (a.bias ? a.bias[co] : 0.f) + (base ? base[o] : 0.f);
+        const float res = tout[e] + (a.bias ? a.bias[co] : 0.f), u0 = base ? base[o] : 0.f;
+        sr += res * res;
+        su += u0 * u0;
+        out[o] = res + u0;
+      }
+    }
+    if (a.rpart) {
+      // per-tile partial sums for the residual ratio: wave sums, then the 4 waves in LDS
+      __shared__ float red[2][NT / 64];
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) {
+        sr += __shfl_xor(sr, d);
+        su += __shfl_xor(su, d);
+      }
+      if (lane == 0) { red[0][wave] = sr; red[1][wave] = su; }
+      __syncthreads();
+      if (tid == 0) {
+        float r2 = 0.f, u2 = 0.f;
+        for (int w = 0; w < NT / 64; ++w) { r2 += red[0][w]; u2 += red[1][w]; }
+        const size_t t = ((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        a.rpart[2 * t] = r2;
+        a.rpart[2 * t + 1] = u2;
       }
     }
   } else {
@@ -329,14 +352,24 @@ __global__ __launch_bounds__(NT) void k_wgrad(WgradArgs a) {
 }
 
 // sum the per-tile partials into the gradient slice (deterministic)
+// Sum the per-tile partials: a block covers 64 parameters, its 4 waves split the tiles
+// (each wave reads 64 consecutive parameters of a tile row: 256 contiguous bytes), and the
+// four wave sums are added in a fixed order.
 __global__ void k_reduce_parts(const float* __restrict__ part, int tiles, int n, float* __restrict__ grad_w,
                                float* __restrict__ grad_b, int nw) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int t = 0; t < tiles; ++t) s += part[(size_t)t * n + e];
-  if (e < nw) grad_w[e] = s;
-  else grad_b[e - nw] = s;
+  if (e < n)
+    for (int t = wave; t < tiles; t += 4) s += part[(size_t)t * n + e];
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && e < n) {
+    const float v = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    if (e < nw) grad_w[e] = v;
+    else grad_b[e - nw] = v;
+  }
 }
 
 // ---------------------------------------------------------------- loss, Adam, fallback
@@ -372,14 +405,14 @@ __global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __re
 }
 
 // per-image ratio ||r||_2 / ||u||_2 of the CNN residual r = y - u to the MCI image u
-__global__ void k_ratio(const float* __restrict__ y, const float* __restrict__ u, int64_t per_img, float* __restrict__ ratio) {
+// ratio[b] = ||residual_b|| / ||u_b|| from the last layer's per-tile partial sums
+__global__ void k_ratio(const float* __restrict__ rpart, int tiles, float* __restrict__ ratio) {
   __shared__ float rn[NT], un[NT];
   const int b = blockIdx.x;
   float sr = 0.f, su = 0.f;
-  for (int64_t e = threadIdx.x; e < per_img; e += NT) {
-    const float uu = u[b * per_img + e], rr = y[b * per_img + e] - uu;
-    sr += rr * rr;
-    su += uu * uu;
+  for (int t = threadIdx.x; t < tiles; t += NT) {
+    sr += rpart[2 * ((size_t)b * tiles + t)];
+    su += rpart[2 * ((size_t)b * tiles + t) + 1];
   }
   rn[threadIdx.x] = sr;
   un[threadIdx.x] = su;
@@ -473,7 +506,7 @@ static hipError_t conv(int inm, int cout, int epi, const ConvArgs& a, int64_t B,
 
 // forward through the four layers; out = u + CNN(u)
 static hipError_t ref_forward(mci_refiner_s* r, const float* u, float* out, int64_t B, int H, int W, const RefWs& ws,
-                              hipStream_t s) {
+                              hipStream_t s, float* rpart = nullptr) {
   hipError_t e;
   ConvArgs a{};
   a.H = H; a.W = W;
@@ -483,7 +516,7 @@ static hipError_t ref_forward(mci_refiner_s* r, const float* u, float* out, int6
   if ((e = conv(IN32, 32, EPI_RELU, a, B, s)) != hipSuccess) return e;
   a.in = ws.a2; a.w = r->w + OF3; a.bias = r->p + B3; a.out = ws.a3;
   if ((e = conv(IN32, 32, EPI_RELU, a, B, s)) != hipSuccess) return e;
-  a.in = ws.a3; a.w = r->w + OF4; a.bias = r->p + B4; a.base = u; a.out = out;
+  a.in = ws.a3; a.w = r->w + OF4; a.bias = r->p + B4; a.base = u; a.out = out; a.rpart = rpart;
   return conv(IN32, 16, EPI_RESID, a, B, s);
 }
 
@@ -498,7 +531,7 @@ static hipError_t wgrad(bool gin3, bool xin3, const void* g, const void* x, floa
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int tiles = (int)(B * grid.x * grid.y), n = nw + nb;
-  hipLaunchKernelGGL(k_reduce_parts, dim3((n + 255) / 256), dim3(256), 0, s, part, tiles, n, gw, gb, nw);
+  hipLaunchKernelGGL(k_reduce_parts, dim3((n + 63) / 64), dim3(256), 0, s, part, tiles, n, gw, gb, nw);
   return hipGetLastError();
 }
 
@@ -637,10 +670,12 @@ mci_status mci_refiner_forward(mci_refiner_t r, const float* u, float* y, int64_
   if (!workspace || ws_bytes < ws.bytes) return rfail(MCI_E_INVALID_ARG, "workspace too small");
   if (apply_fallback && (!ratio || !used)) return rfail(MCI_E_INVALID_ARG, "fallback needs ratio and used arrays");
   RHIP(hipSetDevice(r->device));
-  RHIP(ref_forward(r, u, y, batch, h, w, ws, stream));
+  // the weight-gradient partials buffer (unused by a forward call) takes the ratio's per-tile sums
+  RHIP(ref_forward(r, u, y, batch, h, w, ws, stream, ratio ? ws.part : nullptr));
   if (ratio) {
     const int64_t per = 3 * (int64_t)h * w;
-    hipLaunchKernelGGL(k_ratio, dim3((unsigned)batch), dim3(NT), 0, stream, y, u, per, ratio);
+    const int tiles = ((h + T - 1) / T) * ((w + T - 1) / T);
+    hipLaunchKernelGGL(k_ratio, dim3((unsigned)batch), dim3(NT), 0, stream, ws.part, tiles, ratio);
     RHIP(hipGetLastError());
     if (apply_fallback) {
       hipLaunchKernelGGL(k_fallback, dim3(64, (unsigned)batch), dim3(NT), 0, stream, y, u, per, ratio, r->tau, used);
