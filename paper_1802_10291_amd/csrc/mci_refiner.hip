@@ -352,24 +352,29 @@ __global__ __launch_bounds__(NT) void k_wgrad(WgradArgs a) {
 }
 
 // sum the per-tile partials into the gradient slice (deterministic)
-// Sum the per-tile partials: a block covers 64 parameters, its 4 waves split the tiles
-// (each wave reads 64 consecutive parameters of a tile row: 256 contiguous bytes), and the
-// four wave sums are added in a fixed order.
-__global__ void k_reduce_parts(const float* __restrict__ part, int tiles, int n, float* __restrict__ grad_w,
-                               float* __restrict__ grad_b, int nw) {
-  __shared__ float red[4][64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int e = blockIdx.x * 64 + lane;
+// Sum the per-tile partials in two deterministic stages: stage 1 gives RS slices of the tiles
+// (t = s, s + RS, ...) to separate threads, 64 consecutive parameters per wave (256 contiguous
+// bytes of a partials row); stage 2 adds the RS slice sums of a parameter in order.
+constexpr int RS = 32;
+
+__global__ void k_reduce_parts1(const float* __restrict__ part, int tiles, int n, float* __restrict__ part2) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sl = blockIdx.y;
+  if (e >= n) return;
   float s = 0.f;
-  if (e < n)
-    for (int t = wave; t < tiles; t += 4) s += part[(size_t)t * n + e];
-  red[wave][lane] = s;
-  __syncthreads();
-  if (wave == 0 && e < n) {
-    const float v = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-    if (e < nw) grad_w[e] = v;
-    else grad_b[e - nw] = v;
-  }
+  for (int t = sl; t < tiles; t += RS) s += part[(size_t)t * n + e];
+  part2[(size_t)sl * n + e] = s;
+}
+
+__global__ void k_reduce_parts2(const float* __restrict__ part2, int n, float* __restrict__ grad_w,
+                                float* __restrict__ grad_b, int nw) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float s = 0.f;
+#pragma unroll 8
+  for (int sl = 0; sl < RS; ++sl) s += part2[(size_t)sl * n + e];
+  if (e < nw) grad_w[e] = s;
+  else grad_b[e - nw] = s;
 }
 
 // ---------------------------------------------------------------- loss, Adam, fallback
@@ -468,7 +473,7 @@ static size_t al256(size_t n) { return (n + 255) & ~(size_t)255; }
 // workspace layout for a batch of B images of H x W
 struct RefWs {
   bf16 *a1, *a2, *a3, *d0, *d1;
-  float *out, *dr, *part, *lpart;
+  float *out, *dr, *part, *part2, *lpart;
   size_t bytes;
 };
 static RefWs ref_ws(void* base, int64_t B, int H, int W) {
@@ -488,6 +493,7 @@ static RefWs ref_ws(void* base, int64_t B, int H, int W) {
   w.out = (float*)q; q += img;
   w.dr = (float*)q; q += img;
   w.part = (float*)q; q += part;
+  w.part2 = (float*)q; q += al256((size_t)RS * (32 * 9 * 32 + 32) * sizeof(float));
   w.lpart = (float*)q; q += lp;
   w.bytes = (size_t)(q - (char*)base) + 256;
   return w;
@@ -520,8 +526,8 @@ static hipError_t ref_forward(mci_refiner_s* r, const float* u, float* out, int6
   return conv(IN32, 16, EPI_RESID, a, B, s);
 }
 
-static hipError_t wgrad(bool gin3, bool xin3, const void* g, const void* x, float* part, float* gw, float* gb, int nw,
-                        int nb, int64_t B, int H, int W, hipStream_t s) {
+static hipError_t wgrad(bool gin3, bool xin3, const void* g, const void* x, float* part, float* part2, float* gw,
+                        float* gb, int nw, int nb, int64_t B, int H, int W, hipStream_t s) {
   WgradArgs a{g, x, part, H, W};
   dim3 grid((W + T - 1) / T, (H + T - 1) / T, (unsigned)B);
   if (!gin3 && xin3) hipLaunchKernelGGL((k_wgrad<false, true>), grid, dim3(NT), 0, s, a);
@@ -531,7 +537,9 @@ static hipError_t wgrad(bool gin3, bool xin3, const void* g, const void* x, floa
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int tiles = (int)(B * grid.x * grid.y), n = nw + nb;
-  hipLaunchKernelGGL(k_reduce_parts, dim3((n + 63) / 64), dim3(256), 0, s, part, tiles, n, gw, gb, nw);
+  hipLaunchKernelGGL(k_reduce_parts1, dim3((n + 255) / 256, RS), dim3(256), 0, s, part, tiles, n, part2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_parts2, dim3((n + 255) / 256), dim3(256), 0, s, part2, n, gw, gb, nw);
   return hipGetLastError();
 }
 
@@ -546,21 +554,21 @@ static hipError_t ref_backward(mci_refiner_s* r, const float* u, const float* hr
   if ((e = hipGetLastError()) != hipSuccess) return e;
   *nlpart = lb;
   // layer 4: dW4, db4 from (dr, a3); da3 masked by a3 > 0
-  if ((e = wgrad(true, false, ws.dr, ws.a3, ws.part, r->g + W4, r->g + B4, 3 * 9 * 32, 3, B, H, W, s)) != hipSuccess) return e;
+  if ((e = wgrad(true, false, ws.dr, ws.a3, ws.part, ws.part2, r->g + W4, r->g + B4, 3 * 9 * 32, 3, B, H, W, s)) != hipSuccess) return e;
   ConvArgs a{};
   a.H = H; a.W = W;
   a.in = ws.dr; a.w = r->w + OB4; a.mask = ws.a3; a.out = ws.d0;
   if ((e = conv(IN3, 32, EPI_MASK, a, B, s)) != hipSuccess) return e;
   // layer 3
-  if ((e = wgrad(false, false, ws.d0, ws.a2, ws.part, r->g + W3, r->g + B3, 32 * 9 * 32, 32, B, H, W, s)) != hipSuccess) return e;
+  if ((e = wgrad(false, false, ws.d0, ws.a2, ws.part, ws.part2, r->g + W3, r->g + B3, 32 * 9 * 32, 32, B, H, W, s)) != hipSuccess) return e;
   a.in = ws.d0; a.w = r->w + OB3; a.mask = ws.a2; a.out = ws.d1;
   if ((e = conv(IN32, 32, EPI_MASK, a, B, s)) != hipSuccess) return e;
   // layer 2
-  if ((e = wgrad(false, false, ws.d1, ws.a1, ws.part, r->g + W2, r->g + B2, 32 * 9 * 32, 32, B, H, W, s)) != hipSuccess) return e;
+  if ((e = wgrad(false, false, ws.d1, ws.a1, ws.part, ws.part2, r->g + W2, r->g + B2, 32 * 9 * 32, 32, B, H, W, s)) != hipSuccess) return e;
   a.in = ws.d1; a.w = r->w + OB2; a.mask = ws.a1; a.out = ws.d0;
   if ((e = conv(IN32, 32, EPI_MASK, a, B, s)) != hipSuccess) return e;
   // layer 1: dW1, db1 from (dz1, u)
-  return wgrad(false, true, ws.d0, u, ws.part, r->g + W1, r->g + B1, 32 * 27, 32, B, H, W, s);
+  return wgrad(false, true, ws.d0, u, ws.part, ws.part2, r->g + W1, r->g + B1, 32 * 27, 32, B, H, W, s);
 }
 
 static hipError_t refresh_bf16(mci_refiner_s* r, hipStream_t s) {
