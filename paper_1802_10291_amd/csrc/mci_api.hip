@@ -204,13 +204,14 @@ struct DevBufs {
 static mci_status build_real_path(mci_plan_s* p) {
   const mci_plan_desc& d = p->d;
   int fa, fb;
-  if (p->prec != MCI_F32 || p->store != ST_F32 || !d.real_io || d.N % 2 || d.n_out % 2 ||
-      !two_pass_factors(d.n_out / 2, fa, fb))
+  if (p->prec != MCI_F32 || p->store != ST_F32 || !d.real_io || d.n_out % 2 || !two_pass_factors(d.n_out / 2, fa, fb))
     return MCI_OK;
-  const int64_t N = d.N, H = N / 2, P = d.n_out / 2, mu = p->mu;
+  // even N: rows read as N/2 complex pairs; odd N: the length-N transform of the real row
+  const bool half = d.N % 2 == 0;
+  const int64_t N = d.N, H = half ? N / 2 : N, P = d.n_out / 2, mu = p->mu;
   mci_status st;
   if ((st = build_side(p->rfwd, H, -1, MCI_F32)) != MCI_OK) return st;
-  if (!p->rfwd.fa) {   // H neither factors nor needs Bluestein: take Bluestein at a length that factors
+  if (!p->rfwd.fa) {   // the length neither factors nor needs Bluestein: take Bluestein at a length that factors
     free_side(p->rfwd);
     p->rfwd = FftSide();
     if ((st = build_side(p->rfwd, H, -1, MCI_F32, true)) != MCI_OK) return st;
@@ -229,6 +230,7 @@ static mci_status build_real_path(mci_plan_s* p) {
   if (!p->r_Wo || e != hipSuccess) return fail(MCI_E_DEVICE, "real-path table upload");
   RealPath& r = p->real;
   r.M = d.M; r.n_ops = d.n_ops; r.N = N; r.H = H; r.n1 = d.n1; r.n_out = d.n_out; r.P = P; r.K = K;
+  r.half = half;
   r.fwd = &p->rfwd; r.inv = &p->rinv;
   r.tab = (const float2*)p->tab; r.wN = (const float2*)p->r_wN; r.Wo = (const float2*)p->r_Wo;
   r.ok = true;

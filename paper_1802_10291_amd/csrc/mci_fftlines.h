@@ -19,7 +19,8 @@ hipError_t prepare_two_pass(int A, int B);
 // base = offs ? offs[2 (t / per) + side] / 2 + (t % per) tr : (t / per) sig + (t % per) tr, in
 // complex elements (offs: per-instance element offsets of real data, side 0 input / 1 output).
 // pre (optional): input position p < len_in is multiplied by pre[p], positions >= len_in
-// read as zero (chirp and zero padding).  post (optional): output position k is multiplied
+// read as zero (chirp and zero padding); real_in: the input is real values.  post
+// (optional): output position k is multiplied
 // by post[k].  tmp holds count A B complex (two passes only).
 struct LineXform {
   const float2* in = nullptr;
@@ -35,6 +36,9 @@ struct LineXform {
   const float2* pre = nullptr;
   int64_t len_in = 0;
   const float2* post = nullptr;
+  // input is real (float): position p reads (in[p], 0) for p < len_in, else 0; in_sig, in_tr
+  // and the input offsets are then in real elements
+  bool real_in = false;
 };
 hipError_t fft_lines(const LineXform& x, hipStream_t s);
 

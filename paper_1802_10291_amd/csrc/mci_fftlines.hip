@@ -33,10 +33,11 @@ template <int N> constexpr int threads() { return FL * (N / LineFFT<N>::E); }
 struct Side {
   const int64_t* offs = nullptr;
   int side = 0;        // 0: input offsets, 1: output offsets
+  int div = 2;         // real elements per addressed element: 2 complex, 1 real input
   int64_t per = 1, sig = 0, tr = 0;
   __device__ __forceinline__ int64_t base(int64_t t) const {
     const int64_t q = t / per, r = t - q * per;
-    return offs ? offs[2 * q + side] / 2 + r * tr : q * sig + r * tr;
+    return offs ? offs[2 * q + side] / div + r * tr : q * sig + r * tr;
   }
 };
 
@@ -51,9 +52,22 @@ struct LinesArgs {
   const float2* tw;         // N entries e^{-2 pi i k / N}
   const float2* twL;        // L entries e^{-2 pi i m / L} (pass 1 of two), or null
   const float2* pre;        // input position p: p < len_in ? in * pre[p] : 0 (if pre), else in
-  int64_t len_in;           // with pre: input positions at or beyond it read as zero
+  int64_t len_in;           // with pre or real input: positions at or beyond it read as zero
   const float2* post;       // output position k multiplied by post[k], or null
+  int real_in;              // input holds real values (float): position p reads (in[p], 0)
 };
+
+// input position p of a transform starting at `base` (complex or real elements)
+__device__ __forceinline__ float2 load_in(const LinesArgs& a, const void* base, int64_t p) {
+  if (a.real_in) {
+    if (p >= a.len_in) return make_float2(0.f, 0.f);
+    const float x = ((const float*)base)[p];
+    return a.pre ? make_float2(x * a.pre[p].x, x * a.pre[p].y) : make_float2(x, 0.f);
+  }
+  if (!a.pre) return ((const float2*)base)[p];
+  if (p >= a.len_in) return make_float2(0.f, 0.f);
+  return cmul(((const float2*)base)[p], a.pre[p]);
+}
 
 // IN_T / OUT_T: the 16 lines of the workgroup are interleaved (line stride 1, element stride
 // e); they then share one transform and U is a multiple of 16.  Otherwise lines are rows
@@ -69,14 +83,10 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
   const int64_t t0 = (int64_t)blockIdx.x * FL;
   if constexpr (IN_T) {
     const int64_t tr = t0 / a.U, u0 = t0 - tr * a.U;
-    const float2* base = a.in + a.si.base(tr);
+    const void* base = a.real_in ? (const void*)((const float*)a.in + a.si.base(tr)) : (const void*)(a.in + a.si.base(tr));
     for (int e = tid; e < N * FL; e += NT) {
       const int n = e / FL, c = e % FL;
-      const int64_t p = u0 + c + n * a.e_in;
-      float2 v = make_float2(0.f, 0.f);
-      if (!a.pre) v = base[p];
-      else if (p < a.len_in) v = cmul(base[p], a.pre[p]);
-      sml[c * TS + n] = v;
+      sml[c * TS + n] = load_in(a, base, u0 + c + n * a.e_in);
     }
   } else {
     for (int e = tid; e < N * FL; e += NT) {
@@ -85,10 +95,9 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
       float2 v = make_float2(0.f, 0.f);
       if (t < a.n_lines) {
         const int64_t tr = t / a.U, u = t - tr * a.U;
-        const int64_t p = u * a.u_in + n;
-        const float2* base = a.in + a.si.base(tr);
-        if (!a.pre) v = base[p];
-        else if (p < a.len_in) v = cmul(base[p], a.pre[p]);
+        const void* base =
+            a.real_in ? (const void*)((const float*)a.in + a.si.base(tr)) : (const void*)(a.in + a.si.base(tr));
+        v = load_in(a, base, u * a.u_in + n);
       }
       sml[c * TS + n] = v;
     }
@@ -229,21 +238,22 @@ hipError_t fft_lines(const LineXform& x, hipStream_t s) {
   if (x.count <= 0) return hipSuccess;
   const int A = x.A, B = x.B;
   fl::Side si, so;
-  si.offs = x.in_offs; si.side = 0; si.per = x.in_per; si.sig = x.in_sig; si.tr = x.in_tr;
+  si.offs = x.in_offs; si.side = 0; si.div = x.real_in ? 1 : 2; si.per = x.in_per; si.sig = x.in_sig; si.tr = x.in_tr;
   so.offs = x.out_offs; so.side = 1; so.per = x.out_per; so.sig = x.out_sig; so.tr = x.out_tr;
   if (A == 1) {
-    fl::LinesArgs a{x.in, x.out, x.count, 1, si, so, 0, 1, 0, 1, x.twB, nullptr, x.pre, x.len_in, x.post};
+    fl::LinesArgs a{x.in, x.out, x.count, 1, si, so, 0, 1, 0, 1, x.twB, nullptr, x.pre, x.len_in, x.post, x.real_in};
     return fl::run(B, x.sign, 0, a, s, false);
   }
   const int64_t L = (int64_t)A * B;
   fl::Side dense;
   dense.per = 1; dense.sig = L;
   // pass 1: A lines x[a + A b] of length B, twiddled, to tmp[k_b A + a]
-  fl::LinesArgs p1{x.in, x.tmp, x.count * A, A, si, dense, 1, A, 1, A, x.twB, x.twL, x.pre, x.len_in, nullptr};
+  fl::LinesArgs p1{x.in, x.tmp, x.count * A, A, si, dense, 1, A, 1, A, x.twB, x.twL, x.pre, x.len_in, nullptr,
+                   x.real_in};
   hipError_t e = fl::run(B, x.sign, 1, p1, s, false);
   if (e != hipSuccess) return e;
   // pass 2: B contiguous lines tmp[k_b A + a] of length A, to out[k_b + B k_a]
-  fl::LinesArgs p2{x.tmp, x.out, x.count * B, B, dense, so, A, 1, 1, B, x.twA, nullptr, nullptr, 0, x.post};
+  fl::LinesArgs p2{x.tmp, x.out, x.count * B, B, dense, so, A, 1, 1, B, x.twA, nullptr, nullptr, 0, x.post, 0};
   return fl::run(A, x.sign, 2, p2, s, false);
 }
 

@@ -2,11 +2,13 @@
 // single workgroup holds.  The steps are those of the single-pass kernel, each a pass over HBM:
 //
 //  1. channel DFTs (Lemma 3.1): row m of the real samples, read as H = N/2 complex pairs
-//     z[p] = g[2p] + i g[2p+1], goes through a one- or two-pass transform of length H (through
-//     Bluestein's chirp convolution when H does not factor: the chirp is applied as the
-//     first pass loads, the filter spectrum as the second one stores);
+//     z[p] = g[2p] + i g[2p+1] (odd N: as N real values), goes through a one- or two-pass
+//     transform of length H (N) (through Bluestein's chirp convolution when that length does
+//     not factor: the chirp is applied as the first pass loads, the filter spectrum as the
+//     second one stores);
 //  2. apply (eq. matrixeqn1) and the real part: X_m[r] = E[r'] + e^{-2 pi i r / N} O[r'],
-//     r' = r mod H, with E, O the even/odd-sample DFTs recovered from Z; a(k) = sum_m
+//     r' = r mod H, with E, O the even/odd-sample DFTs recovered from Z (odd N: X_m = Z);
+//     a(k) = sum_m
 //     X_m[k mod N] Tab[m][j][i] for k = n1 + i + jN; S(k) = (a(k) + conj a(-k)) / 2;
 //  3. output: with P = n_out / 2 and w = e^{2 pi i / n_out}, the two polyphase components
 //     y[2q] and y[2q + 1] are the real and imaginary parts of
@@ -28,12 +30,20 @@ __device__ __forceinline__ float2 conj2(float2 a) { return make_float2(a.x, -a.y
 __device__ __forceinline__ float2 band_coeff(int64_t k, const float2* __restrict__ Zs, int64_t Lz,
                                              const float2* __restrict__ post, const float2* __restrict__ wN,
                                              const float2* __restrict__ tab, int op, int M, int64_t N, int64_t H,
-                                             int64_t n1) {
+                                             int64_t n1, bool half) {
   const int64_t d = k - n1;
   float2 acc = make_float2(0.f, 0.f);
   if (d < 0 || d >= (int64_t)M * N) return acc;
   const int64_t j = d / N, i = d - j * N;
   const int64_t r = ((k % N) + N) % N;
+  if (!half) {   // X_m[r] is the transform itself
+    for (int m = 0; m < M; ++m) {
+      float2 x = Zs[m * Lz + r];
+      if (post) x = cmul(x, post[r]);
+      acc = cadd(acc, cmul(x, tab[(((int64_t)op * M + m) * M + j) * N + i]));
+    }
+    return acc;
+  }
   const int64_t rh = r < H ? r : r - H;
   const int64_t rr = rh == 0 ? 0 : H - rh;
   const float sg = r < H ? 1.f : -1.f;
@@ -57,7 +67,7 @@ __device__ __forceinline__ float2 band_coeff(int64_t k, const float2* __restrict
 __global__ void k_apply_real(const float2* __restrict__ Z, int64_t Lz, const float2* __restrict__ post,
                              const float2* __restrict__ wN, const float2* __restrict__ tab,
                              const float2* __restrict__ Wo, float2* __restrict__ Zc, int M, int n_ops, int64_t N,
-                             int64_t H, int64_t n1, int64_t K, int64_t P, int64_t batch) {
+                             int64_t H, int64_t n1, int64_t K, int64_t P, int64_t batch, int half_rows) {
   const int64_t half = P / 2 + 1;   // bin pairs {b, P - b}, b = 0 .. P/2
   const int64_t total = batch * n_ops * half;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -68,8 +78,8 @@ __global__ void k_apply_real(const float2* __restrict__ Z, int64_t Lz, const flo
     const bool self = b == 0 || 2 * b == P;
     float2 acc_b = make_float2(0.f, 0.f), acc_m = make_float2(0.f, 0.f);
     for (int64_t k = b - ((b + K) / P) * P; k <= K; k += P) {   // k = b mod P, |k| <= K
-      const float2 ak = band_coeff(k, Zs, Lz, post, wN, tab, op, M, N, H, n1);
-      const float2 amk = conj2(band_coeff(-k, Zs, Lz, post, wN, tab, op, M, N, H, n1));
+      const float2 ak = band_coeff(k, Zs, Lz, post, wN, tab, op, M, N, H, n1, half_rows);
+      const float2 amk = conj2(band_coeff(-k, Zs, Lz, post, wN, tab, op, M, N, H, n1, half_rows));
       const float2 S = make_float2(0.5f * (ak.x + amk.x), 0.5f * (ak.y + amk.y));
       acc_b = cadd(acc_b, cmul(S, Wo[k + K]));
       if (!self) acc_m = cadd(acc_m, cmul(conj2(S), Wo[K - k]));
@@ -107,11 +117,13 @@ hipError_t run_real_1d(const RealPath& r, const void* g, void* y, int64_t batch,
   x.in = (const float2*)g; x.out = Zf; x.tmp = T1; x.count = batch * r.M;
   x.A = f.fa; x.B = f.fb; x.sign = -1;
   x.twA = (const float2*)f.twA; x.twB = (const float2*)f.twB; x.twL = (const float2*)f.tw;
-  x.in_offs = offs; x.in_per = r.M; x.in_sig = r.M * r.H; x.in_tr = r.H;
+  const int64_t L_in = r.half ? r.H : r.N;   // complex pairs, or real samples, per row
+  x.in_offs = offs; x.in_per = r.M; x.in_sig = r.M * L_in; x.in_tr = L_in;
+  x.real_in = !r.half;
+  x.len_in = L_in;
   x.out_sig = Lz;
   if (f.blue) {
     x.pre = (const float2*)f.chirp;
-    x.len_in = r.H;
     x.post = (const float2*)f.bhat;
   }
   hipError_t e = fft_lines(x, s);
@@ -128,7 +140,7 @@ hipError_t run_real_1d(const RealPath& r, const void* g, void* y, int64_t batch,
   const int64_t total = batch * r.n_ops * (r.P / 2 + 1);
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1 << 20));
   hipLaunchKernelGGL(k_apply_real, dim3(grid), dim3(256), 0, s, Zf, Lz, f.blue ? (const float2*)f.chirp : nullptr,
-                     r.wN, r.tab, r.Wo, Zc, r.M, r.n_ops, r.N, r.H, r.n1, r.K, r.P, batch);
+                     r.wN, r.tab, r.Wo, Zc, r.M, r.n_ops, r.N, r.H, r.n1, r.K, r.P, batch, r.half ? 1 : 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // 3. one inverse transform of length P per (signal, op), written as the output row
   LineXform o;

@@ -120,13 +120,15 @@ def test_two_pass_transforms_match_oracle(torch_cuda, N, n_out, M):
 
 @pytest.mark.parametrize("N,n_out,M,n1", [(1024, 4096, 2, None), (1536, 6144, 2, None), (86, 1024, 3, None),
                                           (4096, 65536, 4, None), (1366, 16384, 3, 100), (2048, 8192, 3, -5000),
-                                          (512, 2048, 2, None), (21846, 262144, 3, None)])
+                                          (512, 2048, 2, None), (21846, 262144, 3, None),
+                                          (683, 8192, 3, None), (171, 2048, 3, None), (10923, 131072, 3, None)])
 def test_real_two_pass_matches_oracle(torch_cuda, N, n_out, M, n1):
     """Real-mode multi-kernel path: rows read as N/2 complex pairs (one pass for 256 and 512,
     two for 1024 and 2048, Bluestein for 43, 683 and 10923, Bluestein forced for 768, which
     neither factors into line lengths nor needs it), a band not containing 0, a band far off
     centre that folds several coefficients into each output bin, and the largest
-    mixed-workload length (64 sampled points)."""
+    mixed-workload length (64 sampled points).  Odd N (683, 171, 10923) takes the full-length
+    transform of each real row (Bluestein at 1536, 384 and 24576)."""
     from paper_1802_10291_amd import Plan1D
     cnt = 2 if N > 8192 else 3
     g = S.smooth_noisy_batch(70, cnt, M, N, 2 * M * N)
