@@ -424,28 +424,32 @@ int orc_sampling_series(int M, int64_t N, int64_t n1, const int *kinds, const in
 
 /* ------------------------------------------------------------------------------ */
 /* Separable 2-D upsampling (Section 5.2): every row, then every column of the result, */
-/* is reconstructed from two channels, the line itself and its three-point centred    */
-/* difference, on a grid s times finer.                                              */
+/* is reconstructed from the line itself and its three-point centred difference (and, */
+/* with three channels, its three-point second difference) on a grid s times finer.   */
 /* ------------------------------------------------------------------------------ */
 
-/* One 1-D pass on a real line x[0..N) with channels {x, D x}:
- *   g_2[p] = (x[p+1] - x[p-1]) / (2h),  h = 2 pi / N, indices circular,
- * multiplier b_2(n) = i n, band n1 = -floor((2N - 1) / 2), Re of the result at
- * n_out = s N points.  W: e^{-2 pi i k/N}; E: e^{+2 pi i k/n_out}. */
-static int line_pass(int64_t N, int s, const double *x, int64_t xstride, double *y, int64_t ystride, const cplx *W,
-                     const cplx *E, cplx *work) {
-  static const int kinds[2] = {ORC_MULT_DERIV, ORC_MULT_DERIV};
-  static const int orders[2] = {0, 1};
-  const int64_t mu = 2 * N, n1 = -((2 * N - 1) / 2), n_out = (int64_t)s * N;
-  chanset cs = {2, N, n1, kinds, orders, NULL};
+/* One 1-D pass on a real line x[0..N) with M = 2 channels {x, D x} or M = 3 channels
+ * {x, D x, D2 x}:
+ *   D x[p]  = (x[p+1] - x[p-1]) / (2h),            multiplier i n,
+ *   D2 x[p] = (x[p+1] - 2 x[p] + x[p-1]) / h^2,     multiplier (i n)^2,
+ * h = 2 pi / N, indices circular, band n1 = -floor((M N - 1) / 2), Re of the result at
+ * n_out = s N points.  W: e^{-2 pi i k/N}; E: e^{+2 pi i k/n_out}; work: 3 M N values. */
+static int line_pass(int64_t N, int M, int s, const double *x, int64_t xstride, double *y, int64_t ystride,
+                     const cplx *W, const cplx *E, cplx *work) {
+  static const int kinds[3] = {ORC_MULT_DERIV, ORC_MULT_DERIV, ORC_MULT_DERIV};
+  static const int orders[3] = {0, 1, 2};
+  const int64_t mu = (int64_t)M * N, n1 = -((mu - 1) / 2), n_out = (int64_t)s * N;
+  chanset cs = {M, N, n1, kinds, orders, NULL};
   cplx *g = work, *d = work + mu, *a = work + 2 * mu;
   const double inv2h = (double)N / (2.0 * two_pi());
+  const double invh2 = inv2h * inv2h * 4.0;   /* (N / 2 pi)^2 */
   for (int64_t p = 0; p < N; ++p) {
-    g[p] = x[p * xstride];
-    g[N + p] = (x[((p + 1) % N) * xstride] - x[((p + N - 1) % N) * xstride]) * inv2h;
+    const double xp = x[p * xstride], xn = x[((p + 1) % N) * xstride], xm = x[((p + N - 1) % N) * xstride];
+    g[p] = xp;
+    g[N + p] = (xn - xm) * inv2h;
+    if (M == 3) g[2 * N + p] = (xn - 2.0 * xp + xm) * invh2;
   }
-  direct_dft(N, n1, g, W, d);
-  direct_dft(N, n1, g + N, W, d + N);
+  for (int m = 0; m < M; ++m) direct_dft(N, n1, g + m * N, W, d + m * N);
   if (solve_band(&cs, d, 0, a, NULL) != ORC_OK) return ORC_E_SINGULAR;
   for (int64_t j = 0; j < n_out; ++j) {
     cplx acc = 0.0;
@@ -459,9 +463,10 @@ static int line_pass(int64_t N, int s, const double *x, int64_t xstride, double 
   return ORC_OK;
 }
 
-/* x: [batch][h][w] real; y: [batch][s h][s w] real.  Rows first, then columns. */
-int orc_upsample_2d(int64_t batch, int64_t h, int64_t w, int s, const double *x, double *y) {
-  if (batch < 0 || h < 1 || w < 1 || s < 1) return ORC_E_INVALID;
+/* x: [batch][h][w] real; y: [batch][s h][s w] real.  Rows first, then columns; M = 2 or 3
+ * channels per line. */
+int orc_upsample_2d(int64_t batch, int64_t h, int64_t w, int s, int M, const double *x, double *y) {
+  if (batch < 0 || h < 1 || w < 1 || s < 1 || (M != 2 && M != 3)) return ORC_E_INVALID;
   const int64_t H = (int64_t)s * h, Wd = (int64_t)s * w;
   cplx *Ww = phase_table(w, -1.0), *Ew = phase_table(Wd, +1.0);
   cplx *Wh = phase_table(h, -1.0), *Eh = phase_table(H, +1.0);
@@ -472,14 +477,14 @@ int orc_upsample_2d(int64_t batch, int64_t h, int64_t w, int s, const double *x,
     double *yb = y + (size_t)b * H * Wd;
 #pragma omp parallel for schedule(dynamic)
     for (int64_t r = 0; r < h; ++r) {
-      cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)6 * w);
-      if (!work || line_pass(w, s, xb + r * w, 1, mid + r * Wd, 1, Ww, Ew, work) != ORC_OK) rc = ORC_E_INVALID;
+      cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)3 * M * w);
+      if (!work || line_pass(w, M, s, xb + r * w, 1, mid + r * Wd, 1, Ww, Ew, work) != ORC_OK) rc = ORC_E_INVALID;
       free(work);
     }
 #pragma omp parallel for schedule(dynamic)
     for (int64_t c = 0; c < Wd; ++c) {
-      cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)6 * h);
-      if (!work || line_pass(h, s, mid + c, Wd, yb + c, Wd, Wh, Eh, work) != ORC_OK) rc = ORC_E_INVALID;
+      cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)3 * M * h);
+      if (!work || line_pass(h, M, s, mid + c, Wd, yb + c, Wd, Wh, Eh, work) != ORC_OK) rc = ORC_E_INVALID;
       free(work);
     }
   }

@@ -63,7 +63,7 @@ def _load():
     lib.orc_reconstruct_1d.argtypes = [i32, i64, i64, pi, pi, pd, i32, pi, pi, i64, i32, i32, i64, pd, pd, P(i64)]
     lib.orc_interp_function.argtypes = [i32, i64, i64, pi, pi, pd, i32, i64, pd, pd]
     lib.orc_sampling_series.argtypes = [i32, i64, i64, pi, pi, pd, pd, i64, pd, pd]
-    lib.orc_upsample_2d.argtypes = [i64, i64, i64, i32, pd, pd]
+    lib.orc_upsample_2d.argtypes = [i64, i64, i64, i32, i32, pd, pd]
     lib.orc_num_threads.argtypes = []
     for name in ("orc_channel_dft", "orc_inverse_tables", "orc_recover_band", "orc_reconstruct_1d",
                  "orc_interp_function", "orc_sampling_series", "orc_upsample_2d", "orc_num_threads"):
@@ -233,15 +233,17 @@ def sampling_series(ch: Channels, g: np.ndarray, t: np.ndarray) -> np.ndarray:
     return out
 
 
-def upsample_2d(x: np.ndarray, s: int) -> np.ndarray:
-    """Separable rows-then-columns MCI upsampling by s with channels {x, Dx} (Section 5.2)."""
+def upsample_2d(x: np.ndarray, s: int, M: int = 2) -> np.ndarray:
+    """Separable rows-then-columns MCI upsampling by s with channels {x, Dx} (M = 2) or
+    {x, Dx, D2x} (M = 3, the setting of Section 5.2's experiments), D and D2 the three-point
+    centred first and second differences in t-units."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     squeeze = x.ndim == 2
     if squeeze:
         x = x[None]
     B, h, w = x.shape
     y = np.zeros((B, s * h, s * w), dtype=np.float64)
-    _check(_load().orc_upsample_2d(B, h, w, s, _pd(x), _pd(y)))
+    _check(_load().orc_upsample_2d(B, h, w, s, M, _pd(x), _pd(y)))
     return y[0] if squeeze else y
 
 

@@ -583,3 +583,52 @@ def test_evaluate_band_cos_to_sin_and_grid_equals_reconstruction():
     for n_out in (40, 7):
         tj = 2 * np.pi * np.arange(n_out) / n_out
         assert np.allclose(O.evaluate_band(band, ch.n1, tj), O.reconstruct_1d(ch, g, n_out)[0], atol=1e-12)
+
+
+# ---------------------------------------------------------------- 2-D with three channels
+def test_2d_three_channels_decimation_consistency():
+    """With channels {x, Dx, D2x} (Section 5.2's experiments use three) the output still
+    passes through the samples: out[s i, s j] = LR[i, j] (Theorem 4.1 on both passes)."""
+    rng = np.random.default_rng(15)
+    x = rng.uniform(size=(2, 10, 14))
+    for s in (2, 3, 4):
+        y = O.upsample_2d(x, s, M=3)
+        assert np.abs(y[:, ::s, ::s] - x).max() < 1e-12
+
+
+def test_2d_three_channels_row_pass_equals_1d_route():
+    """A row pass is the 1-D reconstruction with channels {x, (x[p+1] - x[p-1]) N / (4 pi),
+    (x[p+1] - 2 x[p] + x[p-1]) (N / 2 pi)^2} and multipliers {1, i n, (i n)^2}."""
+    rng = np.random.default_rng(16)
+    w, h, s = 15, 4, 3
+    row = rng.standard_normal(w)
+    x = np.tile(row, (h, 1))
+    y = O.upsample_2d(x, s, M=3)
+    fd = (np.roll(row, -1) - np.roll(row, 1)) * w / (4 * np.pi)
+    fd2 = (np.roll(row, -1) - 2 * row + np.roll(row, 1)) * (w / (2 * np.pi)) ** 2
+    ch = O.Channels(N=w, kinds=[O.MULT_DERIV] * 3, orders=[0, 1, 2])
+    want = O.reconstruct_1d(ch, np.stack([row, fd, fd2]), s * w)[0]
+    for r in range(s * h):
+        assert np.abs(y[r] - want).max() < 1e-12
+
+
+def test_2d_three_channels_fourier_window_form_and_smooth_image():
+    """Shift-equivariance gives the FFT2 window form for three channels too; and a smooth
+    separable image is reproduced closely at x3 (pins the (N / 2 pi)^2 scaling of D2)."""
+    rng = np.random.default_rng(17)
+    h, w, s = 9, 12, 3
+    x = rng.uniform(size=(h, w))
+    imp_w = np.zeros((h, w)); imp_w[:, 0] = 1.0
+    imp_h = np.zeros((h, w)); imp_h[0, :] = 1.0
+    Ww = np.fft.fft(O.upsample_2d(imp_w, s, M=3)[0])
+    Wh = np.fft.fft(O.upsample_2d(imp_h, s, M=3)[:, 0])
+    X = np.fft.fft2(x)
+    Y = X[np.ix_(np.arange(s * h) % h, np.arange(s * w) % w)] * Wh[:, None] * Ww[None, :]
+    assert np.abs(O.upsample_2d(x, s, M=3) - np.fft.ifft2(Y).real).max() < 1e-12
+    n = 30
+    u = lambda t: np.cos(2 * t) + 0.3 * np.sin(3 * t)
+    v = lambda t: np.sin(t) + 0.2 * np.cos(4 * t)
+    tc, tf = 2 * np.pi * np.arange(n) / n, 2 * np.pi * np.arange(s * n) / (s * n)
+    y = O.upsample_2d(np.outer(u(tc), v(tc)), s, M=3)
+    want = np.outer(u(tf), v(tf))
+    assert np.abs(y - want).max() < 2e-2 * np.abs(want).max()
