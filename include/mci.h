@@ -163,7 +163,9 @@ typedef struct {
   int32_t scale;        /* upsampling factor s >= 1: output is (s h) x (s w) */
   int32_t precision;    /* MCI_F32 (MCI_F64 accepted for validation runs) */
   int32_t storage;      /* mci_storage of lr and hr */
-  int32_t reserved;
+  int32_t channels;     /* channels per line: 2 = {x, Dx} (0 also means 2), or 3 = {x, Dx, D2x} with the
+                           three-point second difference (x[p+1] - 2x[p] + x[p-1]) / h^2 and multiplier
+                           (i n)^2, the setting of the paper's Section 5.2 experiments */
 } mci_plan2d_desc;
 
 /* mci_plan_2d -- build a 2-D upsampling plan (two 1-D plans, rows and columns). */

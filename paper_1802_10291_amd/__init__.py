@@ -160,11 +160,14 @@ class Plan1D(_Variants):
 
 
 class Plan2D(_Variants):
-    """A 2-D separable upsampling plan (``mci_plan_2d``): lr [batch, h, w] -> hr [batch, s h, s w]."""
+    """A 2-D separable upsampling plan (``mci_plan_2d``): lr [batch, h, w] -> hr [batch, s h, s w],
+    with channels {x, Dx} (channels=2) or {x, Dx, D2x} (channels=3) per line."""
 
-    def __init__(self, h: int, w: int, scale: int, precision: str = "f32", storage: str = "native", device: int = 0):
+    def __init__(self, h: int, w: int, scale: int, precision: str = "f32", storage: str = "native", device: int = 0,
+                 channels: int = 2):
         d = _lib.mci_plan2d_desc()
         d.h, d.w, d.scale = int(h), int(w), int(scale)
+        d.channels = int(channels)
         d.precision = {"f32": _lib.MCI_F32, "f64": _lib.MCI_F64}[precision]
         d.storage = {"native": _lib.MCI_STORE_NATIVE, "f16": _lib.MCI_STORE_F16}[storage]
         self.desc = d

@@ -49,7 +49,7 @@ class mci_plan_info_t(ctypes.Structure):
 
 class mci_plan2d_desc(ctypes.Structure):
     _fields_ = [("h", ctypes.c_int32), ("w", ctypes.c_int32), ("scale", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("storage", ctypes.c_int32), ("channels", ctypes.c_int32)]
 
 
 MCI_VARIANT_MULTIPASS_R8, MCI_VARIANT_MULTIPASS_R4, MCI_VARIANT_FUSED_T1, MCI_VARIANT_FUSED_T2, \

@@ -24,7 +24,7 @@ struct LinePassArgs {
 
 bool line_pass_supported(int N, int SC);
 std::vector<std::complex<double>> line_windows(const std::vector<std::complex<double>>& tab, int64_t N, int64_t n1,
-                                               int SC);
+                                               int SC, int M);
 hipError_t run_line_pass(int N, int SC, bool cols, int store_in, int store_out, const LinePassArgs& a,
                          int64_t images, hipStream_t s);
 // set the dynamic-LDS limit of the pass's kernel where it exceeds 64 KB (once, at plan time)

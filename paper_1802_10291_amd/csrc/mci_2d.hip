@@ -191,9 +191,10 @@ static hipError_t dispatch(int N, int SC, const LinePassArgs& a, int64_t images,
 #define MCI_LP(NN, SS)                                                                  \
   if (N == NN && SC == SS)                                                              \
     return prep ? prepare<NN, SS, COLS, TI, TO>(a, images, s) : launch<NN, SS, COLS, TI, TO>(a, images, s);
-  MCI_LP(32, 2) MCI_LP(32, 4) MCI_LP(48, 2) MCI_LP(48, 4) MCI_LP(64, 2) MCI_LP(64, 4) MCI_LP(96, 2) MCI_LP(96, 4)
-  MCI_LP(128, 2) MCI_LP(128, 4) MCI_LP(192, 2) MCI_LP(192, 4) MCI_LP(256, 2) MCI_LP(256, 4) MCI_LP(384, 2)
-  MCI_LP(384, 4) MCI_LP(512, 2) MCI_LP(512, 4)
+  MCI_LP(32, 2) MCI_LP(32, 3) MCI_LP(32, 4) MCI_LP(48, 2) MCI_LP(48, 3) MCI_LP(48, 4) MCI_LP(64, 2) MCI_LP(64, 3)
+  MCI_LP(64, 4) MCI_LP(96, 2) MCI_LP(96, 3) MCI_LP(96, 4) MCI_LP(128, 2) MCI_LP(128, 3) MCI_LP(128, 4)
+  MCI_LP(192, 2) MCI_LP(192, 3) MCI_LP(192, 4) MCI_LP(256, 2) MCI_LP(256, 3) MCI_LP(256, 4) MCI_LP(384, 2)
+  MCI_LP(384, 3) MCI_LP(384, 4) MCI_LP(512, 2) MCI_LP(512, 3) MCI_LP(512, 4)
 #undef MCI_LP
   return hipErrorInvalidValue;
 }
@@ -202,24 +203,31 @@ static hipError_t dispatch(int N, int SC, const LinePassArgs& a, int64_t images,
 
 bool line_pass_supported(int N, int SC) {
   const bool n_ok = N == 32 || N == 48 || N == 64 || N == 96 || N == 128 || N == 192 || N == 256 || N == 384 || N == 512;
-  return n_ok && (SC == 2 || SC == 4);
+  return n_ok && (SC == 2 || SC == 3 || SC == 4);
 }
 
-// Polyphase windows of one axis from the FP64 apply table Tab[2][2][N] (identity output,
-// channels {x, Dx}, multipliers {1, i n}).  Returns H[SC][N] (FP64).
+// Polyphase windows of one axis from the FP64 apply table Tab[M][M][N] (identity output,
+// channels {x, Dx} or {x, Dx, D2x}, multipliers {1, i n, (i n)^2}).  Channel m of a line is
+// the line filtered by its difference operator, whose Fourier multiplier at n (theta =
+// 2 pi n / N) is 1, fd(n) = i N sin(theta) / (2 pi) or fd2(n) = (2 cos(theta) - 2) (N / 2 pi)^2,
+// so a(n + jN) = X(n) G(n + jN) with G(n + jN) = sum_m mult_m(n) Tab[m][j][i].  Returns
+// H[SC][N] (FP64).
 std::vector<std::complex<double>> line_windows(const std::vector<std::complex<double>>& tab, int64_t N, int64_t n1,
-                                               int SC) {
+                                               int SC, int M) {
   using C = std::complex<double>;
-  const int64_t mu = 2 * N;
+  const int64_t mu = (int64_t)M * N;
   const int64_t K = std::max<int64_t>(std::llabs(n1), std::llabs(n1 + mu - 1));
   std::vector<C> G(2 * K + 1, 0.0);  // G(k), k = -K..K, zero outside the band
+  const double sN = (double)N / (2.0 * M_PI);
   for (int64_t i = 0; i < N; ++i) {
     const int64_t n = n1 + i;
-    const double s = std::sin(2.0 * M_PI * (double)(((n % N) + N) % N) / (double)N);
-    const C fd(0.0, (double)N * s / (2.0 * M_PI));
-    for (int j = 0; j < 2; ++j) {
+    const double th = 2.0 * M_PI * (double)(((n % N) + N) % N) / (double)N;
+    const C mult[3] = {C(1.0, 0.0), C(0.0, sN * std::sin(th)), C((2.0 * std::cos(th) - 2.0) * sN * sN, 0.0)};
+    for (int j = 0; j < M; ++j) {
       const int64_t k = n + j * N;
-      G[k + K] = tab[(0 * 2 + j) * N + i] + fd * tab[(1 * 2 + j) * N + i];
+      C g = 0.0;
+      for (int m = 0; m < M; ++m) g += mult[m] * tab[((size_t)m * M + j) * N + i];
+      G[k + K] = g;
     }
   }
   std::vector<C> H((size_t)SC * N, 0.0);

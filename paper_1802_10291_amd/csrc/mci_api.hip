@@ -374,13 +374,13 @@ static size_t ws_1d(const mci_plan_s* p, int64_t batch) {
 static size_t ws_2d(const mci_plan_s* p, int64_t batch) {
   if (batch <= 0) return 0;
   if (p->lp) return (size_t)batch * p->d2.scale * p->d2.h * p->d2.w * sizeof(float) + 256;
-  const int64_t h = p->d2.h, w = p->d2.w, s = p->d2.scale;
+  const int64_t h = p->d2.h, w = p->d2.w, s = p->d2.scale, M = p->d2.channels;
   const size_t e = p->prec == MCI_F64 ? 8 : 4;
   auto al = [](size_t n) { return (n + 255) & ~(size_t)255; };
   // row channels, mid image, column channels, column result, and the larger 1-D workspace
-  size_t rows_in = al((size_t)batch * h * 2 * w * e);
+  size_t rows_in = al((size_t)batch * h * M * w * e);
   size_t mid = al((size_t)batch * h * s * w * e);
-  size_t cols_in = al((size_t)batch * s * w * 2 * h * e);
+  size_t cols_in = al((size_t)batch * s * w * M * h * e);
   size_t cols_out = al((size_t)batch * s * w * s * h * e);
   size_t w1 = std::max(ws_1d(p->rows, batch * h), ws_1d(p->cols, batch * s * w));
   return rows_in + mid + cols_in + cols_out + al(w1) + 256;
@@ -424,20 +424,21 @@ static mci_status run_2d(const mci_plan_s* p, const void* lr, void* hr, int64_t 
     return MCI_OK;
   }
   const int64_t h = p->d2.h, w = p->d2.w, s = p->d2.scale, H = s * h, W = s * w;
+  const int M = p->d2.channels;
   const size_t e = p->prec == MCI_F64 ? 8 : 4;
   auto al = [](size_t n) { return (n + 255) & ~(size_t)255; };
   char* base = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
   char* rows_in = base;
-  char* mid = rows_in + al((size_t)batch * h * 2 * w * e);
+  char* mid = rows_in + al((size_t)batch * h * M * w * e);
   char* cols_in = mid + al((size_t)batch * h * W * e);
-  char* cols_out = cols_in + al((size_t)batch * W * 2 * h * e);
+  char* cols_out = cols_in + al((size_t)batch * W * M * h * e);
   char* w1 = cols_out + al((size_t)batch * W * H * e);
   hipError_t err;
-  if ((err = launch_fd_channels(p->prec, p->store, lr, rows_in, batch, h, w, 0, offs, stream)) != hipSuccess)
+  if ((err = launch_fd_channels(p->prec, p->store, lr, rows_in, batch, h, w, 0, offs, M, stream)) != hipSuccess)
     return fail(MCI_E_DEVICE, hipGetErrorString(err));
   mci_status st = plan_run(p->rows, rows_in, mid, batch * h, w1, nullptr, stream);
   if (st != MCI_OK) return st;
-  if ((err = launch_fd_channels(p->prec, p->prec == MCI_F64 ? ST_F64 : ST_F32, mid, cols_in, batch, h, W, 1, nullptr,
+  if ((err = launch_fd_channels(p->prec, p->prec == MCI_F64 ? ST_F64 : ST_F32, mid, cols_in, batch, h, W, 1, nullptr, M,
                                 stream)) != hipSuccess)
     return fail(MCI_E_DEVICE, hipGetErrorString(err));
   if ((st = plan_run(p->cols, cols_in, cols_out, batch * W, w1, nullptr, stream)) != MCI_OK) return st;
@@ -581,19 +582,22 @@ mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out)
   if (desc->precision != MCI_F32 && desc->precision != MCI_F64) return fail(MCI_E_INVALID_ARG, "precision");
   if (desc->storage != MCI_STORE_NATIVE && desc->storage != MCI_STORE_F16) return fail(MCI_E_INVALID_ARG, "storage");
   if (desc->storage == MCI_STORE_F16 && desc->precision != MCI_F32) return fail(MCI_E_INVALID_ARG, "F16 needs F32");
+  if (desc->channels != 0 && desc->channels != 2 && desc->channels != 3)
+    return fail(MCI_E_INVALID_ARG, "channels must be 2 or 3 (0 means 2)");
   mci_plan_s* p = new (std::nothrow) mci_plan_s();
   if (!p) return fail(MCI_E_OUT_OF_MEMORY, "plan");
   p->dims = 2;
   p->device = device;
   p->d2 = *desc;
+  if (p->d2.channels == 0) p->d2.channels = 2;
+  const int M2 = p->d2.channels;
   p->prec = desc->precision;
   p->store = desc->precision == MCI_F64 ? ST_F64 : (desc->storage == MCI_STORE_F16 ? ST_F16 : ST_F32);
   for (int axis = 0; axis < 2; ++axis) {
     const int64_t len = axis == 0 ? desc->w : desc->h;
     mci_plan_desc d{};
-    d.M = 2; d.n_ops = 1; d.N = len; d.n1 = MCI_N1_DEFAULT; d.n_out = (int64_t)desc->scale * len;
-    d.ch[0].kind = MCI_MULT_DERIV; d.ch[0].order = 0;
-    d.ch[1].kind = MCI_MULT_DERIV; d.ch[1].order = 1;
+    d.M = M2; d.n_ops = 1; d.N = len; d.n1 = MCI_N1_DEFAULT; d.n_out = (int64_t)desc->scale * len;
+    for (int m = 0; m < M2; ++m) { d.ch[m].kind = MCI_MULT_DERIV; d.ch[m].order = m; }
     d.ops[0] = MCI_OUT_IDENTITY;
     d.real_io = 1;
     d.precision = desc->precision;
@@ -609,7 +613,7 @@ mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out)
     for (int axis = 0; axis < 2; ++axis) {
       const mci_plan_s* q = axis == 0 ? p->cols : p->rows;
       const int64_t len = q->d.N;
-      std::vector<std::complex<double>> H = line_windows(q->tab_host, len, q->d.n1, desc->scale);
+      std::vector<std::complex<double>> H = line_windows(q->tab_host, len, q->d.n1, desc->scale, M2);
       std::vector<std::complex<double>> tw(len);
       for (int64_t k = 0; k < len; ++k) tw[k] = root_of_unity(k, len);
       hipError_t e;

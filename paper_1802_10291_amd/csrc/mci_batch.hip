@@ -41,7 +41,8 @@ std::string plan_tune_key(const mci_plan_s* p) {
   std::ostringstream k;
   k << device_key(p->device) << "|";
   if (p->dims == 2) {
-    k << "2d|h" << p->d2.h << "|w" << p->d2.w << "|s" << p->d2.scale << "|p" << p->prec << "|st" << p->store;
+    k << "2d|h" << p->d2.h << "|w" << p->d2.w << "|s" << p->d2.scale << "|c" << p->d2.channels << "|p" << p->prec
+      << "|st" << p->store;
     return k.str();
   }
   const mci_plan_desc& d = p->d;

@@ -64,11 +64,11 @@ size_t generic_1d_workspace(const Generic1D& g, int prec, int64_t batch);
 // offs: per-signal (input, output) element offsets (device, 2 per signal) or null (dense)
 hipError_t run_generic_1d(const Generic1D& g, int prec, int store, const void* in, void* out, int64_t batch,
                           void* ws, const int64_t* offs, hipStream_t s);
-// 2-D helpers: build the two channels {x, centred difference} of every line.
-//   rows: x [B][h][w] -> G [B*h][2][w];  cols: x [B][H][W] (column c is a line of length H)
-//   -> G [B*W][2][H].  `deriv_scale` = len / (4 pi).
+// 2-D helpers: build the M channels {x, centred difference[, second difference]} of every line.
+//   rows: x [B][h][w] -> G [B*h][M][w];  cols: x [B][H][W] (column c is a line of length H)
+//   -> G [B*W][M][H].  `deriv_scale` = len / (4 pi).
 hipError_t launch_fd_channels(int prec, int store_in, const void* x, void* G, int64_t B, int64_t h, int64_t w,
-                              int along_cols, const int64_t* offs, hipStream_t s);
+                              int along_cols, const int64_t* offs, int M, hipStream_t s);
 // transpose [B][W][H] -> [B][H][W] with storage conversion to the output type
 // (offs: image b's input at x + offs[2 b], output at dst + offs[2 b + 1]; null: dense)
 hipError_t launch_transpose_out(int prec, int store_out, const void* src, void* dst, int64_t B, int64_t W,

@@ -380,15 +380,17 @@ hipError_t run_generic_1d(const Generic1D& g, int prec, int store, const void* i
 }
 
 // ================================================================= 2-D helpers
-// Channels of each line: the line itself and its centred difference (x[p+1] - x[p-1]) / (2h),
-// h = 2 pi / len, circular.  Output G[line][2][len] in the compute type.
+// Channels of each line: the line itself, its centred difference (x[p+1] - x[p-1]) / (2h) and,
+// with M = 3, its second difference (x[p+1] - 2 x[p] + x[p-1]) / h^2; h = 2 pi / len, circular.
+// Output G[line][M][len] in the compute type.
 template <typename T, typename St>
 __global__ void k_fd_channels(const St* __restrict__ x, T* __restrict__ G, int64_t B, int64_t h, int64_t w,
-                              int along_cols, const int64_t* __restrict__ offs) {
+                              int along_cols, const int64_t* __restrict__ offs, int M) {
   const int64_t len = along_cols ? h : w;
   const int64_t lines_per_img = along_cols ? w : h;
   const int64_t total = B * lines_per_img * len;
   const T sc = (T)((double)len / (4.0 * 3.14159265358979323846));
+  const T sc2 = (T)(((double)len / (2.0 * 3.14159265358979323846)) * ((double)len / (2.0 * 3.14159265358979323846)));
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = e % len;
     const int64_t line = e / len;
@@ -402,24 +404,25 @@ __global__ void k_fd_channels(const St* __restrict__ x, T* __restrict__ G, int64
       const int64_t c0 = (offs ? offs[2 * b] : b * h * w) + l;
       v = ld_as<T>(x, c0 + p * w); vn = ld_as<T>(x, c0 + pn * w); vp = ld_as<T>(x, c0 + pp * w);
     }
-    G[(line * 2) * len + p] = v;
-    G[(line * 2 + 1) * len + p] = (vn - vp) * sc;
+    G[(line * M) * len + p] = v;
+    G[(line * M + 1) * len + p] = (vn - vp) * sc;
+    if (M == 3) G[(line * M + 2) * len + p] = (vn - (T)2 * v + vp) * sc2;
   }
 }
 
 hipError_t launch_fd_channels(int prec, int store_in, const void* x, void* G, int64_t B, int64_t h, int64_t w,
-                              int along_cols, const int64_t* offs, hipStream_t s) {
+                              int along_cols, const int64_t* offs, int M, hipStream_t s) {
   const int64_t total = B * h * w;
   const int bs = 256;
   if (prec == MCI_F64)
     hipLaunchKernelGGL((k_fd_channels<double, double>), dim3(grid_for(total, bs)), dim3(bs), 0, s,
-                       (const double*)x, (double*)G, B, h, w, along_cols, offs);
+                       (const double*)x, (double*)G, B, h, w, along_cols, offs, M);
   else if (store_in == ST_F16)
     hipLaunchKernelGGL((k_fd_channels<float, __half>), dim3(grid_for(total, bs)), dim3(bs), 0, s,
-                       (const __half*)x, (float*)G, B, h, w, along_cols, offs);
+                       (const __half*)x, (float*)G, B, h, w, along_cols, offs, M);
   else
     hipLaunchKernelGGL((k_fd_channels<float, float>), dim3(grid_for(total, bs)), dim3(bs), 0, s,
-                       (const float*)x, (float*)G, B, h, w, along_cols, offs);
+                       (const float*)x, (float*)G, B, h, w, along_cols, offs, M);
   return hipGetLastError();
 }
 

@@ -264,6 +264,29 @@ def test_2d_line_pass_parity(torch_cuda, h, w, s):
     assert np.abs(hr[:, ::s, ::s] - lr).max() <= 1e-5
 
 
+@pytest.mark.parametrize("h,w,s", [(64, 64, 3), (96, 128, 3), (48, 40, 3), (128, 128, 2), (64, 32, 4)])
+def test_2d_three_channels_parity(torch_cuda, h, w, s):
+    """Channels {x, Dx, D2x} per line (Section 5.2's experiments: x3), through the line passes
+    (sides in the line-length set) or the multi-pass route (a side of 40), against the FP64
+    oracle; the output passes through the samples."""
+    from paper_1802_10291_amd import Plan2D
+    lr = SI.random_field_images(21, 2, h, w)
+    plan = Plan2D(h, w, s, channels=3)
+    assert plan.info.path == (0 if 40 in (h, w) else 1)
+    hr = plan.upsample(torch_cuda.from_numpy(lr).cuda()).cpu().numpy().astype(np.float64)
+    want = O.upsample_2d(lr.astype(np.float64), s, M=3)
+    assert rel_l2(hr, want).max() <= 1e-5
+    assert np.abs(hr[:, ::s, ::s] - lr).max() <= 1e-5
+
+
+def test_2d_three_channels_fp64_exact(torch_cuda):
+    from paper_1802_10291_amd import Plan2D
+    lr = SI.random_field_images(22, 2, 30, 36).astype(np.float64)
+    plan = Plan2D(30, 36, 3, precision="f64", channels=3)
+    hr = plan.upsample(torch_cuda.from_numpy(lr).cuda()).cpu().numpy()
+    assert rel_l2(hr, O.upsample_2d(lr, 3, M=3)).max() <= 1e-12
+
+
 def test_2d_line_pass_ragged_batch(torch_cuda):
     """Batch sizes that leave partial 32-line blocks in the row pass."""
     from paper_1802_10291_amd import Plan2D

@@ -133,3 +133,15 @@ def test_batch_and_variant_arguments_rejected_without_device():
     assert (a.value, b.value, c.value) == (0, 0, 0)
     assert lib.mci_reconstruct_batch(h, None, None, None, 0, None) == 0
     assert lib.mci_batch_destroy(h) == 0
+
+
+def test_2d_descriptor_channels_validated_without_device():
+    L = _lib()
+    lib = L.load()
+    d = L.mci_plan2d_desc()
+    d.h, d.w, d.scale, d.precision, d.storage = 16, 16, 3, L.MCI_F32, L.MCI_STORE_NATIVE
+    h = ctypes.c_void_p()
+    for bad in (1, 4, -1):
+        d.channels = bad
+        assert lib.mci_plan_2d(ctypes.byref(d), 0, ctypes.byref(h)) == 1
+        assert "channels" in lib.mci_last_error().decode()
