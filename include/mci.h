@@ -190,11 +190,11 @@ typedef enum {
   MCI_VARIANT_TWO_PASS = 5,     /* multi-pass path with each transform of length A B (A, B in
                                    {32, 48, 64, 96, 128, 192, 256, 384, 512}) in two LDS passes
                                    (one for a single such length); other lengths radix-8 */
-  MCI_VARIANT_REAL_TWO_PASS = 6, /* real mode, FP32 storage, even N and n_out with n_out/2 as
-                                   above: channel DFTs of the sample rows read as N/2 complex
-                                   pairs, apply, real part and a 2-phase polyphase gather in one
-                                   kernel, one inverse transform of length n_out/2 written as
-                                   the output row */
+  MCI_VARIANT_REAL_TWO_PASS = 6, /* FP32 plans in real mode (FP32 or FP16 storage) with even
+                                   n_out and n_out/2 as above: channel DFTs straight from the
+                                   sample rows (read as N/2 complex pairs for even N), apply, real
+                                   part and a 2-phase polyphase gather in one kernel, one inverse
+                                   transform of length n_out/2 written as the output row */
   MCI_NUM_VARIANTS = 7
 } mci_variant;
 

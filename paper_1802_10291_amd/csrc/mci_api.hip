@@ -199,12 +199,13 @@ struct DevBufs {
   }
 };
 
-// Tables of the real-mode multi-kernel path, when the plan qualifies (FP32 storage and
-// arithmetic, real mode, even N and n_out, n_out / 2 a one- or two-pass length).
+// Tables of the real-mode multi-kernel path, when the plan qualifies (FP32 arithmetic, FP32 or
+// FP16 storage, real mode, even n_out with n_out / 2 a one- or two-pass length).
 static mci_status build_real_path(mci_plan_s* p) {
   const mci_plan_desc& d = p->d;
   int fa, fb;
-  if (p->prec != MCI_F32 || p->store != ST_F32 || !d.real_io || d.n_out % 2 || !two_pass_factors(d.n_out / 2, fa, fb))
+  if (p->prec != MCI_F32 || (p->store != ST_F32 && p->store != ST_F16) || !d.real_io || d.n_out % 2 ||
+      !two_pass_factors(d.n_out / 2, fa, fb))
     return MCI_OK;
   // even N: rows read as N/2 complex pairs; odd N: the length-N transform of the real row
   const bool half = d.N % 2 == 0;
@@ -231,6 +232,7 @@ static mci_status build_real_path(mci_plan_s* p) {
   RealPath& r = p->real;
   r.M = d.M; r.n_ops = d.n_ops; r.N = N; r.H = H; r.n1 = d.n1; r.n_out = d.n_out; r.P = P; r.K = K;
   r.half = half;
+  r.f16 = p->store == ST_F16;
   r.fwd = &p->rfwd; r.inv = &p->rinv;
   r.tab = (const float2*)p->tab; r.wN = (const float2*)p->r_wN; r.Wo = (const float2*)p->r_Wo;
   r.ok = true;

@@ -39,6 +39,9 @@ struct LineXform {
   // input is real (float): position p reads (in[p], 0) for p < len_in, else 0; in_sig, in_tr
   // and the input offsets are then in real elements
   bool real_in = false;
+  // FP16 storage of the input (the first pass reads it) or of the output (the last pass
+  // writes it); offsets and strides stay in elements of the stored type
+  bool in_half = false, out_half = false;
 };
 hipError_t fft_lines(const LineXform& x, hipStream_t s);
 

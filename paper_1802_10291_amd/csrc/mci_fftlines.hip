@@ -9,6 +9,7 @@
 // with the register-staged line FFT; where the 16 lines are interleaved in memory (element
 // stride > 1, line stride 1) they go through an LDS tile, so every global access is a run
 // of 16 consecutive complex values.  A length that is itself a line length takes one pass.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,19 +55,26 @@ struct LinesArgs {
   const float2* pre;        // input position p: p < len_in ? in * pre[p] : 0 (if pre), else in
   int64_t len_in;           // with pre or real input: positions at or beyond it read as zero
   const float2* post;       // output position k multiplied by post[k], or null
-  int real_in;              // input holds real values (float): position p reads (in[p], 0)
+  int real_in;              // input holds real values: position p reads (in[p], 0)
+  int in_half, out_half;    // input / output stored as FP16 (half2 pairs, or halves for real input)
 };
 
-// input position p of a transform starting at `base` (complex or real elements)
-__device__ __forceinline__ float2 load_in(const LinesArgs& a, const void* base, int64_t p) {
+// input position p of the transform whose first element is element `base` of the input
+__device__ __forceinline__ float2 load_in(const LinesArgs& a, int64_t base, int64_t p) {
+  const int64_t q = base + p;
   if (a.real_in) {
     if (p >= a.len_in) return make_float2(0.f, 0.f);
-    const float x = ((const float*)base)[p];
+    const float x = a.in_half ? __half2float(((const __half*)a.in)[q]) : ((const float*)a.in)[q];
     return a.pre ? make_float2(x * a.pre[p].x, x * a.pre[p].y) : make_float2(x, 0.f);
   }
-  if (!a.pre) return ((const float2*)base)[p];
-  if (p >= a.len_in) return make_float2(0.f, 0.f);
-  return cmul(((const float2*)base)[p], a.pre[p]);
+  if (a.pre && p >= a.len_in) return make_float2(0.f, 0.f);
+  const float2 v = a.in_half ? __half22float2(((const __half2*)a.in)[q]) : a.in[q];
+  return a.pre ? cmul(v, a.pre[p]) : v;
+}
+
+__device__ __forceinline__ void store_out(const LinesArgs& a, int64_t q, float2 w) {
+  if (a.out_half) ((__half2*)a.out)[q] = __float22half2_rn(w);
+  else a.out[q] = w;
 }
 
 // IN_T / OUT_T: the 16 lines of the workgroup are interleaved (line stride 1, element stride
@@ -83,7 +91,7 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
   const int64_t t0 = (int64_t)blockIdx.x * FL;
   if constexpr (IN_T) {
     const int64_t tr = t0 / a.U, u0 = t0 - tr * a.U;
-    const void* base = a.real_in ? (const void*)((const float*)a.in + a.si.base(tr)) : (const void*)(a.in + a.si.base(tr));
+    const int64_t base = a.si.base(tr);
     for (int e = tid; e < N * FL; e += NT) {
       const int n = e / FL, c = e % FL;
       sml[c * TS + n] = load_in(a, base, u0 + c + n * a.e_in);
@@ -95,9 +103,7 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
       float2 v = make_float2(0.f, 0.f);
       if (t < a.n_lines) {
         const int64_t tr = t / a.U, u = t - tr * a.U;
-        const void* base =
-            a.real_in ? (const void*)((const float*)a.in + a.si.base(tr)) : (const void*)(a.in + a.si.base(tr));
-        v = load_in(a, base, u * a.u_in + n);
+        v = load_in(a, a.si.base(tr), u * a.u_in + n);
       }
       sml[c * TS + n] = v;
     }
@@ -125,21 +131,21 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
     for (int c = 0; c < E; ++c) sml[(l + G * c) * OS + g] = v[c];
     __syncthreads();
     const int64_t tr0 = t0 / a.U, u0 = t0 - tr0 * a.U;
-    float2* base = a.out + a.so.base(tr0);
+    const int64_t base = a.so.base(tr0);
     for (int e = tid; e < N * FL; e += NT) {
       const int k = e / FL, c = e % FL;
       const int64_t q = u0 + c + k * a.e_out;
       float2 w = sml[k * OS + c];
       if (a.post) w = cmul(w, a.post[q]);
-      base[q] = w;
+      store_out(a, base + q, w);
     }
   } else {
     if (t < a.n_lines) {
-      float2* o = a.out + a.so.base(tr);
+      const int64_t base = a.so.base(tr);
 #pragma unroll
       for (int c = 0; c < E; ++c) {
         const int64_t q = u * a.u_out + l + G * c;
-        o[q] = a.post ? cmul(v[c], a.post[q]) : v[c];
+        store_out(a, base + q, a.post ? cmul(v[c], a.post[q]) : v[c]);
       }
     }
   }
@@ -241,7 +247,8 @@ hipError_t fft_lines(const LineXform& x, hipStream_t s) {
   si.offs = x.in_offs; si.side = 0; si.div = x.real_in ? 1 : 2; si.per = x.in_per; si.sig = x.in_sig; si.tr = x.in_tr;
   so.offs = x.out_offs; so.side = 1; so.per = x.out_per; so.sig = x.out_sig; so.tr = x.out_tr;
   if (A == 1) {
-    fl::LinesArgs a{x.in, x.out, x.count, 1, si, so, 0, 1, 0, 1, x.twB, nullptr, x.pre, x.len_in, x.post, x.real_in};
+    fl::LinesArgs a{x.in, x.out, x.count, 1, si, so, 0, 1, 0, 1, x.twB, nullptr, x.pre, x.len_in, x.post, x.real_in,
+                    x.in_half, x.out_half};
     return fl::run(B, x.sign, 0, a, s, false);
   }
   const int64_t L = (int64_t)A * B;
@@ -249,11 +256,12 @@ hipError_t fft_lines(const LineXform& x, hipStream_t s) {
   dense.per = 1; dense.sig = L;
   // pass 1: A lines x[a + A b] of length B, twiddled, to tmp[k_b A + a]
   fl::LinesArgs p1{x.in, x.tmp, x.count * A, A, si, dense, 1, A, 1, A, x.twB, x.twL, x.pre, x.len_in, nullptr,
-                   x.real_in};
+                   x.real_in, x.in_half, 0};
   hipError_t e = fl::run(B, x.sign, 1, p1, s, false);
   if (e != hipSuccess) return e;
   // pass 2: B contiguous lines tmp[k_b A + a] of length A, to out[k_b + B k_a]
-  fl::LinesArgs p2{x.tmp, x.out, x.count * B, B, dense, so, A, 1, 1, B, x.twA, nullptr, nullptr, 0, x.post, 0};
+  fl::LinesArgs p2{x.tmp, x.out, x.count * B, B, dense, so, A, 1, 1, B, x.twA, nullptr, nullptr, 0, x.post, 0, 0,
+                   x.out_half};
   return fl::run(A, x.sign, 2, p2, s, false);
 }
 

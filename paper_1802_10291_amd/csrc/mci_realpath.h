@@ -8,6 +8,7 @@ namespace mci {
 
 struct RealPath {
   bool ok = false;
+  bool f16 = false;                // FP16 storage of samples and outputs (arithmetic FP32)
   bool half = true;               // true: rows read as N/2 complex pairs (even N); false: the
                                   // full length-N transform of the real row (fwd has length N)
   int M = 0, n_ops = 0;
@@ -20,7 +21,7 @@ struct RealPath {
 };
 
 size_t real_path_workspace(const RealPath& r, int64_t batch);
-// g: FP32 [batch][M][N] (or per-instance offsets), y: FP32 [batch][n_ops][n_out]
+// g: [batch][M][N] (or per-instance offsets), y: [batch][n_ops][n_out], FP32 or (f16) FP16
 hipError_t run_real_1d(const RealPath& r, const void* g, void* y, int64_t batch, void* ws, const int64_t* offs,
                        hipStream_t s);
 

@@ -120,6 +120,7 @@ hipError_t run_real_1d(const RealPath& r, const void* g, void* y, int64_t batch,
   const int64_t L_in = r.half ? r.H : r.N;   // complex pairs, or real samples, per row
   x.in_offs = offs; x.in_per = r.M; x.in_sig = r.M * L_in; x.in_tr = L_in;
   x.real_in = !r.half;
+  x.in_half = r.f16;
   x.len_in = L_in;
   x.out_sig = Lz;
   if (f.blue) {
@@ -149,6 +150,7 @@ hipError_t run_real_1d(const RealPath& r, const void* g, void* y, int64_t batch,
   o.twA = (const float2*)v.twA; o.twB = (const float2*)v.twB; o.twL = (const float2*)v.tw;
   o.in_sig = r.P;
   o.out_offs = offs; o.out_per = r.n_ops; o.out_sig = r.n_ops * r.P; o.out_tr = r.P;
+  o.out_half = r.f16;
   return fft_lines(o, s);
 }
 

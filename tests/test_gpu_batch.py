@@ -151,6 +151,20 @@ def test_real_two_pass_matches_oracle(torch_cuda, N, n_out, M, n1):
             assert rel(y[b], want[b]) <= 1e-5, b
 
 
+@pytest.mark.parametrize("N,n_out,M", [(1024, 4096, 2), (683, 8192, 3), (1366, 16384, 3), (512, 2048, 4)])
+def test_real_two_pass_f16_storage(torch_cuda, N, n_out, M):
+    """The real-mode path with FP16 samples and outputs (pairs read by the first pass, the last
+    pass writes half2), derivative channels in units of N; within FP16 rounding of the oracle."""
+    from paper_1802_10291_amd import Plan1D
+    g = S.smooth_noisy_batch(80, 3, M, N, 2 * M * N, dtype=np.float16, deriv_scale=N)
+    plan = Plan1D(N=N, n_out=n_out, channels=[("table", t) for t in scaled_deriv_tables(M, N)], storage="f16")
+    plan.set_variant("real_two_pass")
+    y = plan.reconstruct(torch_cuda.from_numpy(g).cuda()).cpu().numpy().astype(np.float64)
+    want = oracle_1d(g, M, N, n_out, scaled=True)
+    for b in range(3):
+        assert rel(y[b], want[b]) <= 1e-3, b
+
+
 def test_2d_variants_match_oracle(torch_cuda):
     from paper_1802_10291_amd import Plan2D
     lr = SI.random_field_images(3, 2, 64, 64)
