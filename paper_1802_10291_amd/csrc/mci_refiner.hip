@@ -103,29 +103,53 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tx0 = blockIdx.x * T, ty0 = blockIdx.y * T, b = blockIdx.z;
   const int H = a.H, W = a.W;
-  // ---- halo tile (zero outside the image)
+  const int px = lane & 15, kb = lane >> 4;
+  // ---- weights of every tap first: their loads overlap the tile's
+  constexpr int NTAP = INM == IN32 ? 9 : 1;
+  bf16x8 bw[NTAP][NB];
+#pragma unroll
+  for (int tap = 0; tap < NTAP; ++tap)
+#pragma unroll
+    for (int n = 0; n < NB; ++n)
+      bw[tap][n] = INM == IN32 ? *(const bf16x8*)(a.w + ((16 * n + px) * 9 + tap) * C + 8 * kb)
+                               : *(const bf16x8*)(a.w + (16 * n + px) * 32 + 8 * kb);
+  // ---- halo tile (zero outside the image): every load issued before the first LDS write
+  constexpr int CH = HT * HT * 4, IT = (CH + NT - 1) / NT;
   if constexpr (INM == IN32) {
     const bf16* in = (const bf16*)a.in + (size_t)b * H * W * C;
-    for (int e = tid; e < HT * HT * 4; e += NT) {       // 16-byte chunks: 4 per pixel
+    uint4 v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {            // 16-byte chunks: 4 per pixel
+      const int e = tid + NT * it;
       const int pix = e >> 2, part = e & 3;
       const int y = ty0 - 1 + pix / HT, x = tx0 - 1 + pix % HT;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (y >= 0 && y < H && x >= 0 && x < W) v = *(const uint4*)(in + ((size_t)y * W + x) * C + part * 8);
-      *(uint4*)(tin + pix * C + part * 8) = v;
+      v[it] = make_uint4(0, 0, 0, 0);
+      if (e < CH && y >= 0 && y < H && x >= 0 && x < W) v[it] = *(const uint4*)(in + ((size_t)y * W + x) * C + part * 8);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + NT * it;
+      if (e < CH) *(uint4*)(tin + (e >> 2) * C + (e & 3) * 8) = v[it];
     }
   } else {
     const float* in = (const float*)a.in + (size_t)b * 3 * H * W;
-    for (int e = tid; e < HT * HT * 4; e += NT) {
+    float v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + NT * it;
       const int pix = e >> 2, ci = e & 3;
       const int y = ty0 - 1 + pix / HT, x = tx0 - 1 + pix % HT;
-      float v = 0.f;
-      if (ci < 3 && y >= 0 && y < H && x >= 0 && x < W) v = in[((size_t)ci * H + y) * W + x];
-      tin[pix * 4 + ci] = tobf(v);
+      v[it] = 0.f;
+      if (e < CH && ci < 3 && y >= 0 && y < H && x >= 0 && x < W) v[it] = in[((size_t)ci * H + y) * W + x];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + NT * it;
+      if (e < CH) tin[e] = tobf(v[it]);
     }
   }
   __syncthreads();
   // ---- MFMA: wave handles tile rows 4 wave .. 4 wave + 3
-  const int px = lane & 15, kb = lane >> 4;
   f4 acc[4][NB];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
@@ -135,21 +159,16 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap % 3;
-      bf16x8 bw[NB];
-#pragma unroll
-      for (int n = 0; n < NB; ++n) bw[n] = *(const bf16x8*)(a.w + ((16 * n + px) * 9 + tap) * C + 8 * kb);
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int row = 4 * wave + m;
         const bf16x8 av = *(const bf16x8*)(tin + ((row + dy) * HT + (px + dx)) * C + 8 * kb);
 #pragma unroll
-        for (int n = 0; n < NB; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[n], acc[m][n], 0, 0, 0);
+        for (int n = 0; n < NB; ++n)
+          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[tap][n], acc[m][n], 0, 0, 0);
       }
     }
   } else {
-    bf16x8 bw[NB];
-#pragma unroll
-    for (int n = 0; n < NB; ++n) bw[n] = *(const bf16x8*)(a.w + (16 * n + px) * 32 + 8 * kb);
     // this lane's 8 (tap, channel) slots k = 8 kb + j
     int off[8], chn[8];
 #pragma unroll
@@ -165,7 +184,7 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) av[j] = off[j] >= 0 ? tin[(row * HT + px + off[j]) * 4 + chn[j]] : tobf(0.f);
 #pragma unroll
-      for (int n = 0; n < NB; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[n], acc[m][n], 0, 0, 0);
+      for (int n = 0; n < NB; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[0][n], acc[m][n], 0, 0, 0);
     }
   }
   // ---- epilogue: D[pixel = 4 kb + i][co = px + 16 n] of tile row 4 wave + m
@@ -678,7 +697,8 @@ mci_status mci_refiner_forward(mci_refiner_t r, const float* u, float* y, int64_
   if (!workspace || ws_bytes < ws.bytes) return rfail(MCI_E_INVALID_ARG, "workspace too small");
   if (apply_fallback && (!ratio || !used)) return rfail(MCI_E_INVALID_ARG, "fallback needs ratio and used arrays");
   RHIP(hipSetDevice(r->device));
-  // the weight-gradient partials buffer (unused by a forward call) takes the ratio's per-tile sums
+  // the weight-gradient partials buffer (unused by a forward call) takes the ratio's
+  // per-tile sums
   RHIP(ref_forward(r, u, y, batch, h, w, ws, stream, ratio ? ws.part : nullptr));
   if (ratio) {
     const int64_t per = 3 * (int64_t)h * w;

@@ -199,3 +199,23 @@ def test_refiner_training_beats_plain_mci(torch_cuda):
     print(f"PSNR MCI {p_mci:.3f} dB, refined {p_ref:.3f} dB")
     assert frac == 1.0 and tau > 0
     assert p_ref > p_mci
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("H,W", [(64, 48), (37, 50)])
+def test_forward_output_matches_training_loss(torch_cuda, H, W):
+    """The inference forward (with the ratio's per-tile sums in its last epilogue) and the
+    forward inside a training step run the same layer kernels, so the training loss equals
+    the squared error of the inference output (up to the order of the loss reduction), on
+    tiled and ragged image sizes."""
+    from paper_1802_10291_amd import Refiner
+    torch = torch_cuda
+    rng = np.random.default_rng(H * W)
+    r = Refiner(seed=3)
+    r.set_params(random_params(19).astype(np.float32))
+    u = torch.from_numpy(rng.uniform(size=(3, 3, H, W)).astype(np.float32)).cuda()
+    hr = torch.from_numpy(rng.uniform(size=(3, 3, H, W)).astype(np.float32)).cuda()
+    y, _, _ = r.forward(u)
+    loss = float(r.backward(u, hr))
+    want = float(((y.double() - hr.double()) ** 2).mean())
+    assert loss == pytest.approx(want, rel=1e-5)
