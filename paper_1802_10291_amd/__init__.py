@@ -66,6 +66,34 @@ class _Variants:
         raise NotImplementedError
 
 
+def _desc_1d(N, n_out, channels, ops, n1, real, precision, storage, allow_singular_zero, cond_max):
+    """An mci_plan_desc, and the host channel tables it points to (kept alive by the caller)."""
+    d = _lib.mci_plan_desc()
+    d.M = len(channels)
+    d.n_ops = len(ops)
+    d.N = int(N)
+    d.n1 = _lib.MCI_N1_DEFAULT if n1 is None else int(n1)
+    d.n_out = int(n_out)
+    tables = []
+    for k, (kind, arg) in enumerate(channels):
+        d.ch[k].kind = _KINDS[kind]
+        if kind == "table":
+            t = np.ascontiguousarray(np.asarray(arg, dtype=np.complex128).ravel().view(np.float64))
+            tables.append(t)
+            d.ch[k].table = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            d.ch[k].order = int(arg)
+    for o, (op, order) in enumerate(ops):
+        d.ops[o] = _OPS[op]
+        d.op_orders[o] = int(order)
+    d.real_io = 1 if real else 0
+    d.precision = {"f32": _lib.MCI_F32, "f64": _lib.MCI_F64}[precision]
+    d.storage = {"native": _lib.MCI_STORE_NATIVE, "f16": _lib.MCI_STORE_F16}[storage]
+    d.flags = _lib.MCI_ALLOW_SINGULAR_ZERO if allow_singular_zero else 0
+    d.cond_max = float(cond_max)
+    return d, tables
+
+
 class Plan1D(_Variants):
     """A 1-D reconstruction plan (``mci_plan``).
 
@@ -77,29 +105,8 @@ class Plan1D(_Variants):
     def __init__(self, N: int, n_out: int, channels: Sequence[Channel], ops: Sequence[Tuple[str, int]] = (("identity", 0),),
                  n1: Optional[int] = None, real: bool = True, precision: str = "f32", storage: str = "native",
                  allow_singular_zero: bool = False, cond_max: float = 0.0, device: int = 0):
-        d = _lib.mci_plan_desc()
-        d.M = len(channels)
-        d.n_ops = len(ops)
-        d.N = int(N)
-        d.n1 = _lib.MCI_N1_DEFAULT if n1 is None else int(n1)
-        d.n_out = int(n_out)
-        self._tables = []
-        for k, (kind, arg) in enumerate(channels):
-            d.ch[k].kind = _KINDS[kind]
-            if kind == "table":
-                t = np.ascontiguousarray(np.asarray(arg, dtype=np.complex128).ravel().view(np.float64))
-                self._tables.append(t)
-                d.ch[k].table = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-            else:
-                d.ch[k].order = int(arg)
-        for o, (op, order) in enumerate(ops):
-            d.ops[o] = _OPS[op]
-            d.op_orders[o] = int(order)
-        d.real_io = 1 if real else 0
-        d.precision = {"f32": _lib.MCI_F32, "f64": _lib.MCI_F64}[precision]
-        d.storage = {"native": _lib.MCI_STORE_NATIVE, "f16": _lib.MCI_STORE_F16}[storage]
-        d.flags = _lib.MCI_ALLOW_SINGULAR_ZERO if allow_singular_zero else 0
-        d.cond_max = float(cond_max)
+        d, self._tables = _desc_1d(N, n_out, channels, ops, n1, real, precision, storage, allow_singular_zero,
+                                   cond_max)
         self.desc = d
         self.M, self.N, self.n_out, self.n_ops, self.real = d.M, int(N), int(n_out), d.n_ops, real
         self.precision, self.storage, self.device = precision, storage, device
@@ -150,6 +157,65 @@ class Plan1D(_Variants):
     def close(self):
         if getattr(self, "handle", None):
             mci_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class OffGrid:
+    """Evaluation of the reconstruction at arbitrary points t (``mci_offgrid_plan`` /
+    ``mci_evaluate_1d``): the same channels, band and output operators as :class:`Plan1D`,
+    evaluated by a nonuniform FFT of kernel width ``width`` (0: 8 for FP32, 16 for FP64)."""
+
+    def __init__(self, N: int, channels: Sequence[Channel], ops: Sequence[Tuple[str, int]] = (("identity", 0),),
+                 n1: Optional[int] = None, real: bool = True, precision: str = "f32", width: int = 0,
+                 allow_singular_zero: bool = False, cond_max: float = 0.0, device: int = 0):
+        d, self._tables = _desc_1d(N, 1, channels, ops, n1, real, precision, "native", allow_singular_zero,
+                                   cond_max)
+        self.M, self.N, self.n_ops, self.real = d.M, int(N), d.n_ops, real
+        self.precision, self.device = precision, device
+        self.handle = _lib.mci_offgrid_plan(d, width, device)
+        self.grid_len, self.width, self.beta, grid_plan = _lib.mci_offgrid_info(self.handle)
+        self._ws = None
+
+    def io_dtype(self):
+        torch = _torch()
+        return torch.float64 if self.precision == "f64" else torch.float32
+
+    def evaluate(self, g, t, out=None):
+        """g: cuda tensor [batch, M, N] (real) or [batch, M, N, 2]; t: float64 cuda tensor
+        [n_t] (the same points for every signal) or [batch, n_t].  Returns
+        [batch, n_ops, n_t] (or [..., 2])."""
+        torch = _torch()
+        if not g.is_cuda or not t.is_cuda:
+            raise ValueError("g and t must be device tensors")
+        tail = (self.M, self.N) if self.real else (self.M, self.N, 2)
+        if tuple(g.shape[1:]) != tail or g.dtype != self.io_dtype() or not g.is_contiguous():
+            raise ValueError(f"g must be contiguous {self.io_dtype()} [batch, {', '.join(map(str, tail))}]")
+        batch = g.shape[0]
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.dim() not in (1, 2) or \
+                (t.dim() == 2 and t.shape[0] != batch):
+            raise ValueError("t must be contiguous float64 [n_t] or [batch, n_t]")
+        n_t = t.shape[-1]
+        shape = (batch, self.n_ops, n_t) if self.real else (batch, self.n_ops, n_t, 2)
+        if out is None:
+            out = torch.empty(shape, dtype=self.io_dtype(), device=g.device)
+        elif tuple(out.shape) != shape or out.dtype != self.io_dtype() or not out.is_contiguous():
+            raise ValueError("bad out tensor")
+        need = _lib.mci_offgrid_workspace_size(self.handle, batch)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+        _lib.mci_evaluate_1d(self.handle, g.data_ptr(), t.data_ptr(), n_t, t.dim() == 1, out.data_ptr(), batch,
+                             self._ws.data_ptr(), need, _stream_handle(g.device))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mci_offgrid_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

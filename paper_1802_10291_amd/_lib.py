@@ -71,7 +71,8 @@ class mci_batch_item(ctypes.Structure):
 EXPORTS = ["mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_workspace_size", "mci_reconstruct_1d",
            "mci_plan_2d", "mci_upsample_2d", "mci_status_string", "mci_last_error", "mci_plan_variants",
            "mci_plan_set_variant", "mci_plan_autotune", "mci_batch_create", "mci_batch_destroy", "mci_batch_sizes",
-           "mci_reconstruct_batch"]
+           "mci_reconstruct_batch", "mci_offgrid_plan", "mci_offgrid_destroy", "mci_offgrid_info",
+           "mci_offgrid_workspace_size", "mci_evaluate_1d"]
 
 _lib = None
 
@@ -115,6 +116,14 @@ def load(path: str = LIB_PATH):
     lib.mci_batch_destroy.argtypes = [vp]
     lib.mci_batch_sizes.argtypes = [vp, P(i64), P(i64), P(sz)]
     lib.mci_reconstruct_batch.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.mci_offgrid_plan.argtypes = [P(mci_plan_desc), i32, i32, P(vp)]
+    lib.mci_offgrid_destroy.argtypes = [vp]
+    lib.mci_offgrid_info.argtypes = [vp, P(i64), P(ctypes.c_int32), P(ctypes.c_double), P(vp)]
+    lib.mci_offgrid_workspace_size.argtypes = [vp, i64, P(sz)]
+    lib.mci_evaluate_1d.argtypes = [vp, vp, vp, i64, i32, vp, i64, vp, sz, vp]
+    for name in ("mci_offgrid_plan", "mci_offgrid_destroy", "mci_offgrid_info", "mci_offgrid_workspace_size",
+                 "mci_evaluate_1d"):
+        getattr(lib, name).restype = i32
     for name in ("mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_workspace_size", "mci_reconstruct_1d",
                  "mci_plan_2d", "mci_upsample_2d", "mci_plan_variants", "mci_plan_set_variant", "mci_plan_autotune",
                  "mci_batch_create", "mci_batch_destroy", "mci_batch_sizes", "mci_reconstruct_batch"):
@@ -207,6 +216,36 @@ def mci_batch_sizes(batch: int):
 
 def mci_reconstruct_batch(batch: int, in_ptr: int, out_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
     check(load().mci_reconstruct_batch(batch, in_ptr, out_ptr, ws_ptr, ws_bytes, stream), "mci_reconstruct_batch")
+
+
+def mci_offgrid_plan(desc: mci_plan_desc, width: int = 0, device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    check(load().mci_offgrid_plan(ctypes.byref(desc), width, device, ctypes.byref(h)), "mci_offgrid_plan")
+    return h.value
+
+
+def mci_offgrid_destroy(plan: int) -> None:
+    check(load().mci_offgrid_destroy(plan), "mci_offgrid_destroy")
+
+
+def mci_offgrid_info(plan: int):
+    """(grid length L, width w, beta, handle of the grid plan)"""
+    L, w, beta, g = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_void_p()
+    check(load().mci_offgrid_info(plan, ctypes.byref(L), ctypes.byref(w), ctypes.byref(beta), ctypes.byref(g)),
+          "mci_offgrid_info")
+    return L.value, w.value, beta.value, g.value
+
+
+def mci_offgrid_workspace_size(plan: int, batch: int) -> int:
+    n = ctypes.c_size_t()
+    check(load().mci_offgrid_workspace_size(plan, batch, ctypes.byref(n)), "mci_offgrid_workspace_size")
+    return n.value
+
+
+def mci_evaluate_1d(plan: int, g_ptr: int, t_ptr: int, n_t: int, t_shared: bool, y_ptr: int, batch: int,
+                    ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    check(load().mci_evaluate_1d(plan, g_ptr, t_ptr, n_t, 1 if t_shared else 0, y_ptr, batch, ws_ptr, ws_bytes,
+                                 stream), "mci_evaluate_1d")
 
 
 # ----------------------------------------------------------------------------- refiner

@@ -59,6 +59,8 @@ static int64_t next_7smooth(int64_t n) {
   }
 }
 
+int64_t mci::next_smooth_length(int64_t n) { return next_7smooth(n); }
+
 template <typename C>
 static void* upload(const std::vector<std::complex<double>>& v, hipError_t& err) {
   std::vector<C> h(v.size());
@@ -239,7 +241,7 @@ static mci_status build_real_path(mci_plan_s* p) {
   return MCI_OK;
 }
 
-static mci_status build_plan(const mci_plan_desc* desc, int device, mci_plan_s** out) {
+mci_status mci::build_plan(const mci_plan_desc* desc, int device, mci_plan_s** out, const std::vector<double>* oscale) {
   mci_status st = validate(desc);
   if (st != MCI_OK) return st;
   int ndev = 0;
@@ -290,6 +292,16 @@ static mci_status build_plan(const mci_plan_desc* desc, int device, mci_plan_s**
   for (int o = 0; o < n_ops; ++o) { a.ops[o] = desc->ops[o]; a.op_orders[o] = desc->op_orders[o]; }
   a.tables = d_tables; a.tab64 = tab64; a.tab32 = tab32; a.cond = cond; a.sing = sing;
   a.allow_zero = (desc->flags & MCI_ALLOW_SINGULAR_ZERO) ? 1 : 0;
+  if (oscale) {
+    if ((int64_t)oscale->size() != mu) { destroy_plan(p); return fail(MCI_E_INVALID_ARG, "output scale length"); }
+    double* d_os = (double*)tmp.alloc((size_t)mu * sizeof(double), e);
+    if (!d_os) { destroy_plan(p); return fail(MCI_E_OUT_OF_MEMORY, "output scale"); }
+    if ((e = hipMemcpy(d_os, oscale->data(), (size_t)mu * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) {
+      destroy_plan(p);
+      return fail(MCI_E_DEVICE, "output scale upload");
+    }
+    a.oscale = d_os;
+  }
   if ((e = launch_plan_tables(a, 0)) != hipSuccess) { destroy_plan(p); return fail(MCI_E_DEVICE, hipGetErrorString(e)); }
   std::vector<double> hc(N);
   std::vector<int> hs(N);

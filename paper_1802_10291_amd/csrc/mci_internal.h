@@ -45,6 +45,9 @@ struct PlanKernelArgs {
   double* cond;           // [N]
   int* sing;              // [N]
   int allow_zero;
+  // optional real factor per band index n - n1 (mu entries, device), multiplied into every
+  // table entry of coefficient n: the deconvolution of off-grid evaluation; null = none
+  const double* oscale = nullptr;
 };
 
 // Arguments of the generic (multi-pass) 1-D path.

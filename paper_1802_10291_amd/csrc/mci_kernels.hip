@@ -143,7 +143,8 @@ __global__ void k_plan_tables(PlanKernelArgs a) {
           q.x /= rs[m];
           q.y /= rs[m];
           const double2 o = outop_d(a.ops[op], a.op_orders[op], n + (int64_t)j * a.N);
-          t = make_double2((q.x * o.x - q.y * o.y) * invN, (q.x * o.y + q.y * o.x) * invN);
+          const double sc = a.oscale ? a.oscale[i + (int64_t)j * a.N] * invN : invN;
+          t = make_double2((q.x * o.x - q.y * o.y) * sc, (q.x * o.y + q.y * o.x) * sc);
         }
         const int64_t idx = (((int64_t)op * M + m) * M + j) * a.N + i;
         a.tab64[idx] = t;

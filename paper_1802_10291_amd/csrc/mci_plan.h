@@ -59,6 +59,13 @@ size_t plan_workspace(const mci_plan_s* p, int64_t batch);
 mci_status plan_run(const mci_plan_s* p, const void* in, void* out, int64_t batch, void* ws, const int64_t* offs,
                     hipStream_t s);
 
+// Build a 1-D plan.  oscale (mu entries, or null): a real factor per band index n - n1
+// multiplied into the apply tables (off-grid evaluation's deconvolution).
+mci_status build_plan(const mci_plan_desc* desc, int device, mci_plan_s** out,
+                      const std::vector<double>* oscale = nullptr);
+// smallest n' >= n whose prime factors are all at most 7
+int64_t next_smooth_length(int64_t n);
+
 uint32_t plan_variant_mask(const mci_plan_s* p);
 mci_status plan_set_variant(mci_plan_s* p, int v);
 // cache key of the plan's shape on the current device

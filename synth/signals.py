@@ -116,3 +116,43 @@ def smooth_noisy_batch(first: int, count: int, M: int, N: int, n_max: int, seed_
             out[s, m] = (np.fft.ifft(folded) * N).real
     del k
     return out
+
+
+# ---------------------------------------------------------------- the test signal of Section 5.1
+def phi_closed(z: np.ndarray) -> np.ndarray:
+    """The rational function phi of Section 5.1 (analytic in the closed unit disc)."""
+    return (0.08 * z**2 + 0.06 * z**10) / ((1.3 - z) * (1.5 - z)) + \
+           (0.05 * z**3 + 0.09 * z**10) / ((1.2 + z) * (1.3 + z))
+
+
+def _taylor(P, Q, nmax):
+    """Taylor coefficients of P(z)/Q(z) at 0 by the recurrence sum_j Q_j c_{n-j} = P_n."""
+    c = np.zeros(nmax + 1)
+    for n in range(nmax + 1):
+        s = P[n] if n < len(P) else 0.0
+        for j in range(1, len(Q)):
+            if n - j >= 0:
+                s -= Q[j] * c[n - j]
+        c[n] = s / Q[0]
+    return c
+
+
+def phi_coeffs(nmax: int = 700) -> np.ndarray:
+    """Power-series coefficients c_0 .. c_nmax of phi (its poles lie at |z| >= 1.2, so the
+    terms past n = 700 are below 1e-55 of the leading ones)."""
+    P1 = np.zeros(11); P1[2] = 0.08; P1[10] = 0.06
+    P2 = np.zeros(11); P2[3] = 0.05; P2[10] = 0.09
+    # (1.3 - z)(1.5 - z) = 1.95 - 2.8 z + z^2 ; (1.2 + z)(1.3 + z) = 1.56 + 2.5 z + z^2
+    return _taylor(P1, [1.95, -2.8, 1.0], nmax) + _taylor(P2, [1.56, 2.5, 1.0], nmax)
+
+
+def phi_samples(kind: str, t: np.ndarray, c: np.ndarray) -> np.ndarray:
+    """Samples at t of f = Re phi(e^{it}) (kind 'f'), its Hilbert transform Im phi(e^{it})
+    ('H'), and the derivatives f' ('d1') and f'' ('d2'), from the power series c of phi."""
+    if kind == "f":
+        return phi_closed(np.exp(1j * t)).real
+    if kind == "H":
+        return phi_closed(np.exp(1j * t)).imag
+    order = {"d1": 1, "d2": 2}[kind]
+    n = np.arange(c.size)
+    return (((1j * n) ** order) * c[None, :] * np.exp(1j * np.outer(t, n))).sum(1).real

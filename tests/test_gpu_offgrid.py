@@ -1,0 +1,206 @@
+"""Off-grid evaluation on the GPU (``mci_evaluate_1d``) against the FP64 oracle.
+
+The oracle evaluates eq. DFTexpression (with the output operator of the closing paragraph
+of Section 3) as a direct sum over the recovered band at each point
+(``recover_band`` + ``evaluate_band``, both pinned in the CPU suite).  The GPU evaluates it
+as a nonuniform FFT whose spreading kernel has width w: its relative error is about
+10^(1 - w) (the kernel's aliasing) plus the plan's rounding.
+
+Tolerances (relative L2 per result):
+  * FP64 plans, default w = 16: 1e-11 (aliasing ~1e-13, FP64 rounding ~1e-15 times the sum
+    lengths);
+  * FP32 plans, default w = 8: 1e-5 (aliasing ~1e-7, FP32 rounding as for the on-grid path);
+  * width sweeps in FP64: 10^(2 - w), one decade above the kernel's error estimate.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+_OK = {"deriv": O.MULT_DERIV, "hilbert": O.MULT_HILBERT}
+_OO = {"identity": O.OUT_IDENTITY, "hilbert": O.OUT_HILBERT, "deriv": O.OUT_DERIV}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1802_10291_amd  # noqa: F401  (fails loudly without the built library)
+    return torch
+
+
+def _oracle_eval(channels, N, n1, g, t, ops, real):
+    """[batch][n_ops][n_t] from the oracle; t is [n_t] or [batch][n_t]."""
+    ch = O.Channels(N=N, kinds=[_OK[k] for k, _ in channels], orders=[int(v) for _, v in channels], n1=n1)
+    a = O.recover_band(ch, g)
+    B = g.shape[0]
+    out = np.zeros((B, len(ops), t.shape[-1]), dtype=np.float64 if real else np.complex128)
+    for b in range(B):
+        tb = t if t.ndim == 1 else t[b]
+        for o, (op, order) in enumerate(ops):
+            out[b, o] = O.evaluate_band(a[b], ch.n1, tb, op=_OO[op], order=int(order), real=real)
+    return out
+
+
+def _run(torch, N, channels, ops, real, precision, g, t, n1=None, width=0):
+    from paper_1802_10291_amd import OffGrid
+    og = OffGrid(N=N, channels=channels, ops=ops, n1=n1, real=real, precision=precision, width=width)
+    dt = np.float64 if precision == "f64" else np.float32
+    if real:
+        gs = g.astype(dt)
+        g_ref = gs.astype(np.float64)
+    else:
+        parts = np.stack([g.real, g.imag], axis=-1).astype(dt)
+        gs = np.ascontiguousarray(parts)
+        g_ref = parts[..., 0].astype(np.float64) + 1j * parts[..., 1].astype(np.float64)
+    y = og.evaluate(torch.from_numpy(gs).cuda(), torch.from_numpy(np.ascontiguousarray(t)).cuda())
+    torch.cuda.synchronize()
+    y = y.cpu().numpy().astype(np.float64)
+    if not real:
+        y = y[..., 0] + 1j * y[..., 1]
+    return y, g_ref, og
+
+
+def _rel(y, want):
+    B, K = y.shape[0], y.shape[1]
+    y2, w2 = y.reshape(B * K, -1), want.reshape(B * K, -1)
+    return (np.linalg.norm(y2 - w2, axis=1) / np.maximum(np.linalg.norm(w2, axis=1), 1e-300)).max()
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-11), ("f32", 1e-5)])
+@pytest.mark.parametrize("shared", [True, False])
+def test_offgrid_real_matches_oracle(torch_cuda, precision, tol, shared):
+    """{f, f'} at N = 64 (band [-63, 64]), f and Hf at 1000 points (several 256-point blocks
+    and a ragged tail) spread over [-3 pi, 5 pi], shared by the batch or per signal."""
+    rng = np.random.default_rng(21 + shared)
+    channels, ops = [("deriv", 0), ("deriv", 1)], [("identity", 0), ("hilbert", 0)]
+    g = rng.standard_normal((3, 2, 64))
+    t = rng.uniform(-3 * np.pi, 5 * np.pi, size=1000 if shared else (3, 1000))
+    y, g_ref, og = _run(torch_cuda, 64, channels, ops, True, precision, g, t)
+    assert og.grid_len >= 4 * 64 + 2
+    want = _oracle_eval(channels, 64, None, g_ref, t, ops, True)
+    assert _rel(y, want) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_offgrid_complex_hilbert_channel(torch_cuda, precision, tol):
+    """Complex samples from channels {f, Hf} on the band [-N + 1, N] (it must straddle 0 for
+    the Hilbert channel, Example 3.7), outputs f and f', 777 points."""
+    rng = np.random.default_rng(5)
+    N = 45
+    channels, ops = [("deriv", 0), ("hilbert", 0)], [("identity", 0), ("deriv", 1)]
+    g = rng.standard_normal((2, 2, N)) + 1j * rng.standard_normal((2, 2, N))
+    t = rng.uniform(0, 2 * np.pi, size=777)
+    y, g_ref, og = _run(torch_cuda, N, channels, ops, False, precision, g, t, n1=-N + 1)
+    want = _oracle_eval(channels, N, -N + 1, g_ref, t, ops, False)
+    assert _rel(y, want) <= tol
+
+
+def test_offgrid_band_off_centre(torch_cuda):
+    """n1 = 0 with derivative channels (a band [0, 3N) that is not centred): the grid is
+    sized from K = max |n| = 3N - 1, so the accuracy is that of a centred band."""
+    rng = np.random.default_rng(8)
+    N = 30
+    channels, ops = [("deriv", 0), ("deriv", 1), ("deriv", 2)], [("identity", 0)]
+    g = rng.standard_normal((2, 3, N)) + 1j * rng.standard_normal((2, 3, N))
+    t = rng.uniform(-1.0, 1.0, size=300)
+    y, g_ref, og = _run(torch_cuda, N, channels, ops, False, "f64", g, t, n1=0)
+    assert og.grid_len >= 4 * (3 * N - 1) + 2
+    want = _oracle_eval(channels, N, 0, g_ref, t, ops, False)
+    assert _rel(y, want) <= 1e-11
+
+
+@pytest.mark.parametrize("width", [4, 6, 8, 12])
+def test_offgrid_width_sets_accuracy(torch_cuda, width):
+    """FP64 plans with a narrower kernel: the error follows the kernel, 10^(1 - w), within
+    a decade, and shrinks as w grows."""
+    rng = np.random.default_rng(40 + width)
+    channels, ops = [("deriv", 0), ("deriv", 1)], [("identity", 0)]
+    g = rng.standard_normal((2, 2, 100))
+    t = rng.uniform(0, 2 * np.pi, size=2000)
+    y, g_ref, og = _run(torch_cuda, 100, channels, ops, True, "f64", g, t, width=width)
+    assert og.width == width
+    want = _oracle_eval(channels, 100, None, g_ref, t, ops, True)
+    err = _rel(y, want)
+    assert err <= 10.0 ** (2 - width), err
+    assert err >= 1e-16
+
+
+def test_offgrid_on_grid_points_match_reconstruction(torch_cuda):
+    """At t_j = 2 pi j / n_out the off-grid values are the on-grid reconstruction (FP64)."""
+    from paper_1802_10291_amd import Plan1D
+    torch = torch_cuda
+    rng = np.random.default_rng(77)
+    N, n_out = 50, 360
+    channels, ops = [("deriv", 0), ("deriv", 1)], [("identity", 0), ("deriv", 1)]
+    g = rng.standard_normal((4, 2, N))
+    t = 2 * np.pi * np.arange(n_out) / n_out
+    y, _, _ = _run(torch, N, channels, ops, True, "f64", g, t)
+    plan = Plan1D(N=N, n_out=n_out, channels=channels, ops=ops, precision="f64")
+    yr = plan.reconstruct(torch.from_numpy(g).cuda()).cpu().numpy()
+    assert _rel(y, yr) <= 1e-11
+
+
+def test_offgrid_wraps_and_edges(torch_cuda):
+    """Points at multiples of 2 pi, just below 0, far outside [0, 2 pi) (1e4 periods away),
+    and an empty call."""
+    from paper_1802_10291_amd import OffGrid
+    torch = torch_cuda
+    rng = np.random.default_rng(3)
+    channels, ops = [("deriv", 0)], [("identity", 0)]
+    N = 33
+    g = rng.standard_normal((2, 1, N))
+    base = np.array([0.0, 2 * np.pi, -2 * np.pi, -1e-12, 1e-12, np.pi, 2 * np.pi - 1e-9, 1.2345])
+    t = np.concatenate([base, base + 2 * np.pi * 1e4])
+    y, g_ref, _ = _run(torch, N, channels, ops, True, "f64", g, t)
+    want = _oracle_eval(channels, N, None, g_ref, t, ops, True)
+    # the far points carry the rounding of t itself: |t| ~ 6e4, ulp 7e-12, f' ~ N |f|
+    assert _rel(y, want) <= 1e-9
+    assert np.abs(y[:, :, :8] - want[:, :, :8]).max() <= 1e-11 * np.abs(want).max()
+    og = OffGrid(N=N, channels=channels, ops=ops, precision="f64")
+    gt = torch.from_numpy(g).cuda()
+    empty = og.evaluate(gt, torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert tuple(empty.shape) == (2, 1, 0)
+    none = og.evaluate(gt[:0], torch.zeros(5, dtype=torch.float64, device="cuda"))
+    assert tuple(none.shape) == (0, 1, 5)
+
+
+def test_offgrid_rejects_bad_arguments(torch_cuda):
+    from paper_1802_10291_amd import MCIError, OffGrid
+    torch = torch_cuda
+    with pytest.raises(MCIError):
+        OffGrid(N=16, channels=[("deriv", 0)], width=20)
+    og = OffGrid(N=16, channels=[("deriv", 0)], precision="f32")
+    g = torch.zeros((2, 1, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        og.evaluate(g, torch.zeros(4, dtype=torch.float32, device="cuda"))      # t must be float64
+    with pytest.raises(ValueError):
+        og.evaluate(g, torch.zeros((3, 4), dtype=torch.float64, device="cuda"))  # batch mismatch
+
+
+def test_offgrid_full_size_sampled(torch_cuda):
+    """The batched FP32 workload shape -- {f, f', f''} with N = 1366 samples each (band 4098),
+    16384 signals -- evaluated at 8192 shared random points, checked on 6 sampled signals
+    x 512 sampled points against the oracle's direct sums."""
+    from paper_1802_10291_amd import OffGrid
+    from synth import signals as S
+    torch = torch_cuda
+    M, N, B, n_t = 3, 1366, 16384, 8192
+    channels, ops = [("deriv", 0), ("deriv", 1), ("deriv", 2)], [("identity", 0)]
+    og = OffGrid(N=N, channels=channels, ops=ops, precision="f32")
+    rng = np.random.default_rng(1234)
+    t = np.sort(rng.uniform(0, 2 * np.pi, size=n_t))
+    pool = 256
+    host = S.smooth_noisy_batch(0, pool, M, N, 8192)
+    g = torch.from_numpy(host).cuda().repeat(B // pool, 1, 1)
+    y = og.evaluate(g, torch.from_numpy(t).cuda())
+    torch.cuda.synchronize()
+    sig = rng.choice(B, size=6, replace=False)
+    pts = rng.choice(n_t, size=512, replace=False)
+    got = y[torch.from_numpy(sig).cuda()][:, :, torch.from_numpy(pts).cuda()].cpu().numpy().astype(np.float64)
+    want = _oracle_eval(channels, N, None, host[sig % pool].astype(np.float64), t[pts], ops, True)
+    assert _rel(got, want) <= 1e-5
+    assert torch.isfinite(y).all()

@@ -145,3 +145,24 @@ def test_2d_descriptor_channels_validated_without_device():
         d.channels = bad
         assert lib.mci_plan_2d(ctypes.byref(d), 0, ctypes.byref(h)) == 1
         assert "channels" in lib.mci_last_error().decode()
+
+
+def test_offgrid_arguments_rejected_without_device():
+    L = _lib()
+    lib = L.load()
+    h = ctypes.c_void_p()
+    d = _desc(L)
+    assert lib.mci_offgrid_plan(ctypes.byref(d), 1, 0, ctypes.byref(h)) == 1     # width below 2
+    assert lib.mci_offgrid_plan(ctypes.byref(d), 17, 0, ctypes.byref(h)) == 1    # width above 16
+    assert h.value is None
+    d = _desc(L, storage=L.MCI_STORE_F16)
+    assert lib.mci_offgrid_plan(ctypes.byref(d), 0, 0, ctypes.byref(h)) == 4     # MCI_E_UNSUPPORTED
+    d = _desc(L, M=0)
+    assert lib.mci_offgrid_plan(ctypes.byref(d), 0, 0, ctypes.byref(h)) == 1
+    assert lib.mci_offgrid_plan(None, 0, 0, ctypes.byref(h)) == 1
+    assert lib.mci_offgrid_plan(ctypes.byref(_desc(L)), 0, 0, None) == 1
+    assert lib.mci_offgrid_destroy(None) == 0
+    n = ctypes.c_size_t()
+    assert lib.mci_offgrid_workspace_size(None, 1, ctypes.byref(n)) == 1
+    assert lib.mci_offgrid_info(None, None, None, None, None) == 1
+    assert lib.mci_evaluate_1d(None, None, None, 1, 1, None, 1, None, 0, None) == 1

@@ -21,28 +21,9 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 # ---------------------------------------------------------------- test signal of Section 5.1
-def _taylor(P, Q, nmax):
-    """Taylor coefficients of P(z)/Q(z) at 0 by the recurrence sum_j Q_j c_{n-j} = P_n."""
-    c = np.zeros(nmax + 1)
-    for n in range(nmax + 1):
-        s = P[n] if n < len(P) else 0.0
-        for j in range(1, len(Q)):
-            if n - j >= 0:
-                s -= Q[j] * c[n - j]
-        c[n] = s / Q[0]
-    return c
-
-
-def _phi(z):
-    return (0.08 * z**2 + 0.06 * z**10) / ((1.3 - z) * (1.5 - z)) + \
-           (0.05 * z**3 + 0.09 * z**10) / ((1.2 + z) * (1.3 + z))
-
-
-def _phi_coeffs(nmax=700):
-    P1 = np.zeros(11); P1[2] = 0.08; P1[10] = 0.06
-    P2 = np.zeros(11); P2[3] = 0.05; P2[10] = 0.09
-    # (1.3 - z)(1.5 - z) = 1.95 - 2.8 z + z^2 ; (1.2 + z)(1.3 + z) = 1.56 + 2.5 z + z^2
-    return _taylor(P1, [1.95, -2.8, 1.0], nmax) + _taylor(P2, [1.56, 2.5, 1.0], nmax)
+_phi = S.phi_closed
+_phi_coeffs = S.phi_coeffs
+_phi_channel = S.phi_samples
 
 
 def test_phi_series_matches_closed_form():
@@ -51,18 +32,6 @@ def test_phi_series_matches_closed_form():
     t = np.linspace(0.0, 2 * np.pi, 41)
     ser = (c[None, :] * np.exp(1j * np.outer(t, n))).sum(1)
     assert np.abs(ser - _phi(np.exp(1j * t))).max() < 1e-13
-
-
-def _phi_channel(kind, t, c):
-    """Samples of f = Re phi(e^{it}) (kind 'f'), its Hilbert transform Im phi ('H'),
-    and the derivatives f' ('d1'), f'' ('d2') from the power series of phi."""
-    if kind == "f":
-        return _phi(np.exp(1j * t)).real
-    if kind == "H":
-        return _phi(np.exp(1j * t)).imag
-    order = {"d1": 1, "d2": 2}[kind]
-    n = np.arange(c.size)
-    return (((1j * n) ** order) * c[None, :] * np.exp(1j * np.outer(t, n))).sum(1).real
 
 
 def _load_table1():
