@@ -13,7 +13,8 @@ one JSON line with throughput (reconstructed output samples/s), the roofline of 
 dominant kernel (timed with HIP events on its stream) and the FP64 CPU oracle on a
 bounded sample of the same workload, plus the relative error of that sample.
 
-  python bench.py [--steps K] [--warmup W] [--workload batched1d|sisr2|sisr4|sisr3|refiner|uneven] [--no-cpu]
+  python bench.py [--steps K] [--warmup W] [--workload batched1d|sisr2|sisr4|sisr3|refiner|uneven|offgrid]
+                  [--no-cpu]
                   [--storage f32|f16] [--lanes 4]
 """
 import argparse
@@ -53,7 +54,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batched1d",
-                    choices=["batched1d", "sisr2", "sisr4", "sisr3", "refiner", "uneven"])
+                    choices=["batched1d", "sisr2", "sisr4", "sisr3", "refiner", "uneven", "offgrid"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16"], help="uneven: storage of the packed buffers")
     ap.add_argument("--lanes", type=int, default=4, help="uneven: concurrent lanes of the batch")
     ap.add_argument("--pairs", type=int, default=20000, help="refiner: training pairs")
@@ -199,6 +200,100 @@ def bench_batched1d(args, torch):
         result["rel_err_vs_fp64_oracle"] = {"max": float(err.max()), "median": float(np.median(err)),
                                             "signals": int(ns)}
     result["copy_bandwidth_GBs"] = copy_bandwidth(torch)
+    return result
+
+
+def bench_offgrid(args, torch):
+    """Off-grid evaluation: the batched workload's signals ({f, f', f''}, N = 1366, band 4098)
+    evaluated at 16384 seeded uniform random points in [0, 2 pi) shared by the batch."""
+    from paper_1802_10291_amd import OffGrid, _lib
+    from synth import signals as S
+
+    B = args.batch or 16384
+    M, N, n_max, n_t = 3, 1366, 8192, 16384
+    pool = min(2048, B)
+    log(f"generating {pool} seeded signals (tiled to {B})")
+    from concurrent.futures import ThreadPoolExecutor
+    host = np.empty((pool, M, N), dtype=np.float32)
+
+    def work(c):
+        n = min(256, pool - c)
+        host[c:c + n] = S.smooth_noisy_batch(c, n, M, N, n_max)
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(work, range(0, pool, 256)))
+    g = torch.from_numpy(host).cuda().repeat((B + pool - 1) // pool, 1, 1)[:B].contiguous()
+    t_host = np.random.default_rng(2024).uniform(0.0, 2 * np.pi, size=n_t)
+    t = torch.from_numpy(t_host).cuda()
+    og = OffGrid(N=N, channels=[("deriv", 0), ("deriv", 1), ("deriv", 2)], precision="f32")
+    y = torch.empty((B, 1, n_t), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    L, w = og.grid_len, og.width
+    log(f"grid length {L}, kernel width {w}")
+
+    def step():
+        og.evaluate(g, t, out=y)
+
+    wall, per = time_steps(torch, step, args.steps, args.warmup, stream)
+    ms = float(np.mean(per))
+    # the grid stage alone (the grid plan of the same off-grid plan, same input)
+    gp = _lib.mci_offgrid_info(og.handle)[3]
+    gneed = _lib.mci_workspace_size(gp, B)
+    gws = torch.empty(max(gneed, 1), dtype=torch.uint8, device="cuda")
+    gy = torch.empty((B, 1, L), dtype=torch.float32, device="cuda")
+    sh = int(stream.cuda_stream)
+
+    def grid_step():
+        _lib.mci_reconstruct_1d(gp, g.data_ptr(), gy.data_ptr(), B, gws.data_ptr(), gneed, sh)
+
+    _, gper = time_steps(torch, grid_step, args.steps, args.warmup, stream)
+    del gy, gws
+    ms_grid = float(np.mean(gper))
+    value = B * n_t * args.steps / (sum(per) * 1e-3)
+    alg_bytes = B * (M * N * 4 + n_t * 4) + n_t * 8
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    result = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"1-D off-grid FP32 MCI: {B} signals x M=3 derivative channels {{f,f',f''}} x N=1366 "
+                               f"samples (band mu=4098) evaluated at {n_t} random points shared by the batch "
+                               f"(grid {L}, kernel width {w})",
+                   "batch": B, "M": M, "N": N, "n_t": n_t, "grid_len": L, "width": w},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "whole off-grid step",
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "stages_ms": {"grid": ms_grid, "gather": ms - ms_grid},
+        # the gather stage on its own: it reads the grid once and writes the outputs
+        "gather_roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                            "algorithmic_bytes": B * (L + n_t) * 4,
+                            "achieved": B * (L + n_t) * 4 / ((ms - ms_grid) * 1e-3) / 1e9,
+                            "frac": B * (L + n_t) * 4 / ((ms - ms_grid) * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "wall_s": wall,
+    }
+    if not args.no_cpu:
+        from oracle import oracle as O
+        ch = O.Channels(N=N, kinds=[O.MULT_DERIV] * 3, orders=[0, 1, 2])
+        idx = np.linspace(0, B - 1, 64).astype(np.int64)
+        g_s = g[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+        y_s = y[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+        log(f"CPU oracle: direct sums at {n_t} points per signal, up to 64 signals or ~15 s")
+        t0 = time.perf_counter()
+        errs = []
+        for k in range(len(idx)):
+            a = O.recover_band(ch, g_s[k])
+            want = O.evaluate_band(a, ch.n1, t_host)
+            errs.append(np.linalg.norm(y_s[k, 0] - want) / np.linalg.norm(want))
+            if time.perf_counter() - t0 > 15.0:
+                break
+        dt = time.perf_counter() - t0
+        ns = len(errs)
+        result["cpu_baseline"] = {"value": ns * n_t / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"{ns} of the {B} signals (evenly spaced indices), FP64 direct DFT + "
+                                            f"Gaussian elimination + direct sum at each of the {n_t} points; "
+                                            f"{dt:.1f} s"}
+        result["rel_err_vs_fp64_oracle"] = {"max": float(np.max(errs)), "median": float(np.median(errs)),
+                                            "signals": int(ns)}
     return result
 
 
@@ -512,6 +607,8 @@ def main():
         res = bench_refiner(args, torch)
     elif args.workload == "uneven":
         res = bench_uneven(args, torch)
+    elif args.workload == "offgrid":
+        res = bench_offgrid(args, torch)
     elif args.workload == "sisr3":
         # the setting of the paper's super-resolution experiments: x3 with {x, Dx, D2x} per axis
         res = bench_sisr(args, torch, 3, M=3, HR=384)

@@ -271,32 +271,37 @@ mci_status mci_reconstruct_batch(mci_batch_t batch, const void* in, void* out, v
 /* Off-grid evaluation (Theorem 3.3 holds at every real t; eq. DFTexpression with the    */
 /* output operator of the closing paragraph of Section 3, at caller-given points).        */
 /* The band coefficients are recovered as by mci_reconstruct_1d, divided by the Fourier    */
-/* coefficients of a spreading kernel, transformed onto an oversampled grid of L >= 4 K + 2 */
-/* points (K = max |n| over the band), and every point sums the w grid values around it     */
-/* weighted by the kernel ES(x) = exp(beta (sqrt(1 - x^2) - 1)), beta = 2.3 w: a type-2      */
-/* nonuniform FFT.  Its relative error is about 10^(1 - w) on top of the plan's rounding.   */
+/* coefficients of a spreading kernel, transformed onto an oversampled grid (L = the power  */
+/* of two at or above 4 K + 2, K = max |n| over the band, oversampling s = L / (2 K + 1)),  */
+/* and every point sums the w grid values around it weighted by the kernel                  */
+/* ES(x) = exp(beta (sqrt(1 - x^2) - 1)), beta = 0.97 pi w (1 - 1 / (2 s)): a type-2         */
+/* nonuniform FFT.  Its relative error is 5 to 20 times exp(-pi w sqrt(1 - 1 / s)), on top  */
+/* of the plan's rounding.                                                                  */
 /* ----------------------------------------------------------------------------------- */
 typedef struct mci_offgrid_s* mci_offgrid_t;
 
 /* mci_offgrid_plan -- desc as for mci_plan, except that n_out is ignored and storage must
  * be MCI_STORE_NATIVE (MCI_E_UNSUPPORTED otherwise).  width: kernel width w in grid points,
- * 2..16, or 0 for 8 (FP32 plans, error ~1e-7) / 16 (FP64 plans, ~1e-13).  Errors as
- * mci_plan, plus MCI_E_INVALID_ARG for a width out of range or a band longer than 2^26. */
+ * 2..16, or 0 for the smallest w whose estimated error is below 4e-7 (FP32 plans) or
+ * 1e-12 (FP64 plans).  Errors as mci_plan, plus MCI_E_INVALID_ARG for a width out of range
+ * or a band longer than 2^26. */
 mci_status mci_offgrid_plan(const mci_plan_desc* desc, int32_t width, int device, mci_offgrid_t* out);
 mci_status mci_offgrid_destroy(mci_offgrid_t plan);
 /* Grid length L, width w, beta, and the plan that reconstructs onto the grid (owned by the
  * off-grid plan; its variant may be changed or autotuned).  Any output pointer may be NULL. */
 mci_status mci_offgrid_info(mci_offgrid_t plan, int64_t* grid_len, int32_t* width, double* beta,
                             mci_plan_t* grid_plan);
-/* Device scratch for a batch: the grid ([batch][n_ops][L] in plan precision, complex when
- * not real_io) plus the grid plan's workspace. */
-mci_status mci_offgrid_workspace_size(mci_offgrid_t plan, int64_t batch, size_t* bytes);
+/* Device scratch for a batch of `batch` signals and n_t points: the grid ([batch][n_ops][L]
+ * in plan precision, complex when not real_io), a table of n_t tap starts and w n_t weights,
+ * and the grid plan's workspace. */
+mci_status mci_offgrid_workspace_size(mci_offgrid_t plan, int64_t batch, int64_t n_t, size_t* bytes);
 /* mci_evaluate_1d -- y[b][op][j] = (o_op f_b)(t_j) for every signal b.
  *   g : device, samples as for mci_reconstruct_1d.
  *   t : device FP64 points (radians, any real value; taken modulo 2 pi): [n_t] shared by
  *       every signal when t_shared != 0, else [batch][n_t].
  *   y : device, [batch][n_ops][n_t] (real_io) or [batch][n_ops][n_t][2], plan precision.
- * batch = 0 or n_t = 0 is a no-op.  Asynchronous on stream; no allocation. */
+ * workspace: mci_offgrid_workspace_size(plan, batch, n_t) bytes.  batch = 0 or n_t = 0 is a
+ * no-op.  Asynchronous on stream; no allocation. */
 mci_status mci_evaluate_1d(mci_offgrid_t plan, const void* g, const double* t, int64_t n_t, int32_t t_shared,
                            void* y, int64_t batch, void* workspace, size_t ws_bytes, hipStream_t stream);
 

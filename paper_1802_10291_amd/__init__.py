@@ -169,7 +169,8 @@ class Plan1D(_Variants):
 class OffGrid:
     """Evaluation of the reconstruction at arbitrary points t (``mci_offgrid_plan`` /
     ``mci_evaluate_1d``): the same channels, band and output operators as :class:`Plan1D`,
-    evaluated by a nonuniform FFT of kernel width ``width`` (0: 8 for FP32, 16 for FP64)."""
+    evaluated by a nonuniform FFT of kernel width ``width`` (0: chosen for an error near
+    4e-7 in FP32 plans, 1e-12 in FP64 plans)."""
 
     def __init__(self, N: int, channels: Sequence[Channel], ops: Sequence[Tuple[str, int]] = (("identity", 0),),
                  n1: Optional[int] = None, real: bool = True, precision: str = "f32", width: int = 0,
@@ -206,7 +207,7 @@ class OffGrid:
             out = torch.empty(shape, dtype=self.io_dtype(), device=g.device)
         elif tuple(out.shape) != shape or out.dtype != self.io_dtype() or not out.is_contiguous():
             raise ValueError("bad out tensor")
-        need = _lib.mci_offgrid_workspace_size(self.handle, batch)
+        need = _lib.mci_offgrid_workspace_size(self.handle, batch, n_t)
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(max(need, 1), dtype=torch.uint8, device=f"cuda:{self.device}")
         _lib.mci_evaluate_1d(self.handle, g.data_ptr(), t.data_ptr(), n_t, t.dim() == 1, out.data_ptr(), batch,

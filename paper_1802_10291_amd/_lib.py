@@ -119,7 +119,7 @@ def load(path: str = LIB_PATH):
     lib.mci_offgrid_plan.argtypes = [P(mci_plan_desc), i32, i32, P(vp)]
     lib.mci_offgrid_destroy.argtypes = [vp]
     lib.mci_offgrid_info.argtypes = [vp, P(i64), P(ctypes.c_int32), P(ctypes.c_double), P(vp)]
-    lib.mci_offgrid_workspace_size.argtypes = [vp, i64, P(sz)]
+    lib.mci_offgrid_workspace_size.argtypes = [vp, i64, i64, P(sz)]
     lib.mci_evaluate_1d.argtypes = [vp, vp, vp, i64, i32, vp, i64, vp, sz, vp]
     for name in ("mci_offgrid_plan", "mci_offgrid_destroy", "mci_offgrid_info", "mci_offgrid_workspace_size",
                  "mci_evaluate_1d"):
@@ -236,9 +236,9 @@ def mci_offgrid_info(plan: int):
     return L.value, w.value, beta.value, g.value
 
 
-def mci_offgrid_workspace_size(plan: int, batch: int) -> int:
+def mci_offgrid_workspace_size(plan: int, batch: int, n_t: int) -> int:
     n = ctypes.c_size_t()
-    check(load().mci_offgrid_workspace_size(plan, batch, ctypes.byref(n)), "mci_offgrid_workspace_size")
+    check(load().mci_offgrid_workspace_size(plan, batch, n_t, ctypes.byref(n)), "mci_offgrid_workspace_size")
     return n.value
 
 

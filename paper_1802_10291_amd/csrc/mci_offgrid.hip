@@ -6,21 +6,28 @@
 // sum costs M N operations per point; this file evaluates it as a type-2 nonuniform FFT:
 //
 //   1. the regular reconstruction path (channel DFTs, per-residue apply, scatter, inverse
-//      FFT) runs onto an oversampled grid of L points, L >= 4 K + 2 with K = max |n| over
-//      the band, its apply tables multiplied by d(n) = 1 / (L psi_hat(n));
+//      FFT) runs onto an oversampled grid of L points, L the power of two at or above
+//      4 K + 2 with K = max |n| over the band (oversampling sigma = L / (2 K + 1) in [2, 4)),
+//      its apply tables multiplied by d(n) = 1 / (L psi_hat(n));
 //   2. each point t gathers the w grid values around it, weighted by the kernel
 //      psi(t) = ES(t / alpha), alpha = pi w / L, with the "exponential of semicircle"
 //      ES(x) = exp(beta (sqrt(1 - x^2) - 1)) on |x| <= 1 (Barnett, Magland and af
-//      Klinteberg, SIAM J. Sci. Comput. 41 (2019); beta = 2.30 w for oversampling 2).
+//      Klinteberg, SIAM J. Sci. Comput. 41 (2019)), beta = 0.97 pi w (1 - 1 / (2 sigma)).
 //
 // Why it is exact up to the kernel's aliasing: with u_j = (1/L) sum_n c(n) e^{i n t_j},
 // t_j = 2 pi j / L, and Psi the 2 pi-periodisation of psi, whose Fourier coefficients are
 // psi_hat(m) = (1/2 pi) int psi(t) e^{-i m t} dt,
 //     sum_j u_j Psi(t - t_j) = sum_n c(n) sum_p psi_hat(n + p L) e^{i (n + p L) t}.
 // With c(n) = o(n) a(n) / psi_hat(n) the p = 0 term is f(t); the p != 0 terms are the
-// error, bounded by psi_hat(n + p L) / psi_hat(n) with |n + p L| >= L - K >= 3K: about
-// 10^(1-w) for this kernel.  psi_hat is an integral of ES against a cosine, evaluated in
-// FP64 by Gauss-Legendre quadrature at plan time.
+// error, bounded by psi_hat(n + p L) / psi_hat(n) with |n + p L| >= L - K >= 3K: measured
+// at 5 to 20 times exp(-pi w sqrt(1 - 1 / sigma)), which sets the default width.  psi_hat
+// is an integral of ES against a cosine, evaluated in FP64 by Gauss-Legendre quadrature at
+// plan time.
+//
+// Points shared by the whole batch (the common case: many signals resampled at the same
+// instants) get their grid start and w weights computed once per call into a small table;
+// one workgroup per output row then stages the row's grid in LDS and sums from it, so the
+// gather reads the grid from HBM once and its only divergent accesses are LDS reads.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,6 +61,8 @@ struct EvalArgs {
   const void* grid;   // [batch][n_ops][L] (real) or [batch][n_ops][L][2]
   const double* t;    // [n_t] (shared) or [batch][n_t]
   void* y;            // [batch][n_ops][n_t] (real) or [batch][n_ops][n_t][2]
+  int* start;         // shared points: grid index of each point's first tap, [n_t]
+  void* wt;           // shared points: weights [w][n_t] in plan precision
   int64_t L, n_t, batch, t_stride;
   int n_ops, w;
   double beta, L_over_2pi;
@@ -65,33 +74,98 @@ __device__ __forceinline__ T es_weight(T x, T beta) {
   return a > T(0) ? exp(beta * (sqrt(a) - T(1))) : T(0);
 }
 
-// One thread per (signal, point): the w kernel weights are computed once and applied to
-// every output operator's grid.  Grid values of a signal (L elements per operator) are
-// re-read by neighbouring points, so they are served from L2.
-template <typename T, bool REAL>
-__global__ __launch_bounds__(NT) void k_eval(EvalArgs a) {
+// Grid position of t in FP64, t L / (2 pi) reduced to [0, L); first tap i0 = ceil(pos - w/2)
+// (may be negative: indices wrap modulo L, a power of two) and the offset of tap 0.
+__device__ __forceinline__ int64_t first_tap(double t, const EvalArgs& a, double& x0) {
+  double pos = t * a.L_over_2pi;
+  pos -= floor(pos / (double)a.L) * (double)a.L;
+  if (pos >= (double)a.L) pos -= (double)a.L;
+  const double start = ceil(pos - 0.5 * a.w);
+  x0 = (start - pos) * (2.0 / a.w);   // kernel argument of tap 0, in [-1, -1 + 2/w)
+  return (int64_t)start;
+}
+
+// Shared points: the weight table, one thread per point.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_weights(EvalArgs a) {
   const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (j >= a.n_t) return;
-  for (int64_t b = blockIdx.y; b < a.batch; b += gridDim.y) {
-    // position on the grid in FP64: t L / (2 pi) reduced to [0, L)
-    double pos = a.t[b * a.t_stride + j] * a.L_over_2pi;
-    pos -= floor(pos / (double)a.L) * (double)a.L;
-    if (pos >= (double)a.L) pos -= (double)a.L;
-    const double start = ceil(pos - 0.5 * a.w);
-    const int64_t i0 = (int64_t)start;
-    const double step = 2.0 / a.w;
-    T wt[MAX_W];
-    int64_t idx[MAX_W];
+  double x0;
+  const int64_t i0 = first_tap(a.t[j], a, x0);
+  a.start[j] = (int)(i0 & (a.L - 1));
+  const double step = 2.0 / a.w;
+  for (int k = 0; k < a.w; ++k) ((T*)a.wt)[k * a.n_t + j] = es_weight<T>((T)(x0 + k * step), (T)a.beta);
+}
+
+// Shared points, rows that fit the LDS: one workgroup per output row (signal b, operator op)
+// copies the row's grid into LDS with coalesced loads, then every thread evaluates points
+// j = tid, tid + NG, ... from the table.
+constexpr int NG = 512;
+
+template <typename T, bool REAL, int W>
+__global__ __launch_bounds__(NG) void k_gather_lds(EvalArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  using V = typename std::conditional<REAL, T, typename std::conditional<sizeof(T) == 4, float2, double2>::type>::type;
+  V* row = (V*)lds_raw;
+  const int64_t r = blockIdx.x;
+  const int64_t L = a.L;
+  {
+    // 16-byte copies: a row is L sizeof(V) bytes, a multiple of 16 (L is a power of two >= 32)
+    const uint4* src = (const uint4*)((const V*)a.grid + r * L);
+    uint4* dst = (uint4*)row;
+    const int64_t n16 = L * (int64_t)sizeof(V) / 16;
+    for (int64_t q = threadIdx.x; q < n16; q += NG) dst[q] = src[q];
+  }
+  __syncthreads();
+  const T* wt = (const T*)a.wt;
+  const int mask = (int)(L - 1);
+  // the table loads of a point (start and W weights) are independent: with W fixed at
+  // compile time they issue back to back and share one wait
+  for (int64_t j = threadIdx.x; j < a.n_t; j += NG) {
+    const int s0 = a.start[j];
+    T c[W];
 #pragma unroll
-    for (int k = 0; k < MAX_W; ++k) {
-      if (k < a.w) {
-        const T x = (T)((start + k - pos) * step);
-        wt[k] = es_weight<T>(x, (T)a.beta);
-        int64_t q = i0 + k;
-        q += q < 0 ? a.L : 0;
-        q -= q >= a.L ? a.L : 0;
-        idx[k] = q;
+    for (int k = 0; k < W; ++k) c[k] = wt[k * a.n_t + j];
+    if constexpr (REAL) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < W; ++k) acc += c[k] * row[(s0 + k) & mask];
+      ((T*)a.y)[r * a.n_t + j] = acc;
+    } else {
+      T re = T(0), im = T(0);
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        const V g = row[(s0 + k) & mask];
+        re += c[k] * g.x;
+        im += c[k] * g.y;
       }
+      T* y = (T*)a.y + 2 * (r * a.n_t + j);
+      y[0] = re;
+      y[1] = im;
+    }
+  }
+}
+
+// Every other case: one thread per (row, point), grid read through L2.  Shared points take
+// their tap start and weights from the table; per-signal points compute their own.
+template <typename T, bool REAL, bool SHARED, int W>
+__global__ __launch_bounds__(NT) void k_gather(EvalArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (j >= a.n_t) return;
+  const int64_t mask = a.L - 1;
+  for (int64_t b = blockIdx.y; b < a.batch; b += gridDim.y) {
+    T wt[W];
+    int64_t s0;
+    if constexpr (SHARED) {
+      s0 = a.start[j];
+#pragma unroll
+      for (int k = 0; k < W; ++k) wt[k] = ((const T*)a.wt)[k * a.n_t + j];
+    } else {
+      double x0;
+      s0 = first_tap(a.t[b * a.t_stride + j], a, x0);
+      const double step = 2.0 / W;
+#pragma unroll
+      for (int k = 0; k < W; ++k) wt[k] = es_weight<T>((T)(x0 + k * step), (T)a.beta);
     }
     for (int op = 0; op < a.n_ops; ++op) {
       const int64_t row = b * a.n_ops + op;
@@ -99,23 +173,52 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs a) {
         const T* g = (const T*)a.grid + row * a.L;
         T acc = T(0);
 #pragma unroll
-        for (int k = 0; k < MAX_W; ++k)
-          if (k < a.w) acc += wt[k] * g[idx[k]];
+        for (int k = 0; k < W; ++k) acc += wt[k] * g[(s0 + k) & mask];
         ((T*)a.y)[row * a.n_t + j] = acc;
       } else {
         const T* g = (const T*)a.grid + 2 * row * a.L;
         T re = T(0), im = T(0);
 #pragma unroll
-        for (int k = 0; k < MAX_W; ++k)
-          if (k < a.w) {
-            re += wt[k] * g[2 * idx[k]];
-            im += wt[k] * g[2 * idx[k] + 1];
-          }
+        for (int k = 0; k < W; ++k) {
+          const int64_t q = (s0 + k) & mask;
+          re += wt[k] * g[2 * q];
+          im += wt[k] * g[2 * q + 1];
+        }
         T* y = (T*)a.y + 2 * (row * a.n_t + j);
         y[0] = re;
         y[1] = im;
       }
     }
+  }
+}
+
+template <typename T, bool REAL, int W>
+static hipError_t launch_eval_w(const EvalArgs& a, bool shared, hipStream_t s) {
+  const int64_t gx = (a.n_t + NT - 1) / NT;
+  const dim3 g2((unsigned)gx, (unsigned)std::min<int64_t>(a.batch, 65535));
+  if (!shared) {
+    hipLaunchKernelGGL((k_gather<T, REAL, false, W>), g2, dim3(NT), 0, s, a);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_weights<T>, dim3((unsigned)gx), dim3(NT), 0, s, a);
+  const size_t row_bytes = (size_t)a.L * sizeof(T) * (REAL ? 1 : 2);
+  const int64_t rows = a.batch * a.n_ops;
+  if (row_bytes <= 64 * 1024 && rows <= 0x7fffffff)
+    hipLaunchKernelGGL((k_gather_lds<T, REAL, W>), dim3((unsigned)rows), dim3(NG), row_bytes, s, a);
+  else
+    hipLaunchKernelGGL((k_gather<T, REAL, true, W>), g2, dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, bool REAL>
+static hipError_t launch_eval(const EvalArgs& a, bool shared, hipStream_t s) {
+  switch (a.w) {
+#define MCI_OG_W(W) \
+  case W: return launch_eval_w<T, REAL, W>(a, shared, s);
+    MCI_OG_W(2) MCI_OG_W(3) MCI_OG_W(4) MCI_OG_W(5) MCI_OG_W(6) MCI_OG_W(7) MCI_OG_W(8) MCI_OG_W(9)
+    MCI_OG_W(10) MCI_OG_W(11) MCI_OG_W(12) MCI_OG_W(13) MCI_OG_W(14) MCI_OG_W(15) MCI_OG_W(16)
+#undef MCI_OG_W
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -144,18 +247,20 @@ static void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w
   }
 }
 
-// smallest grid length >= lmin that the reconstruction runs on a fast path: 2 A B with A B
-// a two-pass transform length, a power of two, else the next 7-smooth length
+// grid length: the power of two at or above lmin (every variant of the reconstruction runs
+// it, and the gather wraps indices with a mask)
 static int64_t choose_grid_length(int64_t lmin) {
-  int64_t best = 2 * next_smooth_length((lmin + 1) / 2);
-  for (int64_t c = 2; c < 2 * best; c *= 2)
-    if (c >= lmin && c < best) best = c;
-  for (int a : {1, 32, 48, 64, 96, 128, 192, 256, 384, 512})
-    for (int b : {32, 48, 64, 96, 128, 192, 256, 384, 512}) {
-      const int64_t c = 2LL * a * b;
-      if (c >= lmin && c < best) best = c;
-    }
-  return best;
+  int64_t L = 2;
+  while (L < lmin) L <<= 1;
+  return L;
+}
+
+// default width: the smallest w whose estimated error 20 exp(-pi w sqrt(1 - 1 / sigma))
+// stays below eps (4e-7 for FP32 plans, near their rounding; 1e-12 for FP64 plans)
+static int default_width(double sigma, int prec) {
+  const double eps = prec == MCI_F64 ? 1e-12 : 4e-7;
+  const double w = std::log(20.0 / eps) / (M_PI * std::sqrt(1.0 - 1.0 / sigma));
+  return std::min(MAX_W, std::max(2, (int)std::ceil(w - 1e-9)));
 }
 
 }  // namespace og
@@ -172,15 +277,16 @@ mci_status mci_offgrid_plan(const mci_plan_desc* desc, int32_t width, int device
   if (!desc) return fail(MCI_E_INVALID_ARG, "desc is NULL");
   if (desc->storage != MCI_STORE_NATIVE) return fail(MCI_E_UNSUPPORTED, "off-grid evaluation needs native storage");
   if (desc->precision != MCI_F32 && desc->precision != MCI_F64) return fail(MCI_E_INVALID_ARG, "precision");
-  const int w = width ? width : (desc->precision == MCI_F64 ? 16 : 8);
-  if (w < 2 || w > MAX_W) return fail(MCI_E_INVALID_ARG, "width must be 0 or in 2..16");
+  if (width != 0 && (width < 2 || width > MAX_W)) return fail(MCI_E_INVALID_ARG, "width must be 0 or in 2..16");
   if (desc->M < 1 || desc->M > MCI_MAX_CHANNELS || desc->N < 1) return fail(MCI_E_INVALID_ARG, "M or N");
   const int64_t mu = (int64_t)desc->M * desc->N;
   if (mu > (int64_t)1 << 26) return fail(MCI_E_INVALID_ARG, "band too long for off-grid evaluation");
   const int64_t n1 = desc->n1 == MCI_N1_DEFAULT ? -((mu - 1) / 2) : desc->n1;
   const int64_t K = std::max<int64_t>(std::llabs(n1), std::llabs(n1 + mu - 1));
-  const int64_t L = choose_grid_length(std::max<int64_t>(4 * K + 2, 2 * w));
-  const double beta = 2.30 * w, alpha = M_PI * w / (double)L;
+  const int64_t L = choose_grid_length(std::max<int64_t>(4 * K + 2, 2 * MAX_W));
+  const double sigma = (double)L / (double)(2 * K + 1);
+  const int w = width ? width : default_width(sigma, desc->precision);
+  const double beta = 0.97 * M_PI * w * (1.0 - 0.5 / sigma), alpha = M_PI * w / (double)L;
   // d(n) = 1 / (L psi_hat(n)), psi_hat(n) = (alpha / 2 pi) int_{-1}^{1} ES(x) cos(n alpha x) dx
   std::vector<double> xq, wq, ew;
   gauss_legendre(96, xq, wq);
@@ -232,14 +338,21 @@ mci_status mci_offgrid_info(mci_offgrid_t p, int64_t* grid_len, int32_t* width, 
   return MCI_OK;
 }
 
+static size_t al256(size_t n) { return (n + 255) & ~(size_t)255; }
+
 static size_t grid_bytes(const mci_offgrid_s* p, int64_t batch) {
   const size_t el = (p->prec == MCI_F64 ? 8 : 4) * (p->real_io ? 1 : 2);
-  return ((size_t)batch * p->n_ops * p->L * el + 255) & ~(size_t)255;
+  return al256((size_t)batch * p->n_ops * p->L * el);
 }
 
-mci_status mci_offgrid_workspace_size(mci_offgrid_t p, int64_t batch, size_t* bytes) {
-  if (!p || !bytes || batch < 0) return fail(MCI_E_INVALID_ARG, "plan, bytes or batch");
-  *bytes = grid_bytes(p, batch) + plan_workspace(p->grid, batch);
+// weight table of shared points: tap starts (int) and w weights per point
+static size_t table_bytes(const mci_offgrid_s* p, int64_t n_t) {
+  return al256((size_t)n_t * sizeof(int)) + al256((size_t)n_t * p->w * (p->prec == MCI_F64 ? 8 : 4));
+}
+
+mci_status mci_offgrid_workspace_size(mci_offgrid_t p, int64_t batch, int64_t n_t, size_t* bytes) {
+  if (!p || !bytes || batch < 0 || n_t < 0) return fail(MCI_E_INVALID_ARG, "plan, bytes, batch or n_t");
+  *bytes = grid_bytes(p, batch) + table_bytes(p, n_t) + plan_workspace(p->grid, batch);
   return MCI_OK;
 }
 
@@ -249,14 +362,18 @@ mci_status mci_evaluate_1d(mci_offgrid_t p, const void* g, const double* t, int6
   if (batch < 0 || n_t < 0) return fail(MCI_E_INVALID_ARG, "batch and n_t must be >= 0");
   if (batch == 0 || n_t == 0) return MCI_OK;
   if (!g || !t || !y) return fail(MCI_E_INVALID_ARG, "NULL array");
-  const size_t gb = grid_bytes(p, batch), need = gb + plan_workspace(p->grid, batch);
+  const size_t gb = grid_bytes(p, batch), tb = table_bytes(p, n_t), need = gb + tb + plan_workspace(p->grid, batch);
   if (!workspace || ws_bytes < need) return fail(MCI_E_INVALID_ARG, "workspace too small");
+  if (n_t > 0x7fffffffLL * NT) return fail(MCI_E_INVALID_ARG, "too many points");
   if (hipSetDevice(p->device) != hipSuccess) return fail(MCI_E_DEVICE, "hipSetDevice");
-  void* grid = workspace;
-  void* inner = need > gb ? (void*)((char*)workspace + gb) : nullptr;
+  char* base = (char*)workspace;
+  void* grid = base;
+  EvalArgs a{};
+  a.start = (int*)(base + gb);
+  a.wt = base + gb + al256((size_t)n_t * sizeof(int));
+  void* inner = need > gb + tb ? (void*)(base + gb + tb) : nullptr;
   mci_status st = plan_run(p->grid, g, grid, batch, inner, nullptr, stream);
   if (st != MCI_OK) return st;
-  EvalArgs a{};
   a.grid = grid;
   a.t = t;
   a.y = y;
@@ -268,17 +385,10 @@ mci_status mci_evaluate_1d(mci_offgrid_t p, const void* g, const double* t, int6
   a.w = p->w;
   a.beta = p->beta;
   a.L_over_2pi = (double)p->L / (2.0 * M_PI);
-  const int64_t gx = (n_t + NT - 1) / NT;
-  if (gx > 0x7fffffff) return fail(MCI_E_INVALID_ARG, "too many points");
-  const dim3 grd((unsigned)gx, (unsigned)std::min<int64_t>(batch, 65535));
-  if (p->prec == MCI_F64) {
-    if (p->real_io) hipLaunchKernelGGL((k_eval<double, true>), grd, dim3(NT), 0, stream, a);
-    else hipLaunchKernelGGL((k_eval<double, false>), grd, dim3(NT), 0, stream, a);
-  } else {
-    if (p->real_io) hipLaunchKernelGGL((k_eval<float, true>), grd, dim3(NT), 0, stream, a);
-    else hipLaunchKernelGGL((k_eval<float, false>), grd, dim3(NT), 0, stream, a);
-  }
-  const hipError_t e = hipGetLastError();
+  const bool sh = t_shared != 0;
+  hipError_t e;
+  if (p->prec == MCI_F64) e = p->real_io ? launch_eval<double, true>(a, sh, stream) : launch_eval<double, false>(a, sh, stream);
+  else e = p->real_io ? launch_eval<float, true>(a, sh, stream) : launch_eval<float, false>(a, sh, stream);
   if (e != hipSuccess) return fail(MCI_E_DEVICE, std::string("off-grid evaluation: ") + hipGetErrorString(e));
   return MCI_OK;
 }

@@ -7,10 +7,10 @@ as a nonuniform FFT whose spreading kernel has width w: its relative error is ab
 10^(1 - w) (the kernel's aliasing) plus the plan's rounding.
 
 Tolerances (relative L2 per result):
-  * FP64 plans, default w = 16: 1e-11 (aliasing ~1e-13, FP64 rounding ~1e-15 times the sum
-    lengths);
-  * FP32 plans, default w = 8: 1e-5 (aliasing ~1e-7, FP32 rounding as for the on-grid path);
-  * width sweeps in FP64: 10^(2 - w), one decade above the kernel's error estimate.
+  * FP64 plans, default width (estimated error 1e-12): 1e-11;
+  * FP32 plans, default width (estimated error 4e-7): 1e-5, as for the on-grid path;
+  * width sweeps in FP64: 10^(2 - w), above the kernel's error at the smallest
+    oversampling (2: measured 6e-4 at w = 4, 6e-6 at 6, 1e-7 at 8, 1e-11 at 12).
 """
 import numpy as np
 import pytest

@@ -163,6 +163,6 @@ def test_offgrid_arguments_rejected_without_device():
     assert lib.mci_offgrid_plan(ctypes.byref(_desc(L)), 0, 0, None) == 1
     assert lib.mci_offgrid_destroy(None) == 0
     n = ctypes.c_size_t()
-    assert lib.mci_offgrid_workspace_size(None, 1, ctypes.byref(n)) == 1
+    assert lib.mci_offgrid_workspace_size(None, 1, 1, ctypes.byref(n)) == 1
     assert lib.mci_offgrid_info(None, None, None, None, None) == 1
     assert lib.mci_evaluate_1d(None, None, None, 1, 1, None, 1, None, 0, None) == 1
