@@ -306,6 +306,36 @@ mci_status mci_evaluate_1d(mci_offgrid_t plan, const void* g, const double* t, i
                            void* y, int64_t batch, void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* ----------------------------------------------------------------------------------- */
+/* Averaged approximation error (Theorem 4.4, eq. averageerror) and the plan of least     */
+/* error per signal.  For a signal with Fourier coefficients a(n) the error of the         */
+/* approximation operator averaged over the sampling phase is                             */
+/*   eps^2 = sum_{n outside the band} |a(n)|^2 (1 + sum_{l=1..M} |sum_m q_{m,l}(n) b_m(n)|^2) */
+/* with q the inverse entries at the residue of n; the bracket is a weight of the plan     */
+/* alone, so a batch of signals is scored against several plans in one pass.              */
+/* ----------------------------------------------------------------------------------- */
+#define MCI_MAX_ERROR_PLANS 16
+
+/* Device bytes of the weight table: (n_plans rounded up to a power of two) x n_span
+ * values of the given precision. */
+mci_status mci_averaged_error_workspace_size(int32_t n_plans, int64_t n_span, int32_t precision, size_t* bytes);
+
+/* mci_averaged_error -- eps[s][c] = epsilon(f_s, plan c) for n_sig signals and n_plans plans.
+ *   plans : host array of 1..16 1-D plans on one device.  Channels must be derivative or
+ *           Hilbert multipliers (MCI_E_UNSUPPORTED for table channels, which give no b(n)
+ *           outside the band); a plan with singular residues gives MCI_E_SINGULAR.  Only
+ *           the channels, N and n1 of a plan matter (not n_out, the output operators or
+ *           the precision of its transforms).
+ *   a     : device, [n_sig][n_span] complex (re, im interleaved), float for MCI_F32 and
+ *           double for MCI_F64: a[s][i] = a_s(n_lo + i); coefficients outside the span are 0.
+ *   eps   : device, [n_sig][n_plans] double.  best: device [n_sig] int32, the index of the
+ *           plan of least error (first on ties), or NULL.
+ *   workspace : mci_averaged_error_workspace_size bytes.
+ * Asynchronous on stream; no allocation. */
+mci_status mci_averaged_error(const mci_plan_t* plans, int32_t n_plans, const void* a, int64_t n_lo, int64_t n_span,
+                              int64_t n_sig, int32_t precision, double* eps, int32_t* best, void* workspace,
+                              size_t ws_bytes, hipStream_t stream);
+
+/* ----------------------------------------------------------------------------------- */
 /* Learned residual refiner (not part of the paper; its closing remarks on Section 5.2   */
 /* suggest MCI as the interpolation stage of learning-based super-resolution).          */
 /* y = u + CNN(u), u the MCI upsample of an RGB image, CNN = conv3x3 3->32, ReLU,        */

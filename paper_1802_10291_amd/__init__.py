@@ -226,6 +226,24 @@ class OffGrid:
             pass
 
 
+def averaged_error(plans: Sequence["Plan1D"], a, n_lo: int):
+    """Averaged approximation error (Theorem 4.4) of every signal under every plan
+    (``mci_averaged_error``).  a: complex64 / complex128 cuda tensor [n_sig, n_span] with
+    a[s, i] = a_s(n_lo + i).  Returns (eps float64 [n_sig, n_plans], best int32 [n_sig])."""
+    torch = _torch()
+    if not a.is_cuda or a.dim() != 2 or not a.is_contiguous() or a.dtype not in (torch.complex64, torch.complex128):
+        raise ValueError("a must be a contiguous complex64/complex128 cuda tensor [n_sig, n_span]")
+    prec = _lib.MCI_F64 if a.dtype == torch.complex128 else _lib.MCI_F32
+    n_sig, n_span = a.shape
+    eps = torch.empty((n_sig, len(plans)), dtype=torch.float64, device=a.device)
+    best = torch.empty((n_sig,), dtype=torch.int32, device=a.device)
+    need = _lib.mci_averaged_error_workspace_size(len(plans), n_span, prec)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=a.device)
+    _lib.mci_averaged_error([p.handle for p in plans], a.data_ptr(), int(n_lo), n_span, n_sig, prec, eps.data_ptr(),
+                            best.data_ptr(), ws.data_ptr(), need, _stream_handle(a.device))
+    return eps, best
+
+
 class Plan2D(_Variants):
     """A 2-D separable upsampling plan (``mci_plan_2d``): lr [batch, h, w] -> hr [batch, s h, s w],
     with channels {x, Dx} (channels=2) or {x, Dx, D2x} (channels=3) per line."""

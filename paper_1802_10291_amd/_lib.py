@@ -72,7 +72,8 @@ EXPORTS = ["mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_workspace_size"
            "mci_plan_2d", "mci_upsample_2d", "mci_status_string", "mci_last_error", "mci_plan_variants",
            "mci_plan_set_variant", "mci_plan_autotune", "mci_batch_create", "mci_batch_destroy", "mci_batch_sizes",
            "mci_reconstruct_batch", "mci_offgrid_plan", "mci_offgrid_destroy", "mci_offgrid_info",
-           "mci_offgrid_workspace_size", "mci_evaluate_1d"]
+           "mci_offgrid_workspace_size", "mci_evaluate_1d", "mci_averaged_error_workspace_size",
+           "mci_averaged_error"]
 
 _lib = None
 
@@ -121,8 +122,10 @@ def load(path: str = LIB_PATH):
     lib.mci_offgrid_info.argtypes = [vp, P(i64), P(ctypes.c_int32), P(ctypes.c_double), P(vp)]
     lib.mci_offgrid_workspace_size.argtypes = [vp, i64, i64, P(sz)]
     lib.mci_evaluate_1d.argtypes = [vp, vp, vp, i64, i32, vp, i64, vp, sz, vp]
+    lib.mci_averaged_error_workspace_size.argtypes = [i32, i64, i32, P(sz)]
+    lib.mci_averaged_error.argtypes = [P(vp), i32, vp, i64, i64, i64, i32, vp, vp, vp, sz, vp]
     for name in ("mci_offgrid_plan", "mci_offgrid_destroy", "mci_offgrid_info", "mci_offgrid_workspace_size",
-                 "mci_evaluate_1d"):
+                 "mci_evaluate_1d", "mci_averaged_error_workspace_size", "mci_averaged_error"):
         getattr(lib, name).restype = i32
     for name in ("mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_workspace_size", "mci_reconstruct_1d",
                  "mci_plan_2d", "mci_upsample_2d", "mci_plan_variants", "mci_plan_set_variant", "mci_plan_autotune",
@@ -246,6 +249,20 @@ def mci_evaluate_1d(plan: int, g_ptr: int, t_ptr: int, n_t: int, t_shared: bool,
                     ws_ptr: int, ws_bytes: int, stream: int) -> None:
     check(load().mci_evaluate_1d(plan, g_ptr, t_ptr, n_t, 1 if t_shared else 0, y_ptr, batch, ws_ptr, ws_bytes,
                                  stream), "mci_evaluate_1d")
+
+
+def mci_averaged_error_workspace_size(n_plans: int, n_span: int, precision: int) -> int:
+    n = ctypes.c_size_t()
+    check(load().mci_averaged_error_workspace_size(n_plans, n_span, precision, ctypes.byref(n)),
+          "mci_averaged_error_workspace_size")
+    return n.value
+
+
+def mci_averaged_error(plans, a_ptr: int, n_lo: int, n_span: int, n_sig: int, precision: int, eps_ptr: int,
+                       best_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    arr = (ctypes.c_void_p * max(1, len(plans)))(*plans)
+    check(load().mci_averaged_error(arr, len(plans), a_ptr, n_lo, n_span, n_sig, precision, eps_ptr, best_ptr,
+                                    ws_ptr, ws_bytes, stream), "mci_averaged_error")
 
 
 # ----------------------------------------------------------------------------- refiner

@@ -5,7 +5,7 @@ import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
-SOURCES = ["mci_fused.hip", "mci_kernels.hip", "mci_2d.hip", "mci_refiner.hip", "mci_api.hip", "mci_batch.hip", "mci_fftlines.hip", "mci_realpath.hip", "mci_offgrid.hip"]
+SOURCES = ["mci_fused.hip", "mci_kernels.hip", "mci_2d.hip", "mci_refiner.hip", "mci_api.hip", "mci_batch.hip", "mci_fftlines.hip", "mci_realpath.hip", "mci_offgrid.hip", "mci_error.hip"]
 LIB = os.path.join(_HERE, "libmci.so")
 
 HIPCC_FLAGS = [

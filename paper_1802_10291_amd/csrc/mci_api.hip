@@ -175,6 +175,7 @@ static void destroy_plan(mci_plan_s* p) {
     if (p->lp_tw[a]) (void)hipFree(p->lp_tw[a]);
   }
   if (p->tab) (void)hipFree(p->tab);
+  if (p->qdev) (void)hipFree(p->qdev);
   free_side(p->fwd);
   free_side(p->inv);
   free_side(p->rfwd);
@@ -285,12 +286,18 @@ mci_status mci::build_plan(const mci_plan_desc* desc, int device, mci_plan_s** o
   double* cond = (double*)tmp.alloc((size_t)N * sizeof(double), e);
   int* sing = (int*)tmp.alloc((size_t)N * sizeof(int), e);
   if (!tab64 || !tab32 || !cond || !sing) { destroy_plan(p); return fail(MCI_E_OUT_OF_MEMORY, "plan scratch"); }
+  if ((e = hipMalloc(&p->qdev, (size_t)N * M * M * sizeof(double2))) != hipSuccess) {
+    p->qdev = nullptr;
+    destroy_plan(p);
+    return fail(MCI_E_OUT_OF_MEMORY, "inverse table");
+  }
 
   PlanKernelArgs a{};
   a.M = M; a.n_ops = n_ops; a.N = N; a.n1 = p->d.n1;
   for (int k = 0; k < M; ++k) { a.kinds[k] = desc->ch[k].kind; a.orders[k] = desc->ch[k].order; }
   for (int o = 0; o < n_ops; ++o) { a.ops[o] = desc->ops[o]; a.op_orders[o] = desc->op_orders[o]; }
   a.tables = d_tables; a.tab64 = tab64; a.tab32 = tab32; a.cond = cond; a.sing = sing;
+  a.qraw = (double2*)p->qdev;
   a.allow_zero = (desc->flags & MCI_ALLOW_SINGULAR_ZERO) ? 1 : 0;
   if (oscale) {
     if ((int64_t)oscale->size() != mu) { destroy_plan(p); return fail(MCI_E_INVALID_ARG, "output scale length"); }

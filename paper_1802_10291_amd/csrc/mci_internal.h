@@ -48,6 +48,9 @@ struct PlanKernelArgs {
   // optional real factor per band index n - n1 (mu entries, device), multiplied into every
   // table entry of coefficient n: the deconvolution of off-grid evaluation; null = none
   const double* oscale = nullptr;
+  // optional raw inverse entries q_mj(n1 + i) = (H_n^{-1})[m][j] as [N][M][M] (zero for a
+  // singular residue): the averaged-error weights need them without the output operator
+  double2* qraw = nullptr;
 };
 
 // Arguments of the generic (multi-pass) 1-D path.

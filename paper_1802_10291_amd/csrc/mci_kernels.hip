@@ -150,6 +150,17 @@ __global__ void k_plan_tables(PlanKernelArgs a) {
         a.tab64[idx] = t;
         a.tab32[idx] = make_float2((float)t.x, (float)t.y);
       }
+  if (a.qraw)
+    for (int m = 0; m < M; ++m)
+      for (int j = 0; j < M; ++j) {
+        double2 q = make_double2(0.0, 0.0);
+        if (!singular) {
+          q = V[j][m];
+          q.x /= rs[m];
+          q.y /= rs[m];
+        }
+        a.qraw[(i * M + m) * M + j] = q;
+      }
 }
 
 hipError_t launch_plan_tables(const PlanKernelArgs& a, hipStream_t s) {

@@ -33,6 +33,7 @@ struct mci_plan_s {
   bool use_real = false;
   int variant = MCI_VARIANT_MULTIPASS_R8;
   std::vector<std::complex<double>> tab_host;   // FP64 apply table [n_ops][M][M][N]
+  void* qdev = nullptr;     // FP64 inverse entries q_mj(n1 + i), [N][M][M] complex (averaged error)
   // 2-D fused line passes: windows H[SC][len] and twiddles per axis (cols, rows)
   bool lp = false;          // active
   bool lp_avail = false;    // built

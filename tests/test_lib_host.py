@@ -166,3 +166,18 @@ def test_offgrid_arguments_rejected_without_device():
     assert lib.mci_offgrid_workspace_size(None, 1, 1, ctypes.byref(n)) == 1
     assert lib.mci_offgrid_info(None, None, None, None, None) == 1
     assert lib.mci_evaluate_1d(None, None, None, 1, 1, None, 1, None, 0, None) == 1
+
+
+def test_averaged_error_arguments_rejected_without_device():
+    L = _lib()
+    lib = L.load()
+    n = ctypes.c_size_t()
+    assert lib.mci_averaged_error_workspace_size(0, 10, 0, ctypes.byref(n)) == 1     # no plans
+    assert lib.mci_averaged_error_workspace_size(17, 10, 0, ctypes.byref(n)) == 1    # above 16
+    assert lib.mci_averaged_error_workspace_size(3, 10, 5, ctypes.byref(n)) == 1     # precision
+    assert lib.mci_averaged_error_workspace_size(3, 10, 1, ctypes.byref(n)) == 0
+    assert n.value == 4 * 10 * 8 + (256 - (4 * 10 * 8) % 256)                        # 4 padded rows, FP64
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.mci_averaged_error(arr, 1, None, 0, 10, 1, 0, None, None, None, 0, None) == 1   # NULL plan
+    assert lib.mci_averaged_error(None, 1, None, 0, 10, 1, 0, None, None, None, 0, None) == 1
+    assert lib.mci_averaged_error(arr, 0, None, 0, 10, 1, 0, None, None, None, 0, None) == 1
