@@ -52,7 +52,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="batched1d",
                     choices=["batched1d", "sisr2", "sisr4", "sisr3", "refiner", "uneven", "offgrid", "errsel"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16"], help="uneven: storage of the packed buffers")
