@@ -20,6 +20,14 @@
 //     The last FFT pass leaves element q = tid + 256 c in thread tid, so the Q outputs
 //     of q are written by one vector store and a wave writes 64 consecutive q.
 //
+// Split Bluestein (BLUE = 2): the chirp convolution has H inputs and only H outputs, so its
+// outputs are taken in two halves of Ko = ceil(H / 2).  Half h needs the chirp kernel on
+// n in [h Ko - H + 1, h Ko + Ko - 1], H + Ko - 1 values, and a circular convolution of that
+// length computes it without wrap-around: with w_h[m] = b[h Ko - H + 1 + m],
+// y[h Ko + k'] = (u (*) w_h)[k' + H - 1], k' < Ko.  One forward FFT of the chirped input
+// serves both halves, so a length-PF transform triple (PF >= H + Ko - 1, e.g. 1024 for
+// H = 683) replaces the pair of length >= 2H - 1 (2048) the full form needs.
+//
 // The FFTs are register-staged Stockham passes: every thread holds E = L / 256 elements,
 // input slot c of a pass is element tid + 256 c for every radix, and so is output slot c
 // of the last pass -- which lets the Bluestein forward FFT, the pointwise product and the
@@ -48,7 +56,8 @@ struct FusedArgs {
   int zero_s;         // 1 when some |k| <= K is in neither the band nor its negative
   const float2* twF;  // PF entries e^{-2 pi i k / PF}
   const float2* chirp;  // H entries e^{-i pi k^2 / H} (Bluestein)
-  const float2* bhat;   // PF entries: DFT_PF of the conjugate chirp, / PF
+  const float2* bhat;   // full Bluestein: PF entries, DFT_PF of the conjugate chirp, / PF;
+                        // split Bluestein: 2 PF entries, the two halves' kernel segments (see the kernel)
   const float2* wN;     // H + 1 entries e^{-2 pi i k / N}
   const float2* tab;    // [M][M][N]: q_mj(n1 + i) o(.) / N
   const float2* twI;    // P entries e^{-2 pi i k / P}
@@ -204,15 +213,21 @@ __device__ __forceinline__ void fft(float2* lds, float2 (&v)[T][L / NT], const f
 // ---------------------------------------------------------------- the fused kernel
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
-// LDS use of one workgroup, in complex slots (see the layout in the kernel).
-// When all Q/2 output transforms run together S is dead once they are formed and their
-// scratch starts at 0; otherwise it starts after S, which later transforms still read.
+// LDS use of one workgroup, in complex slots (see the layout in the kernel): the forward
+// transforms' scratch, then the channel spectra (computed in place) and S, then the output
+// transforms' scratch, each phase reusing the space from slot 0.  Every output transform's
+// input is gathered from S before the first one runs, so S is dead by then.
 __host__ __device__ constexpr int fused_slots(int PF, int P, int TI, int Q, int M, int H, int K) {
   const int fwd = M * padded(PF);
-  const int mid = (K + 1) + M * (H + 1) + M * H;
-  const int inv = (TI * 2 == Q ? 0 : K + 1) + TI * padded(P);
+  const int mid = M * (H + 1) + (K + 1);
+  const int inv = TI * padded(P);
+  (void)Q;
   return fwd > mid ? (fwd > inv ? fwd : inv) : (mid > inv ? mid : inv);
 }
+
+// waves per SIMD the kernel is compiled for: 4 where its LDS can allow it (the split
+// Bluestein and power-of-two forms at PF <= 1024 with up to 3 channels), else 3
+constexpr int fused_waves(int PF, int M) { return PF <= 1024 && M <= 3 ? 4 : 3; }
 
 // Storage access: two consecutive real samples as one complex value, and four consecutive
 // outputs as one vector store (FP32, or FP16 with round-to-nearest conversion).
@@ -235,19 +250,20 @@ __device__ __forceinline__ void st_quad(__half* y, int q, float2 lo, float2 hi) 
 
 // TI: how many of the Q/2 output transforms run side by side (1 or Q/2).  TS: storage type
 // of the samples and outputs (float or __half); all arithmetic is FP32.
-template <int PF, bool BLUE, int P, int Q, int M, int TI, typename TS>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
+template <int PF, int BLUE, int P, int Q, int M, int TI, typename TS>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves(PF, M))))
 void k_mci1d_fused(FusedArgs a) {
   extern __shared__ float2 sm[];
   constexpr int EF = PF / NT, EI = P / NT;
   const int tid = threadIdx.x;
   const int N = a.N, H = a.H, XH = a.H + 1;
-  // layout: forward scratch [M][padded(PF)] | S [K+1], X [M][H+1], Zc [M][H] | output scratch [TI][padded(P)]
+  // layout, each phase from slot 0: forward scratch [M][padded(PF)] | channel spectra
+  // Zc -> X in place [M][H+1], then S [K+1] | output scratch [TI][padded(P)]
   float2* F = sm;
-  float2* Sv = sm;
-  float2* X = sm + (a.K + 1);
-  float2* Zc = X + M * XH;
-  float2* Z = (TI * 2 == Q) ? sm : sm + (a.K + 1);
+  float2* X = sm;
+  float2* Zc = sm;
+  float2* Sv = sm + M * XH;
+  float2* Z = sm;
 
   {
     // one signal per workgroup: a persistent loop would keep the loop invariants of every
@@ -280,7 +296,46 @@ void k_mci1d_fused(FusedArgs a) {
         }
       }
       fft<PF, -1, M>(F, v, a.twF);
-      if constexpr (BLUE) {
+      if constexpr (BLUE == 2) {
+        // two output halves from one forward transform; the first half's outputs wait in
+        // registers until the second transform is done with the scratch
+        const int Ko = (H + 1) / 2;
+        float2 w0[M][EF], w[M][EF];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+          for (int c = 0; c < EF; ++c) {
+            const float2 bh = a.bhat[h * PF + tid + NT * c];
+#pragma unroll
+            for (int m = 0; m < M; ++m) w[m][c] = cmul(v[m][c], bh);
+          }
+          fft<PF, +1, M>(F, w, a.twF);
+          if (h == 0) {
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+#pragma unroll
+              for (int c = 0; c < EF; ++c) w0[m][c] = w[m][c];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < EF; ++c) {
+          const int e = tid + NT * c;
+          if (e >= H - 1) {
+            const int k0 = e - (H - 1), k1 = Ko + e - (H - 1);
+            if (k0 < Ko) {
+              const float2 ch = a.chirp[k0];
+#pragma unroll
+              for (int m = 0; m < M; ++m) Zc[m * XH + k0] = cmul(w0[m][c], ch);
+            }
+            if (k1 < H) {
+              const float2 ch = a.chirp[k1];
+#pragma unroll
+              for (int m = 0; m < M; ++m) Zc[m * XH + k1] = cmul(w[m][c], ch);
+            }
+          }
+        }
+      } else if constexpr (BLUE == 1) {
 #pragma unroll
         for (int c = 0; c < EF; ++c) {
           const float2 bh = a.bhat[tid + NT * c];
@@ -298,28 +353,38 @@ void k_mci1d_fused(FusedArgs a) {
           }
         }
       }
-      __syncthreads();
+      if constexpr (BLUE != 2) {
+        __syncthreads();
 #pragma unroll
-      for (int m = 0; m < M; ++m)
+        for (int m = 0; m < M; ++m)
 #pragma unroll
-        for (int c = 0; c < EF; ++c) {
-          const int k = tid + NT * c;
-          if (k < H) Zc[m * H + k] = v[m][c];
-        }
+          for (int c = 0; c < EF; ++c) {
+            const int k = tid + NT * c;
+            if (k < H) Zc[m * XH + k] = v[m][c];
+          }
+      }
     }
     __syncthreads();
     if (a.zero_s)
       for (int k = tid; k <= a.K; k += NT) Sv[k] = make_float2(0.f, 0.f);
-    for (int k = tid; k <= H; k += NT) {
-      const float2 wn = a.wN[k];
-      const int k1 = k == H ? 0 : k, k2 = k == 0 ? 0 : H - k;
+    // X[k] = E[k] + w_N^k O[k], k = 0..H, in place over Zc: X[k] and X[H - k] both need
+    // Zc[k] and Zc[H - k] (Zc[0] for k = 0, whose partner is the spare slot H), so the
+    // thread owning the pair reads both before writing and no other thread touches them
+    for (int k = tid; 2 * k <= H; k += NT) {
+      const int kb = H - k, kr = k == 0 ? 0 : kb;
+      const float2 wk = a.wN[k], wb = a.wN[kb];
 #pragma unroll
       for (int m = 0; m < M; ++m) {
-        const float2 z1 = Zc[m * H + k1];
-        const float2 z2 = conjf2(Zc[m * H + k2]);
-        const float2 e = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
-        const float2 o = make_float2(0.5f * (z1.y - z2.y), -0.5f * (z1.x - z2.x));   // (z1 - z2) / (2i)
-        X[m * XH + k] = cadd(e, cmul(wn, o));
+        const float2 A = Zc[m * XH + k], B = Zc[m * XH + kr];
+        // X[k]: z1 = A, z2 = conj B;  X[kb]: z1 = B, z2 = conj A
+        const float2 e = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
+        const float2 o = make_float2(0.5f * (A.y + B.y), -0.5f * (A.x - B.x));   // (z1 - z2) / (2i)
+        const float2 eb = make_float2(e.x, -e.y);
+        const float2 ob = make_float2(o.x, -o.y);
+        const float2 xk = cadd(e, cmul(wk, o));
+        const float2 xb = cadd(eb, cmul(wb, ob));
+        X[m * XH + k] = xk;
+        X[m * XH + kb] = xb;
       }
     }
     __syncthreads();
@@ -368,22 +433,28 @@ void k_mci1d_fused(FusedArgs a) {
     // ---------------- 3. output grid: Q/2 complex inverse FFTs of length P, TI at a time
     TS* ys = (TS*)a.y + (a.offs ? a.offs[2 * sig + 1] : sig * (int64_t)a.Nout);
     float2 keep[(Q / 2 - TI > 0 ? Q / 2 - TI : 1)][EI];   // earlier transforms' outputs
+    // every transform's input is gathered from S first: the scratch then reuses S's space
+    float2 vin[Q / 2][EI];
+#pragma unroll
+    for (int pc = 0; pc < Q / 2; ++pc) {
+      const float2* U = a.U + (int64_t)pc * (2 * a.K + 1) + a.K;   // U[k], k = -K..K
+#pragma unroll
+      for (int c = 0; c < EI; ++c) {
+        const int b = tid + NT * c;
+        float2 acc = make_float2(0.f, 0.f);
+        if (b <= a.K) acc = cmul(Sv[b], U[b]);
+        const int k2 = b - P;                  // the other band position congruent to b (K < P)
+        if (k2 >= -a.K) acc = cadd(acc, cmul(conjf2(Sv[-k2]), U[k2]));
+        vin[pc][c] = acc;
+      }
+    }
 #pragma unroll
     for (int pc0 = 0; pc0 < Q / 2; pc0 += TI) {
       float2 v[TI][EI];
 #pragma unroll
-      for (int t = 0; t < TI; ++t) {
-        const float2* U = a.U + (int64_t)(pc0 + t) * (2 * a.K + 1) + a.K;   // U[k], k = -K..K
+      for (int t = 0; t < TI; ++t)
 #pragma unroll
-        for (int c = 0; c < EI; ++c) {
-          const int b = tid + NT * c;
-          float2 acc = make_float2(0.f, 0.f);
-          if (b <= a.K) acc = cmul(Sv[b], U[b]);
-          const int k2 = b - P;                  // the other band position congruent to b (K < P)
-          if (k2 >= -a.K) acc = cadd(acc, cmul(conjf2(Sv[-k2]), U[k2]));
-          v[t][c] = acc;
-        }
-      }
+        for (int c = 0; c < EI; ++c) v[t][c] = vin[pc0 + t][c];
       fft<P, +1, TI>(Z, v, a.twI);
       if (pc0 + TI < Q / 2) {
 #pragma unroll
@@ -414,7 +485,7 @@ struct FusedTables {
   float2 *twF, *chirp, *bhat, *wN, *twI, *wout;
 };
 
-template <int PF, bool BLUE, int P, int Q, int M, int TI, typename TS>
+template <int PF, int BLUE, int P, int Q, int M, int TI, typename TS>
 static hipError_t launch_mt(const FusedPlan& fp, const void* g, void* y, int64_t batch, const int64_t* offs,
                             hipStream_t s) {
   FusedArgs a = *(const FusedArgs*)fp.args;
@@ -429,7 +500,7 @@ static hipError_t launch_mt(const FusedPlan& fp, const void* g, void* y, int64_t
 }
 
 // Raise the kernels' dynamic LDS limit once, at plan time (not while a launch may be captured).
-template <int PF, bool BLUE, int P, int Q, int M, typename TS>
+template <int PF, int BLUE, int P, int Q, int M, typename TS>
 static hipError_t prep_m(const int* lds_ti) {
   if (lds_ti[0] > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_mci1d_fused<PF, BLUE, P, Q, M, 1, TS>,
@@ -442,7 +513,7 @@ static hipError_t prep_m(const int* lds_ti) {
   return hipSuccess;
 }
 
-template <int PF, bool BLUE, int P, int Q>
+template <int PF, int BLUE, int P, int Q>
 static hipError_t prep_t(int M, int store, const int* lds_ti) {
   const bool h = store == ST_F16;
   switch (M) {
@@ -453,7 +524,7 @@ static hipError_t prep_t(int M, int store, const int* lds_ti) {
   }
 }
 
-template <int PF, bool BLUE, int P, int Q, int M>
+template <int PF, int BLUE, int P, int Q, int M>
 static hipError_t launch_m(const FusedPlan& fp, const void* g, void* y, int64_t batch, const int64_t* offs,
                            hipStream_t s) {
   if (fp.store == ST_F16) {
@@ -464,7 +535,7 @@ static hipError_t launch_m(const FusedPlan& fp, const void* g, void* y, int64_t 
   return launch_mt<PF, BLUE, P, Q, M, 1, float>(fp, g, y, batch, offs, s);
 }
 
-template <int PF, bool BLUE, int P, int Q>
+template <int PF, int BLUE, int P, int Q>
 static hipError_t launch_t(const FusedPlan& fp, const void* g, void* y, int64_t batch, const int64_t* offs,
                            hipStream_t s) {
   switch (((const FusedArgs*)fp.args)->M) {
@@ -481,17 +552,19 @@ using PrepFn = hipError_t (*)(int, int, const int*);
 
 struct Variant {
   int PF;
-  bool blue;
+  int blue;   // 0: power-of-two H = PF; 1: Bluestein, PF >= 2H - 1; 2: split Bluestein, PF >= H + ceil(H/2) - 1
   int P, Q;
   LaunchFn fn;
   PrepFn prep;
 };
 
 #define MCI_FV(PF, B, P, Q) {PF, B, P, Q, launch_t<PF, B, P, Q>, prep_t<PF, B, P, Q>}
+// at equal PF the first listed wins: the full Bluestein form (two transforms) before the
+// split form (three)
 static const Variant kVariants[] = {
-    MCI_FV(2048, true, 4096, 4), MCI_FV(1024, true, 4096, 4), MCI_FV(1024, false, 4096, 4),
-    MCI_FV(2048, false, 4096, 4), MCI_FV(2048, true, 2048, 4), MCI_FV(1024, false, 1024, 4),
-    MCI_FV(2048, false, 2048, 4),
+    MCI_FV(2048, 1, 4096, 4), MCI_FV(1024, 1, 4096, 4), MCI_FV(1024, 0, 4096, 4),
+    MCI_FV(2048, 0, 4096, 4), MCI_FV(2048, 1, 2048, 4), MCI_FV(1024, 0, 1024, 4),
+    MCI_FV(2048, 0, 2048, 4), MCI_FV(1024, 2, 4096, 4),
 };
 #undef MCI_FV
 
@@ -507,7 +580,9 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   const int64_t K = std::max<int64_t>(std::llabs(n1), std::llabs(n1 + mu - 1));
   const Variant* pick = nullptr;
   for (const Variant& v : kVariants) {
-    const bool fwd_ok = v.blue ? (2 * H - 1 <= v.PF && !is_pow2(H)) : (H == v.PF);
+    const bool fwd_ok = v.blue == 0 ? H == v.PF
+                : v.blue == 1 ? (2 * H - 1 <= v.PF && !is_pow2(H))
+                              : (H + (H + 1) / 2 - 1 <= v.PF && !is_pow2(H));
     if (!fwd_ok || (int64_t)v.P * v.Q != d.n_out) continue;
     if (!pick || v.PF < pick->PF) pick = &v;
   }
@@ -535,7 +610,8 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   // tables (FP64 on the host, stored FP32)
   const int PF = pick->PF, P = pick->P;
   const int Q = pick->Q;
-  std::vector<std::complex<double>> twF(PF), chirp(H), bhat(PF, 0.0), wN(H + 1), twI(P), U((size_t)(Q / 2) * (2 * K + 1));
+  std::vector<std::complex<double>> twF(PF), chirp(H), bhat((size_t)(pick->blue == 2 ? 2 : 1) * PF, 0.0), wN(H + 1),
+      twI(P), U((size_t)(Q / 2) * (2 * K + 1));
   for (int k = 0; k < PF; ++k) twF[k] = root_of_unity(k, PF);
   for (int64_t k = 0; k <= H; ++k) wN[k] = root_of_unity(k, N);
   for (int k = 0; k < P; ++k) twI[k] = root_of_unity(k, P);
@@ -548,13 +624,25 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
     }
   if (pick->blue) {
     for (int64_t k = 0; k < H; ++k) chirp[k] = chirp_value(k, H, -1);
-    for (int64_t m = 0; m < H; ++m) {
-      bhat[m] = std::conj(chirp[m]);
-      if (m) bhat[PF - m] = std::conj(chirp[m]);
-    }
     std::vector<int> rad;
     for (int64_t r = PF; r > 1; r /= 8) rad.push_back(r >= 8 ? 8 : (int)r);
-    host_fft(bhat, rad, -1);
+    if (pick->blue == 1) {
+      // the kernel b[n] = conj c[|n|], |n| < H, placed circularly
+      for (int64_t m = 0; m < H; ++m) {
+        bhat[m] = std::conj(chirp[m]);
+        if (m) bhat[PF - m] = std::conj(chirp[m]);
+      }
+      host_fft(bhat, rad, -1);
+    } else {
+      // half h: w_h[m] = b[h Ko - H + 1 + m], m < H + Ko - 1 (<= PF), zero beyond
+      const int64_t Ko = (H + 1) / 2;
+      for (int h = 0; h < 2; ++h) {
+        std::vector<std::complex<double>> wh(PF, 0.0);
+        for (int64_t m = 0; m < H + Ko - 1; ++m) wh[m] = std::conj(chirp_value(h * Ko - H + 1 + m, H, -1));
+        host_fft(wh, rad, -1);
+        for (int m = 0; m < PF; ++m) bhat[(size_t)h * PF + m] = wh[m];
+      }
+    }
     for (auto& x : bhat) x /= (double)PF;
   }
   const size_t n_all = twF.size() + chirp.size() + bhat.size() + wN.size() + twI.size() + U.size();

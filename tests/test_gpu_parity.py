@@ -216,6 +216,8 @@ FUSED = [
     (1366, 16384, [("deriv", 0), ("deriv", 1), ("deriv", 2)], -2500),   # shifted band
     (2048, 16384, [("deriv", 0), ("hilbert", 0)], None),                # Hilbert channel
     (1000, 16384, [("deriv", 0), ("deriv", 1), ("deriv", 2)], 100),     # band not containing 0
+    (1100, 16384, [("deriv", 0), ("deriv", 1), ("deriv", 2)], None),    # split Bluestein, H = 550
+    (1200, 16384, [("deriv", 0)], None),                                # split Bluestein, M = 1, H = 600
 ]
 
 
@@ -224,7 +226,7 @@ def test_fused_kernel_parity(torch_cuda, case):
     N, n_out, channels, n1 = FUSED[case]
     M = len(channels)
     g = S.smooth_noisy_batch(10 * case, 3, M, N, 2 * N)
-    if channels[1][0] == "hilbert":
+    if any(k == "hilbert" for k, _ in channels):
         g = np.random.default_rng(case).standard_normal((3, M, N))
     y, want, plan = run_case(torch_cuda, N, n_out, channels, g=g, n1=n1)
     assert plan.info.path == 1, "expected the fused kernel"
