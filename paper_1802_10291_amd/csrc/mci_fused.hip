@@ -54,6 +54,7 @@ struct FusedArgs {
   int Nout, K;        // K = max |k| over the band
   int C, Ch, n_items; // residue pairing: i' = (C - i) mod N; canonical items
   int zero_s;         // 1 when some |k| <= K is in neither the band nor its negative
+  int n1r;            // n1 mod N, in [0, N)
   const float2* twF;  // PF entries e^{-2 pi i k / PF}
   const float2* chirp;  // H entries e^{-i pi k^2 / H} (Bluestein)
   const float2* bhat;   // full Bluestein: PF entries, DFT_PF of the conjugate chirp, / PF;
@@ -396,8 +397,8 @@ void k_mci1d_fused(FusedArgs a) {
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int ii = q ? ip : i;
-        int r = (a.n1 + ii) % N;
-        if (r < 0) r += N;
+        int r = a.n1r + ii;                     // (n1 + ii) mod N, 0 <= ii < N
+        if (r >= N) r -= N;
         float2 d[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) d[m] = r <= H ? X[m * XH + r] : conjf2(X[m * XH + (N - r)]);
@@ -669,6 +670,7 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   // S(k), 0 <= k <= K, is written by the apply iff k or -k lies in [n1, n1 + mu)
   a->zero_s = (n1 > 0 || n1 + mu - 1 < 0) ? 1 : 0;
   a->n_items = a->Ch + 1 + (int)((a->C + N) / 2 - a->C);
+  a->n1r = (int)(((n1 % N) + N) % N);
   a->twF = dt + o_twF; a->chirp = dt + o_chirp; a->bhat = dt + o_bhat; a->wN = dt + o_wN;
   a->tab = (const float2*)tab; a->twI = dt + o_twI; a->U = dt + o_U;
   fp.tables = dt;
