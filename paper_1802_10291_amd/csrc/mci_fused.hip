@@ -112,8 +112,9 @@ template <int... Rs> struct RList {};
 // T independent length-L transforms (buffer t at lds + t * padded(L)); one Stockham pass of
 // radix R at stage size NS, then the remaining passes.  On entry v[t][c] holds element
 // tid + NT c of transform t's pass input; after the last pass it holds element tid + NT c
-// of the transform.
-template <int L, int S, int T, int NS, int R, int... Rest>
+// of the transform.  SX: the transforms share one buffer and exchange one after the other
+// (the butterflies of all T still share their twiddles).
+template <int L, int S, int T, bool SX, int NS, int R, int... Rest>
 __device__ __forceinline__ void fft_passes(float2* __restrict__ lds, float2 (&v)[T][L / NT],
                                            const float2* __restrict__ tw, RList<R, Rest...>) {
   constexpr int E = L / NT;
@@ -181,23 +182,40 @@ __device__ __forceinline__ void fft_passes(float2* __restrict__ lds, float2 (&v)
     // For power-of-two NS and R, base % 16 + (r NS) % 16 < 16, so
     // pad(base + r NS) = pad(base) + r NS + (r NS) / 16: one address per butterfly, the
     // rest are immediate offsets.  Likewise pad(tid + NT c) = pad(tid) + c (NT + NT / 16).
-    __syncthreads();
+    const int pt = pad(tid);
+    if constexpr (SX) {
 #pragma unroll
-    for (int b = 0; b < BPT; ++b) {
-      const int j = tid + NT * b;
-      const int pb = pad((j / NS) * NS * R + (j % NS));
+      for (int t = 0; t < T; ++t) {
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < BPT; ++b) {
+          const int j = tid + NT * b;
+          const int pb = pad((j / NS) * NS * R + (j % NS));
+#pragma unroll
+          for (int r = 0; r < R; ++r) lds[pb + r * NS + (r * NS) / 16] = u[t][b][r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < E; ++c) v[t][c] = lds[pt + c * (NT + NT / 16)];
+      }
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < BPT; ++b) {
+        const int j = tid + NT * b;
+        const int pb = pad((j / NS) * NS * R + (j % NS));
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int r = 0; r < R; ++r) lds[t * LP + pb + r * NS + (r * NS) / 16] = u[t][b][r];
+      }
+      __syncthreads();
 #pragma unroll
       for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[t * LP + pb + r * NS + (r * NS) / 16] = u[t][b][r];
+        for (int c = 0; c < E; ++c) v[t][c] = lds[t * LP + pt + c * (NT + NT / 16)];
     }
-    __syncthreads();
-    const int pt = pad(tid);
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-      for (int c = 0; c < E; ++c) v[t][c] = lds[t * LP + pt + c * (NT + NT / 16)];
-    fft_passes<L, S, T, NS * R>(lds, v, tw, RList<Rest...>{});
+    fft_passes<L, S, T, SX, NS * R>(lds, v, tw, RList<Rest...>{});
   }
 }
 
@@ -208,7 +226,12 @@ template <> struct Radices<4096> { using type = RList<16, 16, 16>; };
 
 template <int L, int S, int T>
 __device__ __forceinline__ void fft(float2* lds, float2 (&v)[T][L / NT], const float2* tw) {
-  fft_passes<L, S, T, 1>(lds, v, tw, typename Radices<L>::type{});
+  fft_passes<L, S, T, false, 1>(lds, v, tw, typename Radices<L>::type{});
+}
+// T transforms through one scratch buffer of padded(L) slots
+template <int L, int S, int T>
+__device__ __forceinline__ void fft_serial(float2* lds, float2 (&v)[T][L / NT], const float2* tw) {
+  fft_passes<L, S, T, true, 1>(lds, v, tw, typename Radices<L>::type{});
 }
 
 // ---------------------------------------------------------------- the fused kernel
@@ -448,6 +471,15 @@ void k_mci1d_fused(FusedArgs a) {
         if (k2 >= -a.K) acc = cadd(acc, cmul(conjf2(Sv[-k2]), U[k2]));
         vin[pc][c] = acc;
       }
+    }
+    if constexpr (TI == 1 && Q == 4) {
+      // both transforms' butterflies together (one twiddle formation), exchanges in turn
+      // through the one scratch buffer
+      fft_serial<P, +1, 2>(Z, vin, a.twI);
+#pragma unroll
+      for (int c = 0; c < EI; ++c) st_quad(ys, tid + NT * c, vin[0][c], vin[1][c]);
+      __syncthreads();
+      return;
     }
 #pragma unroll
     for (int pc0 = 0; pc0 < Q / 2; pc0 += TI) {
