@@ -678,8 +678,8 @@ def bench_refiner(args, torch):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (each signal or image is "
-              "independent; see the sharding note in the design document). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (every signal and image is independent, "
+              "so a batch would shard by contiguous ranges with no collective). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -701,6 +701,10 @@ def main():
         res = bench_sisr(args, torch, 3, M=3, HR=384)
     else:
         res = bench_sisr(args, torch, 2 if args.workload == "sisr2" else 4)
+    cpu = res.get("cpu_baseline")
+    if cpu and cpu.get("unit") == res.get("unit") and cpu.get("value"):
+        # the oracle's time for one whole step of the workload, extrapolated from its sample
+        cpu["full_step_s_extrapolated"] = res["value"] * res["ms_per_step"] * 1e-3 / cpu["value"]
     print(json.dumps(res), flush=True)
 
 
