@@ -223,6 +223,7 @@ static mci_status build_real_path(mci_plan_s* p) {
   if ((st = build_side(p->rinv, P, +1, MCI_F32)) != MCI_OK) return st;
   if (!p->rfwd.fa || !p->rinv.fa || p->rinv.blue) return MCI_OK;
   const int64_t K = std::max<int64_t>(std::llabs(d.n1), std::llabs(d.n1 + mu - 1));
+  if (mu > ((int64_t)1 << 29) || K + P > ((int64_t)1 << 30)) return MCI_OK;   // the path's indices are 32-bit
   std::vector<std::complex<double>> wN(H), Wo(2 * K + 1);
   for (int64_t k = 0; k < H; ++k) wN[k] = root_of_unity(k, N);
   for (int64_t k = -K; k <= K; ++k)

@@ -18,6 +18,8 @@
 // A thread of step 2 owns the bins b and P - b, which receive S(k) and S(-k) = conj S(k).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "mci_device.h"
 #include "mci_fftlines.h"
 #include "mci_realpath.h"
@@ -26,26 +28,33 @@ namespace mci {
 
 __device__ __forceinline__ float2 conj2(float2 a) { return make_float2(a.x, -a.y); }
 
-// a(k) of signal Zs for output op `op`; zero outside the band
-__device__ __forceinline__ float2 band_coeff(int64_t k, const float2* __restrict__ Zs, int64_t Lz,
+// a(k) of signal Zs for output op `op`; zero outside the band.  32-bit indices (the plan
+// keeps M N and P + K below 2^30): k = n1 + j N + i, and k mod N = (n1 mod N + i) mod N.
+__device__ __forceinline__ float2 band_coeff(int k, const float2* __restrict__ Zs, int64_t Lz,
                                              const float2* __restrict__ post, const float2* __restrict__ wN,
-                                             const float2* __restrict__ tab, int op, int M, int64_t N, int64_t H,
-                                             int64_t n1, bool half) {
-  const int64_t d = k - n1;
+                                             const float2* __restrict__ tab, int op, int M, int N, int H,
+                                             int n1, int n1r, bool half) {
+  const int d = k - n1;
   float2 acc = make_float2(0.f, 0.f);
-  if (d < 0 || d >= (int64_t)M * N) return acc;
-  const int64_t j = d / N, i = d - j * N;
-  const int64_t r = ((k % N) + N) % N;
+  if (d < 0 || d >= M * N) return acc;
+  int j = 0, i = d;
+  while (i >= N) {   // at most M - 1 steps
+    i -= N;
+    ++j;
+  }
+  int r = n1r + i;
+  if (r >= N) r -= N;
+  const float2* tb = tab + ((int64_t)(op * M) * M + j) * N + i;   // Tab[op][m][j][i] at tb[m M N]
   if (!half) {   // X_m[r] is the transform itself
     for (int m = 0; m < M; ++m) {
       float2 x = Zs[m * Lz + r];
       if (post) x = cmul(x, post[r]);
-      acc = cadd(acc, cmul(x, tab[(((int64_t)op * M + m) * M + j) * N + i]));
+      acc = cadd(acc, cmul(x, tb[(int64_t)m * M * N]));
     }
     return acc;
   }
-  const int64_t rh = r < H ? r : r - H;
-  const int64_t rr = rh == 0 ? 0 : H - rh;
+  const int rh = r < H ? r : r - H;
+  const int rr = rh == 0 ? 0 : H - rh;
   const float sg = r < H ? 1.f : -1.f;
   const float2 w = wN[rh];
   for (int m = 0; m < M; ++m) {
@@ -59,33 +68,38 @@ __device__ __forceinline__ float2 band_coeff(int64_t k, const float2* __restrict
     const float2 o = make_float2(0.5f * (z1.y - z2.y), -0.5f * (z1.x - z2.x));   // (z1 - z2) / (2i)
     const float2 wo = cmul(w, o);
     const float2 x = make_float2(e.x + sg * wo.x, e.y + sg * wo.y);
-    acc = cadd(acc, cmul(x, tab[(((int64_t)op * M + m) * M + j) * N + i]));
+    acc = cadd(acc, cmul(x, tb[(int64_t)m * M * N]));
   }
   return acc;
 }
 
+// One thread per bin pair {b, P - b} (blockIdx.x), looping over a slice of the signals
+// (blockIdx.y): the band positions k = b mod P and their residues are the same for every
+// signal, so only the signal's own values are loaded per iteration.
 __global__ void k_apply_real(const float2* __restrict__ Z, int64_t Lz, const float2* __restrict__ post,
                              const float2* __restrict__ wN, const float2* __restrict__ tab,
-                             const float2* __restrict__ Wo, float2* __restrict__ Zc, int M, int n_ops, int64_t N,
-                             int64_t H, int64_t n1, int64_t K, int64_t P, int64_t batch, int half_rows) {
-  const int64_t half = P / 2 + 1;   // bin pairs {b, P - b}, b = 0 .. P/2
-  const int64_t total = batch * n_ops * half;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = e % half, bo = e / half;
-    const int op = (int)(bo % n_ops);
-    const int64_t sig = bo / n_ops;
+                             const float2* __restrict__ Wo, float2* __restrict__ Zc, int M, int n_ops, int N,
+                             int H, int n1, int n1r, int K, int P, int64_t batch, int half_rows) {
+  const int half = P / 2 + 1;   // bin pairs {b, P - b}, b = 0 .. P/2
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= half) return;
+  const bool self = b == 0 || 2 * b == P;
+  const int k0 = b - ((b + K) / P) * P;   // the first k = b mod P with k >= -K
+  for (int64_t sig = blockIdx.y; sig < batch; sig += gridDim.y) {
     const float2* Zs = Z + sig * M * Lz;
-    const bool self = b == 0 || 2 * b == P;
-    float2 acc_b = make_float2(0.f, 0.f), acc_m = make_float2(0.f, 0.f);
-    for (int64_t k = b - ((b + K) / P) * P; k <= K; k += P) {   // k = b mod P, |k| <= K
-      const float2 ak = band_coeff(k, Zs, Lz, post, wN, tab, op, M, N, H, n1, half_rows);
-      const float2 amk = conj2(band_coeff(-k, Zs, Lz, post, wN, tab, op, M, N, H, n1, half_rows));
-      const float2 S = make_float2(0.5f * (ak.x + amk.x), 0.5f * (ak.y + amk.y));
-      acc_b = cadd(acc_b, cmul(S, Wo[k + K]));
-      if (!self) acc_m = cadd(acc_m, cmul(conj2(S), Wo[K - k]));
+    for (int op = 0; op < n_ops; ++op) {
+      float2 acc_b = make_float2(0.f, 0.f), acc_m = make_float2(0.f, 0.f);
+      for (int k = k0; k <= K; k += P) {
+        const float2 ak = band_coeff(k, Zs, Lz, post, wN, tab, op, M, N, H, n1, n1r, half_rows);
+        const float2 amk = conj2(band_coeff(-k, Zs, Lz, post, wN, tab, op, M, N, H, n1, n1r, half_rows));
+        const float2 S = make_float2(0.5f * (ak.x + amk.x), 0.5f * (ak.y + amk.y));
+        acc_b = cadd(acc_b, cmul(S, Wo[k + K]));
+        if (!self) acc_m = cadd(acc_m, cmul(conj2(S), Wo[K - k]));
+      }
+      const int64_t bo = sig * n_ops + op;
+      Zc[bo * P + b] = acc_b;
+      if (!self) Zc[bo * P + (P - b)] = acc_m;
     }
-    Zc[bo * P + b] = acc_b;
-    if (!self) Zc[bo * P + (P - b)] = acc_m;
   }
 }
 
@@ -137,11 +151,14 @@ hipError_t run_real_1d(const RealPath& r, const void* g, void* y, int64_t batch,
     u.in_sig = u.out_sig = Lz;
     if ((e = fft_lines(u, s)) != hipSuccess) return e;
   }
-  // 2. apply, real part, polyphase gather
-  const int64_t total = batch * r.n_ops * (r.P / 2 + 1);
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1 << 20));
-  hipLaunchKernelGGL(k_apply_real, dim3(grid), dim3(256), 0, s, Zf, Lz, f.blue ? (const float2*)f.chirp : nullptr,
-                     r.wN, r.tab, r.Wo, Zc, r.M, r.n_ops, r.N, r.H, r.n1, r.K, r.P, batch, r.half ? 1 : 0);
+  // 2. apply, real part, polyphase gather: bins across x, signals across y (each thread
+  //    takes every gridDim.y-th signal)
+  const int gx = (int)((r.P / 2 + 1 + 255) / 256);
+  const int gy = (int)std::max<int64_t>(1, std::min<int64_t>({batch, std::max<int64_t>(1, 65536 / gx), 65535}));
+  const int n1r = (int)(((r.n1 % r.N) + r.N) % r.N);
+  hipLaunchKernelGGL(k_apply_real, dim3(gx, gy), dim3(256), 0, s, Zf, Lz, f.blue ? (const float2*)f.chirp : nullptr,
+                     r.wN, r.tab, r.Wo, Zc, r.M, r.n_ops, (int)r.N, (int)r.H, (int)r.n1, n1r, (int)r.K, (int)r.P,
+                     batch, r.half ? 1 : 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // 3. one inverse transform of length P per (signal, op), written as the output row
   LineXform o;
