@@ -14,28 +14,9 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
+from refiner_util import bf16_round, gpu_params, random_params
 
 SL = O.CNN_SLICES
-
-
-def bf16_round(x):
-    """Round FP32 values to the nearest BF16 (ties to even), returned as float32."""
-    x = np.ascontiguousarray(x, dtype=np.float32)
-    b = x.view(np.uint32).astype(np.uint64)
-    r = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
-    return r.astype(np.uint32).view(np.float32)
-
-
-def random_params(seed, scale=1.0):
-    rng = np.random.default_rng(seed)
-    p = np.zeros(O.CNN_NPARAM)
-    p[SL["W1"]] = rng.standard_normal(32 * 27) * np.sqrt(2 / 27) * scale
-    p[SL["W2"]] = rng.standard_normal(32 * 288) * np.sqrt(2 / 288) * scale
-    p[SL["W3"]] = rng.standard_normal(32 * 288) * np.sqrt(2 / 288) * scale
-    p[SL["W4"]] = rng.standard_normal(3 * 288) * 0.05 * scale
-    for b in ("b1", "b2", "b3", "b4"):
-        p[SL[b]] = rng.standard_normal(SL[b].stop - SL[b].start) * 0.05
-    return p
 
 
 # ------------------------------------------------------------------ oracle pins (CPU)
@@ -104,14 +85,6 @@ def torch_cuda():
     return torch
 
 
-def _gpu_params(p):
-    """The parameters the GPU computes with: FP32 biases, BF16-rounded weights."""
-    q = p.astype(np.float32).copy()
-    for w in ("W1", "W2", "W3", "W4"):
-        q[SL[w]] = bf16_round(q[SL[w]])
-    return q
-
-
 def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
@@ -127,7 +100,7 @@ def test_refiner_forward_parity(torch_cuda, H, W):
     r.set_params(p.astype(np.float32))
     y, ratio, used = r.forward(torch_cuda.from_numpy(u).cuda())
     y = y.cpu().numpy().astype(np.float64)
-    want = O.cnn_forward(_gpu_params(p).astype(np.float64), u.astype(np.float64))
+    want = O.cnn_forward(gpu_params(p).astype(np.float64), u.astype(np.float64))
     assert rel(y - u, want - u) <= 2e-2
     # ratio = ||y - u|| / ||u|| per image
     rr = [np.linalg.norm(y[b] - u[b]) / np.linalg.norm(u[b]) for b in range(2)]
@@ -146,7 +119,7 @@ def test_refiner_gradient_parity(torch_cuda):
     r.set_params(p.astype(np.float32))
     loss = float(r.backward(torch_cuda.from_numpy(u).cuda(), torch_cuda.from_numpy(hr).cuda()))
     g = r.get_grads().astype(np.float64)
-    lw, gw = O.cnn_grad(_gpu_params(p).astype(np.float64), u.astype(np.float64), hr.astype(np.float64))
+    lw, gw = O.cnn_grad(gpu_params(p).astype(np.float64), u.astype(np.float64), hr.astype(np.float64))
     assert loss == pytest.approx(lw, rel=2e-2)
     for name, s in SL.items():
         assert rel(g[s], gw[s]) <= 5e-2, (name, rel(g[s], gw[s]))
