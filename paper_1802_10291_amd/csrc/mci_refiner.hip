@@ -96,7 +96,7 @@ struct ConvArgs {
 };
 
 template <int INM, int COUT, int EPI>
-__global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_conv(ConvArgs a) {
   constexpr int NB = COUT / 16;                 // 16-wide output-channel blocks
   __shared__ __attribute__((aligned(16))) bf16 tin[INM == IN32 ? HT * HT * C : HT * HT * 4];
   __shared__ __attribute__((aligned(16))) float tout[T * T * (EPI == EPI_RESID ? 4 : 16)];   // reused per epilogue
@@ -104,11 +104,14 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
   const int tx0 = blockIdx.x * T, ty0 = blockIdx.y * T, b = blockIdx.z;
   const int H = a.H, W = a.W;
   const int px = lane & 15, kb = lane >> 4;
-  // ---- weights of every tap first: their loads overlap the tile's
+  // ---- weights: the first NPRE taps load before the tile (their loads overlap the tile's);
+  // tap t + NPRE loads as tap t's MFMAs start, so at most NPRE + 1 taps are live and the
+  // registers stay within the budget of 4 waves per SIMD
   constexpr int NTAP = INM == IN32 ? 9 : 1;
+  constexpr int NPRE = INM == IN32 ? 4 : 1;
   bf16x8 bw[NTAP][NB];
 #pragma unroll
-  for (int tap = 0; tap < NTAP; ++tap)
+  for (int tap = 0; tap < NPRE; ++tap)
 #pragma unroll
     for (int n = 0; n < NB; ++n)
       bw[tap][n] = INM == IN32 ? *(const bf16x8*)(a.w + ((16 * n + px) * 9 + tap) * C + 8 * kb)
@@ -158,6 +161,10 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
   if constexpr (INM == IN32) {
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
+      if (tap + NPRE < NTAP)
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+          bw[tap + NPRE][n] = *(const bf16x8*)(a.w + ((16 * n + px) * 9 + tap + NPRE) * C + 8 * kb);
       const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
