@@ -356,3 +356,16 @@ def test_table1_on_gpu(torch_cuda, precision):
             w1 = np.linalg.norm(F - want[0]) / np.linalg.norm(F)
             w2 = np.linalg.norm(HF - want[1]) / np.linalg.norm(HF)
             assert abs(e1 - w1) <= 1e-5 and abs(e2 - w2) <= 1e-5, (mu, names, e1, w1, e2, w2)
+
+
+def test_fused_kernel_table_channels(torch_cuda):
+    """The fused kernel with table multipliers: scaled derivatives (i n / N)^m given as
+    tables over the band."""
+    N, n_out, M = 1366, 16384, 3
+    mu = M * N
+    n = np.arange(O.default_n1(mu), O.default_n1(mu) + mu)
+    channels = [("table", (1j * n / N) ** m) for m in range(M)]
+    g = S.smooth_noisy_batch(70, 3, M, N, 2 * N)
+    y, want, plan = run_case(torch_cuda, N, n_out, channels, g=g)
+    assert plan.info.path == 1, "expected the fused kernel"
+    assert_parity(y, want, TOL["f32"])
