@@ -281,10 +281,9 @@ void k_mci1d_fused(FusedArgs a) {
   constexpr int EF = PF / NT, EI = P / NT;
   const int tid = threadIdx.x;
   const int N = a.N, H = a.H, XH = a.H + 1;
-  // layout, each phase from slot 0: forward scratch [M][padded(PF)] | channel spectra
-  // Zc -> X in place [M][H+1], then S [K+1] | output scratch [TI][padded(P)]
+  // layout, each phase from slot 0: forward scratch [M][padded(PF)] | half-length channel
+  // spectra Zc [M][H+1] (X is formed from them in the apply), then S [K+1] | output scratch
   float2* F = sm;
-  float2* X = sm;
   float2* Zc = sm;
   float2* Sv = sm + M * XH;
   float2* Z = sm;
@@ -391,45 +390,40 @@ void k_mci1d_fused(FusedArgs a) {
     __syncthreads();
     if (a.zero_s)
       for (int k = tid; k <= a.K; k += NT) Sv[k] = make_float2(0.f, 0.f);
-    // X[k] = E[k] + w_N^k O[k], k = 0..H, in place over Zc: X[k] and X[H - k] both need
-    // Zc[k] and Zc[H - k] (Zc[0] for k = 0, whose partner is the spare slot H), so the
-    // thread owning the pair reads both before writing and no other thread touches them
-    for (int k = tid; 2 * k <= H; k += NT) {
-      const int kb = H - k, kr = k == 0 ? 0 : kb;
-      const float2 wk = a.wN[k], wb = a.wN[kb];
-#pragma unroll
-      for (int m = 0; m < M; ++m) {
-        const float2 A = Zc[m * XH + k], B = Zc[m * XH + kr];
-        // X[k]: z1 = A, z2 = conj B;  X[kb]: z1 = B, z2 = conj A
-        const float2 e = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
-        const float2 o = make_float2(0.5f * (A.y + B.y), -0.5f * (A.x - B.x));   // (z1 - z2) / (2i)
-        const float2 eb = make_float2(e.x, -e.y);
-        const float2 ob = make_float2(o.x, -o.y);
-        const float2 xk = cadd(e, cmul(wk, o));
-        const float2 xb = cadd(eb, cmul(wb, ob));
-        X[m * XH + k] = xk;
-        X[m * XH + kb] = xb;
-      }
-    }
-    __syncthreads();
+    __syncthreads();   // S zeroed before the apply writes it
     // ---------------- 2. apply, residue pairs -> S
     for (int it = tid; it < a.n_items; it += NT) {
       const int i = it <= a.Ch ? it : a.C + 1 + (it - a.Ch - 1);
       const int ip = i <= a.C ? a.C - i : a.C - i + N;
+      // X_m at residue r = (n1 + i) mod N, formed here from the half-length spectrum:
+      // X[k] = E[k] + w_N^k O[k] for k = min(r, N - r) <= H, conjugated when r > H.  Residue
+      // i' has r' = (N - r) mod N, so its value is the conjugate (the channels are real).
+      int r = a.n1r + i;                        // (n1 + i) mod N, 0 <= i < N
+      if (r >= N) r -= N;
+      const bool lo = r <= H;
+      const int k = lo ? r : N - r;
+      const int k1 = k == H ? 0 : k, k2 = k == 0 ? 0 : H - k;
+      const float2 wn = a.wN[k];
+      float2 d[2][M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const float2 z1 = Zc[m * XH + k1];
+        const float2 z2 = conjf2(Zc[m * XH + k2]);
+        const float2 e = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
+        const float2 o = make_float2(0.5f * (z1.y - z2.y), -0.5f * (z1.x - z2.x));   // (z1 - z2) / (2i)
+        const float2 x = cadd(e, cmul(wn, o));
+        d[0][m] = lo ? x : conjf2(x);
+        d[1][m] = conjf2(d[0][m]);
+      }
       float2 av[2][M];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int ii = q ? ip : i;
-        int r = a.n1r + ii;                     // (n1 + ii) mod N, 0 <= ii < N
-        if (r >= N) r -= N;
-        float2 d[M];
-#pragma unroll
-        for (int m = 0; m < M; ++m) d[m] = r <= H ? X[m * XH + r] : conjf2(X[m * XH + (N - r)]);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
           float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-          for (int m = 0; m < M; ++m) acc = cadd(acc, cmul(d[m], a.tab[(m * M + j) * N + ii]));
+          for (int m = 0; m < M; ++m) acc = cadd(acc, cmul(d[q][m], a.tab[(m * M + j) * N + ii]));
           av[q][j] = acc;
         }
       }
