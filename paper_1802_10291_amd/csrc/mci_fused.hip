@@ -55,6 +55,7 @@ struct FusedArgs {
   int C, Ch, n_items; // residue pairing: i' = (C - i) mod N; canonical items
   int zero_s;         // 1 when some |k| <= K is in neither the band nor its negative
   int n1r;            // n1 mod N, in [0, N)
+  int B0;             // (-2 n1 - C) / N: -(n1 + i + jN) = n1 + i' + (B - j) N, B = B0 for i <= C, else B0 - 1
   const float2* twF;  // PF entries e^{-2 pi i k / PF}
   const float2* chirp;  // H entries e^{-i pi k^2 / H} (Bluestein)
   const float2* bhat;   // full Bluestein: PF entries, DFT_PF of the conjugate chirp, / PF;
@@ -236,6 +237,11 @@ __device__ __forceinline__ void fft_serial(float2* lds, float2 (&v)[T][L / NT], 
 
 // ---------------------------------------------------------------- the fused kernel
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+// acc + a b as four fused multiply-adds
+__device__ __forceinline__ float2 cmac(float2 acc, float2 a, float2 b) {
+  return make_float2(__builtin_fmaf(-a.y, b.y, __builtin_fmaf(a.x, b.x, acc.x)),
+                     __builtin_fmaf(a.y, b.x, __builtin_fmaf(a.x, b.y, acc.y)));
+}
 
 // LDS use of one workgroup, in complex slots (see the layout in the kernel): the forward
 // transforms' scratch, then the channel spectra (computed in place) and S, then the output
@@ -391,6 +397,9 @@ void k_mci1d_fused(FusedArgs a) {
     if (a.zero_s)
       for (int k = tid; k <= a.K; k += NT) Sv[k] = make_float2(0.f, 0.f);
     __syncthreads();   // S zeroed before the apply writes it
+    // the apply table [M][M][N] as a buffer: every load takes one per-residue VGPR offset
+    const __amdgpu_buffer_rsrc_t trs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.tab, (short)0, M * M * N * 8, 0x00020000);
     // ---------------- 2. apply, residue pairs -> S
     for (int it = tid; it < a.n_items; it += NT) {
       const int i = it <= a.Ch ? it : a.C + 1 + (it - a.Ch - 1);
@@ -404,26 +413,54 @@ void k_mci1d_fused(FusedArgs a) {
       const int k = lo ? r : N - r;
       const int k1 = k == H ? 0 : k, k2 = k == 0 ? 0 : H - k;
       const float2 wn = a.wN[k];
-      float2 d[2][M];
+      // d = 2 X_m (the halves of E and O are folded into the final scale of S)
+      float2 d[M];
 #pragma unroll
       for (int m = 0; m < M; ++m) {
         const float2 z1 = Zc[m * XH + k1];
         const float2 z2 = conjf2(Zc[m * XH + k2]);
-        const float2 e = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
-        const float2 o = make_float2(0.5f * (z1.y - z2.y), -0.5f * (z1.x - z2.x));   // (z1 - z2) / (2i)
+        const float2 e = make_float2(z1.x + z2.x, z1.y + z2.y);
+        const float2 o = make_float2(z1.y - z2.y, z2.x - z1.x);   // (z1 - z2) / i
         const float2 x = cadd(e, cmul(wn, o));
-        d[0][m] = lo ? x : conjf2(x);
-        d[1][m] = conjf2(d[0][m]);
+        d[m] = lo ? x : conjf2(x);
+      }
+      // table entries Tab[m][j][.] at residues i and i': one byte offset per residue, the
+      // row offsets (m M + j) N are uniform
+      const int o0 = i * 8, o1 = ip * 8;
+      auto tab = [&](int m, int j, int off) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(trs, off, (m * M + j) * N * 8, 0);
+        float2 t;
+        __builtin_memcpy(&t, &v, sizeof t);
+        return t;
+      };
+      const int B = i <= a.C ? a.B0 : a.B0 - 1;
+      if (B == M - 1) {
+        // every band position of residue i has its negative at residue i': position j pairs
+        // with position M - 1 - j, and S(|k|) = (a(k) + conj a(-k)) / 2 (conjugated for k < 0)
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          float2 s0 = cmul(d[0], tab(0, j, o0)), s1 = cmul(conjf2(d[0]), tab(0, M - 1 - j, o1));
+#pragma unroll
+          for (int m = 1; m < M; ++m) {
+            s0 = cmac(s0, d[m], tab(m, j, o0));
+            s1 = cmac(s1, conjf2(d[m]), tab(m, M - 1 - j, o1));
+          }
+          const float2 sv = make_float2(0.25f * (s0.x + s1.x), 0.25f * (s0.y - s1.y));
+          const int k = a.n1 + i + j * N;
+          if (k >= 0) Sv[k] = sv;
+          else Sv[-k] = conjf2(sv);
+        }
+        continue;
       }
       float2 av[2][M];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int ii = q ? ip : i;
+        const int oo = q ? o1 : o0;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-          float2 acc = make_float2(0.f, 0.f);
+          float2 acc = cmul(q ? conjf2(d[0]) : d[0], tab(0, j, oo));
 #pragma unroll
-          for (int m = 0; m < M; ++m) acc = cadd(acc, cmul(d[q][m], a.tab[(m * M + j) * N + ii]));
+          for (int m = 1; m < M; ++m) acc = cmac(acc, q ? conjf2(d[m]) : d[m], tab(m, j, oo));
           av[q][j] = acc;
         }
       }
@@ -442,8 +479,8 @@ void k_mci1d_fused(FusedArgs a) {
           for (int jp = 0; jp < M; ++jp)
             if (num == jp * N) { has = true; pv = av[q ^ (single ? 0 : 1)][jp]; }
           const float2 val = av[q][j];
-          if (k >= 0) Sv[k] = make_float2(0.5f * (val.x + pv.x), 0.5f * (val.y - pv.y));
-          else if (!has) Sv[-k] = make_float2(0.5f * val.x, -0.5f * val.y);
+          if (k >= 0) Sv[k] = make_float2(0.25f * (val.x + pv.x), 0.25f * (val.y - pv.y));
+          else if (!has) Sv[-k] = make_float2(0.25f * val.x, -0.25f * val.y);
         }
       }
     }
@@ -697,6 +734,7 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   a->zero_s = (n1 > 0 || n1 + mu - 1 < 0) ? 1 : 0;
   a->n_items = a->Ch + 1 + (int)((a->C + N) / 2 - a->C);
   a->n1r = (int)(((n1 % N) + N) % N);
+  a->B0 = (int)((-2 * n1 - a->C) / N);
   a->twF = dt + o_twF; a->chirp = dt + o_chirp; a->bhat = dt + o_bhat; a->wN = dt + o_wN;
   a->tab = (const float2*)tab; a->twI = dt + o_twI; a->U = dt + o_U;
   fp.tables = dt;
