@@ -33,6 +33,7 @@
 // of the last pass -- which lets the Bluestein forward FFT, the pointwise product and the
 // inverse FFT run back to back in registers.
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 #include <complex>
 #include <vector>
@@ -64,6 +65,7 @@ struct FusedArgs {
   const float2* tab;    // [M][M][N]: q_mj(n1 + i) o(.) / N
   const float2* twI;    // P entries e^{-2 pi i k / P}
   const float2* U;      // [Q/2][2K + 1]: w^{k r0} + i w^{k r1} for k = -K..K, w = e^{2 pi i / Nout}
+  const float2* Ub;     // [Q/2][P]: U at the main band position of b (b if b <= K, else b - P), 0 if none
 };
 
 // ---------------------------------------------------------------- register-staged FFT
@@ -488,19 +490,45 @@ void k_mci1d_fused(FusedArgs a) {
     // ---------------- 3. output grid: Q/2 complex inverse FFTs of length P, TI at a time
     TS* ys = (TS*)a.y + (a.offs ? a.offs[2 * sig + 1] : sig * (int64_t)a.Nout);
     float2 keep[(Q / 2 - TI > 0 ? Q / 2 - TI : 1)][EI];   // earlier transforms' outputs
-    // every transform's input is gathered from S first: the scratch then reuses S's space
+    // every transform's input is gathered from S first: the scratch then reuses S's space.
+    // Zc[b] sums S~(k) U(k) over the band positions k = b and k = b - P (K < P), where S~(k) is
+    // S(k) for k >= 0 and conj S(-k) for k < 0.  The main position is b when b <= K, else
+    // b - P; its multiplier comes from a per-b table that is zero where neither position is
+    // in the band.  Both are in the band only on [P - K, K], where the second term is added.
+    const __amdgpu_buffer_rsrc_t urs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.Ub, (short)0, (Q / 2) * P * 8, 0x00020000);
     float2 vin[Q / 2][EI];
+    // in groups of GW elements: the second term's branch after each group bounds how many of
+    // the table loads the compiler hoists (registers)
+    constexpr int GW = EI < 4 ? EI : 4;
 #pragma unroll
-    for (int pc = 0; pc < Q / 2; ++pc) {
-      const float2* U = a.U + (int64_t)pc * (2 * a.K + 1) + a.K;   // U[k], k = -K..K
+    for (int c0 = 0; c0 < EI; c0 += GW) {
 #pragma unroll
-      for (int c = 0; c < EI; ++c) {
+      for (int c = c0; c < c0 + GW; ++c) {
         const int b = tid + NT * c;
-        float2 acc = make_float2(0.f, 0.f);
-        if (b <= a.K) acc = cmul(Sv[b], U[b]);
-        const int k2 = b - P;                  // the other band position congruent to b (K < P)
-        if (k2 >= -a.K) acc = cadd(acc, cmul(conjf2(Sv[-k2]), U[k2]));
-        vin[pc][c] = acc;
+        const bool lo = b <= a.K;
+        const int kk = min(lo ? b : P - b, a.K);   // clamped where the multiplier is zero
+        float2 sv = Sv[kk];
+        if (!lo) sv.y = -sv.y;
+#pragma unroll
+        for (int pc = 0; pc < Q / 2; ++pc) {
+          const auto u = __builtin_amdgcn_raw_buffer_load_b64(urs, tid * 8, (pc * P + NT * c) * 8, 0);
+          float2 uf;
+          __builtin_memcpy(&uf, &u, sizeof uf);
+          vin[pc][c] = cmul(sv, uf);
+        }
+      }
+#pragma unroll
+      for (int c = c0; c < c0 + GW; ++c) {
+        const int b = tid + NT * c;
+        if (NT * c + NT - 1 >= P - a.K && NT * c <= a.K) {   // this block meets [P - K, K]
+          if (b >= P - a.K && b <= a.K) {
+            const float2 s2 = conjf2(Sv[P - b]);
+#pragma unroll
+            for (int pc = 0; pc < Q / 2; ++pc)
+              vin[pc][c] = cadd(vin[pc][c], cmul(s2, a.U[(int64_t)pc * (2 * a.K + 1) + a.K + (b - P)]));
+          }
+        }
       }
     }
     if constexpr (TI == 1 && Q == 4) {
@@ -675,7 +703,7 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   const int PF = pick->PF, P = pick->P;
   const int Q = pick->Q;
   std::vector<std::complex<double>> twF(PF), chirp(H), bhat((size_t)(pick->blue == 2 ? 2 : 1) * PF, 0.0), wN(H + 1),
-      twI(P), U((size_t)(Q / 2) * (2 * K + 1));
+      twI(P), U((size_t)(Q / 2) * (2 * K + 1)), Ub((size_t)(Q / 2) * P, 0.0);
   for (int k = 0; k < PF; ++k) twF[k] = root_of_unity(k, PF);
   for (int64_t k = 0; k <= H; ++k) wN[k] = root_of_unity(k, N);
   for (int k = 0; k < P; ++k) twI[k] = root_of_unity(k, P);
@@ -685,6 +713,12 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
       const std::complex<double> w0 = std::conj(root_of_unity(k * (2 * pc), d.n_out));
       const std::complex<double> w1 = std::conj(root_of_unity(k * (2 * pc + 1), d.n_out));
       U[(size_t)pc * (2 * K + 1) + (k + K)] = w0 + std::complex<double>(0.0, 1.0) * w1;
+    }
+  // Ub[pc][b] = U at b's main band position: b if b <= K, else b - P if b >= P - K
+  for (int pc = 0; pc < Q / 2; ++pc)
+    for (int64_t b = 0; b < P; ++b) {
+      const int64_t k = b <= K ? b : (b >= P - K ? b - P : INT64_MIN);
+      if (k != INT64_MIN) Ub[(size_t)pc * P + b] = U[(size_t)pc * (2 * K + 1) + (k + K)];
     }
   if (pick->blue) {
     for (int64_t k = 0; k < H; ++k) chirp[k] = chirp_value(k, H, -1);
@@ -709,7 +743,7 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
     }
     for (auto& x : bhat) x /= (double)PF;
   }
-  const size_t n_all = twF.size() + chirp.size() + bhat.size() + wN.size() + twI.size() + U.size();
+  const size_t n_all = twF.size() + chirp.size() + bhat.size() + wN.size() + twI.size() + U.size() + Ub.size();
   std::vector<float2> h(n_all);
   size_t o = 0;
   auto put = [&](const std::vector<std::complex<double>>& v) {
@@ -718,7 +752,7 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
     return at;
   };
   const size_t o_twF = put(twF), o_chirp = put(chirp), o_bhat = put(bhat), o_wN = put(wN), o_twI = put(twI),
-               o_U = put(U);
+               o_U = put(U), o_Ub = put(Ub);
   float2* dt = nullptr;
   if (hipMalloc(&dt, n_all * sizeof(float2)) != hipSuccess) return MCI_E_OUT_OF_MEMORY;
   if (hipMemcpy(dt, h.data(), n_all * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
@@ -736,7 +770,7 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   a->n1r = (int)(((n1 % N) + N) % N);
   a->B0 = (int)((-2 * n1 - a->C) / N);
   a->twF = dt + o_twF; a->chirp = dt + o_chirp; a->bhat = dt + o_bhat; a->wN = dt + o_wN;
-  a->tab = (const float2*)tab; a->twI = dt + o_twI; a->U = dt + o_U;
+  a->tab = (const float2*)tab; a->twI = dt + o_twI; a->U = dt + o_U; a->Ub = dt + o_Ub;
   fp.tables = dt;
   fp.args = a;
   fp.lds_bytes = (int)lds;
