@@ -111,15 +111,36 @@ __device__ __forceinline__ void dft_r(float2* u) {
 }
 
 template <int... Rs> struct RList {};
+template <int R0, int... Rs> struct RList<R0, Rs...> { static constexpr int first = R0; };
 
 // T independent length-L transforms (buffer t at lds + t * padded(L)); one Stockham pass of
 // radix R at stage size NS, then the remaining passes.  On entry v[t][c] holds element
 // tid + NT c of transform t's pass input; after the last pass it holds element tid + NT c
 // of the transform.  SX: the transforms share one buffer and exchange one after the other
 // (the butterflies of all T still share their twiddles).
+// Base twiddles of a pass, loaded before the exchange that precedes it so that the load
+// overlaps the barrier waits (at most 2 butterflies per thread for the radices used here).
+struct PassTw {
+  float2 w1[2], w4[2];
+};
+template <int L, int NS, int R>
+__device__ __forceinline__ PassTw load_pass_tw(const float2* __restrict__ tw) {
+  constexpr int BPT = (L / NT) / R;
+  static_assert(BPT <= 2, "prefetch holds two butterflies");
+  PassTw p;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int j = threadIdx.x + NT * b;
+    const int k1 = (j % NS) * (L / (NS * R));
+    p.w1[b] = tw[k1];
+    if constexpr (R >= 8) p.w4[b] = tw[4 * k1];
+  }
+  return p;
+}
+
 template <int L, int S, int T, bool SX, int NS, int R, int... Rest>
 __device__ __forceinline__ void fft_passes(float2* __restrict__ lds, float2 (&v)[T][L / NT],
-                                           const float2* __restrict__ tw, RList<R, Rest...>) {
+                                           const float2* __restrict__ tw, RList<R, Rest...>, const PassTw& ptw) {
   constexpr int E = L / NT;
   constexpr int BPT = E / R;
   constexpr int LP = padded(L);
@@ -135,13 +156,11 @@ __device__ __forceinline__ void fft_passes(float2* __restrict__ lds, float2 (&v)
     if constexpr (NS > 1) {
       // powers w^r of the butterfly's base twiddle, formed as they are used; w^1 and w^4 are
       // exact table entries, every other power is at most three roundings away from them
-      const int j = tid + NT * b;
-      const int k1 = (j % NS) * (L / (NS * R));
-      float2 w1 = tw[k1];
+      float2 w1 = ptw.w1[b];
       if constexpr (S > 0) w1.y = -w1.y;
       float2 w4 = w1;
       if constexpr (R >= 8) {
-        w4 = tw[4 * k1];
+        w4 = ptw.w4[b];
         if constexpr (S > 0) w4.y = -w4.y;
       }
       float2 wl[4];
@@ -186,6 +205,7 @@ __device__ __forceinline__ void fft_passes(float2* __restrict__ lds, float2 (&v)
     // pad(base + r NS) = pad(base) + r NS + (r NS) / 16: one address per butterfly, the
     // rest are immediate offsets.  Likewise pad(tid + NT c) = pad(tid) + c (NT + NT / 16).
     const int pt = pad(tid);
+    const PassTw ntw = load_pass_tw<L, NS * R, RList<Rest...>::first>(tw);
     if constexpr (SX) {
 #pragma unroll
       for (int t = 0; t < T; ++t) {
@@ -218,7 +238,7 @@ __device__ __forceinline__ void fft_passes(float2* __restrict__ lds, float2 (&v)
 #pragma unroll
         for (int c = 0; c < E; ++c) v[t][c] = lds[t * LP + pt + c * (NT + NT / 16)];
     }
-    fft_passes<L, S, T, SX, NS * R>(lds, v, tw, RList<Rest...>{});
+    fft_passes<L, S, T, SX, NS * R>(lds, v, tw, RList<Rest...>{}, ntw);
   }
 }
 
@@ -229,12 +249,12 @@ template <> struct Radices<4096> { using type = RList<16, 16, 16>; };
 
 template <int L, int S, int T>
 __device__ __forceinline__ void fft(float2* lds, float2 (&v)[T][L / NT], const float2* tw) {
-  fft_passes<L, S, T, false, 1>(lds, v, tw, typename Radices<L>::type{});
+  fft_passes<L, S, T, false, 1>(lds, v, tw, typename Radices<L>::type{}, PassTw{});
 }
 // T transforms through one scratch buffer of padded(L) slots
 template <int L, int S, int T>
 __device__ __forceinline__ void fft_serial(float2* lds, float2 (&v)[T][L / NT], const float2* tw) {
-  fft_passes<L, S, T, true, 1>(lds, v, tw, typename Radices<L>::type{});
+  fft_passes<L, S, T, true, 1>(lds, v, tw, typename Radices<L>::type{}, PassTw{});
 }
 
 // ---------------------------------------------------------------- the fused kernel
