@@ -346,19 +346,34 @@ void k_mci1d_fused(FusedArgs a) {
           }
         }
       }
+      // the split form's kernel spectra, loaded here so that the loads overlap the transform
+      float2 bh[BLUE == 2 ? 2 : 1][EF];
+      if constexpr (BLUE == 2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int c = 0; c < EF; ++c) bh[h][c] = a.bhat[h * PF + tid + NT * c];
+      }
       fft<PF, -1, M>(F, v, a.twF);
       if constexpr (BLUE == 2) {
         // two output halves from one forward transform; the first half's outputs wait in
         // registers until the second transform is done with the scratch
         const int Ko = (H + 1) / 2;
         float2 w0[M][EF], w[M][EF];
+        float2 ch[2][EF];   // output chirp at k0 and k1 (clamped), loaded before the second transform
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
 #pragma unroll
-          for (int c = 0; c < EF; ++c) {
-            const float2 bh = a.bhat[h * PF + tid + NT * c];
+          for (int c = 0; c < EF; ++c)
 #pragma unroll
-            for (int m = 0; m < M; ++m) w[m][c] = cmul(v[m][c], bh);
+            for (int m = 0; m < M; ++m) w[m][c] = cmul(v[m][c], bh[h][c]);
+          if (h == 1) {
+#pragma unroll
+            for (int c = 0; c < EF; ++c) {
+              const int e = tid + NT * c;
+              ch[0][c] = a.chirp[min(max(e - (H - 1), 0), H - 1)];
+              ch[1][c] = a.chirp[min(max(Ko + e - (H - 1), 0), H - 1)];
+            }
           }
           fft<PF, +1, M>(F, w, a.twF);
           if (h == 0) {
@@ -375,14 +390,12 @@ void k_mci1d_fused(FusedArgs a) {
           if (e >= H - 1) {
             const int k0 = e - (H - 1), k1 = Ko + e - (H - 1);
             if (k0 < Ko) {
-              const float2 ch = a.chirp[k0];
 #pragma unroll
-              for (int m = 0; m < M; ++m) Zc[m * XH + k0] = cmul(w0[m][c], ch);
+              for (int m = 0; m < M; ++m) Zc[m * XH + k0] = cmul(w0[m][c], ch[0][c]);
             }
             if (k1 < H) {
-              const float2 ch = a.chirp[k1];
 #pragma unroll
-              for (int m = 0; m < M; ++m) Zc[m * XH + k1] = cmul(w[m][c], ch);
+              for (int m = 0; m < M; ++m) Zc[m * XH + k1] = cmul(w[m][c], ch[1][c]);
             }
           }
         }
