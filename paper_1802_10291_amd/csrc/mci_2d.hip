@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <type_traits>
 #include <complex>
 #include <vector>
@@ -67,14 +68,44 @@ __global__ __launch_bounds__(line_threads<N>()) void k_line_pass(LinePassArgs a)
   }
   // ---- load 32 lines into the tile (line-major)
   const int64_t xoff = COLS ? (a.offs ? a.offs[2 * img] : img * N * (int64_t)a.W) : 0;
+  // FP32 inputs are read as float4 where the rows allow it (N is a multiple of 16, so four
+  // consecutive values of a row segment never straddle a line or the image's last column
+  // when W is a multiple of 4)
   if constexpr (COLS) {
     // row n of image img, columns col0 .. col0 + 31: 32 contiguous values per row
-    for (int e = tid; e < N * LINES; e += NT) {
-      const int n = e / LINES, c = e % LINES;
-      const int64_t col = col0 + c;
-      float v = 0.f;
-      if (col < a.W) v = ld_as<float>(x, xoff + n * (int64_t)a.W + col);
-      tile[c * TS + n] = v;
+    bool vec = false;
+    if constexpr (std::is_same<TI, float>::value) vec = ((xoff | a.W) & 3) == 0 && ((uintptr_t)x & 15) == 0;
+    if (vec) {
+      for (int e4 = tid; e4 < N * LINES / 4; e4 += NT) {
+        const int n = e4 / (LINES / 4), c = 4 * (e4 % (LINES / 4));
+        const int64_t col = col0 + c;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (col < a.W) v = *(const float4*)((const float*)x + xoff + n * (int64_t)a.W + col);
+        tile[c * TS + n] = v.x;
+        tile[(c + 1) * TS + n] = v.y;
+        tile[(c + 2) * TS + n] = v.z;
+        tile[(c + 3) * TS + n] = v.w;
+      }
+    } else {
+      for (int e = tid; e < N * LINES; e += NT) {
+        const int n = e / LINES, c = e % LINES;
+        const int64_t col = col0 + c;
+        float v = 0.f;
+        if (col < a.W) v = ld_as<float>(x, xoff + n * (int64_t)a.W + col);
+        tile[c * TS + n] = v;
+      }
+    }
+  } else if constexpr (std::is_same<TI, float>::value) {
+    // 32 consecutive lines of the intermediate are one contiguous block
+    const float4* x4 = (const float4*)((const float*)x + line0 * N);
+    for (int e4 = tid; e4 < N * LINES / 4; e4 += NT) {
+      const int c = (4 * e4) / N, n = (4 * e4) % N;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (line0 + c < a.lines) v = x4[e4];
+      tile[c * TS + n] = v.x;
+      tile[c * TS + n + 1] = v.y;
+      tile[c * TS + n + 2] = v.z;
+      tile[c * TS + n + 3] = v.w;
     }
   } else {
     for (int e = tid; e < N * LINES; e += NT) {
@@ -148,11 +179,23 @@ __global__ __launch_bounds__(line_threads<N>()) void k_line_pass(LinePassArgs a)
         }
       }
       __syncthreads();
-      for (int e = tid; e < (SC * N / OP) * LINES; e += NT) {
-        const int row = e / LINES, c = e % LINES;
-        const int64_t col = col0 + c;
-        if (col < a.W)
-          st_as<float>(y, (img * (SC * N) + part * (SC * N / OP) + row) * (int64_t)a.W + col, otile[row * OT + c]);
+      if ((a.W & 3) == 0 && ((uintptr_t)y & 15) == 0) {
+        // four consecutive columns of an output row per float4 store
+        for (int e4 = tid; e4 < (SC * N / OP) * LINES / 4; e4 += NT) {
+          const int row = e4 / (LINES / 4), c = 4 * (e4 % (LINES / 4));
+          const int64_t col = col0 + c;
+          if (col < a.W)
+            *(float4*)((float*)y + (img * (SC * N) + part * (SC * N / OP) + row) * (int64_t)a.W + col) =
+                make_float4(otile[row * OT + c], otile[row * OT + c + 1], otile[row * OT + c + 2],
+                            otile[row * OT + c + 3]);
+        }
+      } else {
+        for (int e = tid; e < (SC * N / OP) * LINES; e += NT) {
+          const int row = e / LINES, c = e % LINES;
+          const int64_t col = col0 + c;
+          if (col < a.W)
+            st_as<float>(y, (img * (SC * N) + part * (SC * N / OP) + row) * (int64_t)a.W + col, otile[row * OT + c]);
+        }
       }
     }
   }
