@@ -89,22 +89,43 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
   const int tid = threadIdx.x;
   const int g = tid / G, l = tid % G;
   const int64_t t0 = (int64_t)blockIdx.x * FL;
+  // plain complex input (no chirp, no real or FP16 storage): a bare load per element
+  const bool plain = !a.real_in && !a.pre && !a.in_half;
   if constexpr (IN_T) {
     const int64_t tr = t0 / a.U, u0 = t0 - tr * a.U;
     const int64_t base = a.si.base(tr);
-    for (int e = tid; e < N * FL; e += NT) {
-      const int n = e / FL, c = e % FL;
-      sml[c * TS + n] = load_in(a, base, u0 + c + n * a.e_in);
+    if (plain) {
+      for (int e = tid; e < N * FL; e += NT) {
+        const int n = e / FL, c = e % FL;
+        sml[c * TS + n] = a.in[base + u0 + c + n * a.e_in];
+      }
+    } else {
+      for (int e = tid; e < N * FL; e += NT) {
+        const int n = e / FL, c = e % FL;
+        sml[c * TS + n] = load_in(a, base, u0 + c + n * a.e_in);
+      }
     }
   } else {
-    for (int e = tid; e < N * FL; e += NT) {
-      const int c = e / N, n = e % N;
-      const int64_t t = t0 + c;
-      float2 v = make_float2(0.f, 0.f);
+    // the 16 lines' transform bases and in-transform offsets, once per workgroup (the
+    // divisions by U and by the side's lines per signal stay out of the element loop)
+    __shared__ int64_t lbase[FL], lpos[FL];
+    if (tid < FL) {
+      const int64_t t = t0 + tid;
+      int64_t b = -1, pos = 0;
       if (t < a.n_lines) {
         const int64_t tr = t / a.U, u = t - tr * a.U;
-        v = load_in(a, a.si.base(tr), u * a.u_in + n);
+        b = a.si.base(tr);
+        pos = u * a.u_in;
       }
+      lbase[tid] = b;
+      lpos[tid] = pos;
+    }
+    __syncthreads();
+    for (int e = tid; e < N * FL; e += NT) {
+      const int c = e / N, n = e % N;
+      const int64_t b = lbase[c];
+      float2 v = make_float2(0.f, 0.f);
+      if (b >= 0) v = plain ? a.in[b + lpos[c] + n] : load_in(a, b, lpos[c] + n);
       sml[c * TS + n] = v;
     }
   }
