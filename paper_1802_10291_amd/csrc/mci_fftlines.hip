@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 
 #include "mci_fftlines.h"
@@ -94,7 +95,16 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
   if constexpr (IN_T) {
     const int64_t tr = t0 / a.U, u0 = t0 - tr * a.U;
     const int64_t base = a.si.base(tr);
-    if (plain) {
+    if (plain && ((base + u0) & 1) == 0 && (a.e_in & 1) == 0 && ((uintptr_t)a.in & 15) == 0) {
+      // two neighbouring lines' elements per float4 (u0 is a multiple of 16, so every pair
+      // starts at an even element)
+      for (int e2 = tid; e2 < N * FL / 2; e2 += NT) {
+        const int n = e2 / (FL / 2), c = 2 * (e2 % (FL / 2));
+        const float4 v = *(const float4*)(a.in + base + u0 + c + n * a.e_in);
+        sml[c * TS + n] = make_float2(v.x, v.y);
+        sml[(c + 1) * TS + n] = make_float2(v.z, v.w);
+      }
+    } else if (plain) {
       for (int e = tid; e < N * FL; e += NT) {
         const int n = e / FL, c = e % FL;
         sml[c * TS + n] = a.in[base + u0 + c + n * a.e_in];
@@ -153,12 +163,21 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
     __syncthreads();
     const int64_t tr0 = t0 / a.U, u0 = t0 - tr0 * a.U;
     const int64_t base = a.so.base(tr0);
-    for (int e = tid; e < N * FL; e += NT) {
-      const int k = e / FL, c = e % FL;
-      const int64_t q = u0 + c + k * a.e_out;
-      float2 w = sml[k * OS + c];
-      if (a.post) w = cmul(w, a.post[q]);
-      store_out(a, base + q, w);
+    if (!a.post && !a.out_half && ((base + u0) & 1) == 0 && (a.e_out & 1) == 0 && ((uintptr_t)a.out & 15) == 0) {
+      // two neighbouring lines' outputs per float4 store
+      for (int e2 = tid; e2 < N * FL / 2; e2 += NT) {
+        const int k = e2 / (FL / 2), c = 2 * (e2 % (FL / 2));
+        const float2 w0 = sml[k * OS + c], w1 = sml[k * OS + c + 1];
+        *(float4*)(a.out + base + u0 + c + k * a.e_out) = make_float4(w0.x, w0.y, w1.x, w1.y);
+      }
+    } else {
+      for (int e = tid; e < N * FL; e += NT) {
+        const int k = e / FL, c = e % FL;
+        const int64_t q = u0 + c + k * a.e_out;
+        float2 w = sml[k * OS + c];
+        if (a.post) w = cmul(w, a.post[q]);
+        store_out(a, base + q, w);
+      }
     }
   } else {
     if (t < a.n_lines) {
