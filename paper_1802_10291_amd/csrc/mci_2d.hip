@@ -42,6 +42,11 @@ constexpr int PAIRS = 16;
 
 using namespace lfft;
 
+// the images are read once and the upsampled rows written once: non-temporal accesses
+// (the column-to-row intermediate keeps ordinary ones, the row pass reads it back)
+typedef float f2_nt __attribute__((ext_vector_type(2)));
+typedef float f4_nt __attribute__((ext_vector_type(4)));
+
 template <int N> constexpr int line_threads() { return PAIRS * (N / LineFFT<N>::E); }
 // output row blocks that go through the LDS tile in the columns pass
 template <int N, int SC> constexpr int out_parts() { return SC * N > 1024 ? 4 : 2; }
@@ -80,7 +85,10 @@ __global__ __launch_bounds__(line_threads<N>()) void k_line_pass(LinePassArgs a)
         const int n = e4 / (LINES / 4), c = 4 * (e4 % (LINES / 4));
         const int64_t col = col0 + c;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (col < a.W) v = *(const float4*)((const float*)x + xoff + n * (int64_t)a.W + col);
+        if (col < a.W) {
+          const f4_nt t = __builtin_nontemporal_load((const f4_nt*)((const float*)x + xoff + n * (int64_t)a.W + col));
+          v = make_float4(t.x, t.y, t.z, t.w);
+        }
         tile[c * TS + n] = v.x;
         tile[(c + 1) * TS + n] = v.y;
         tile[(c + 2) * TS + n] = v.z;
@@ -150,9 +158,11 @@ __global__ __launch_bounds__(line_threads<N>()) void k_line_pass(LinePassArgs a)
 #pragma unroll
         for (int r = 0; r < SC; ++r) o[r] = h2 ? out[r][c].y : out[r][c].x;
         if constexpr (std::is_same<TO, float>::value && SC == 4) {
-          *(float4*)(yl + 4 * q) = make_float4(o[0], o[1], o[2], o[3]);
+          const f4_nt t = {o[0], o[1], o[2], o[3]};
+          __builtin_nontemporal_store(t, (f4_nt*)(yl + 4 * q));
         } else if constexpr (std::is_same<TO, float>::value && SC == 2) {
-          *(float2*)(yl + 2 * q) = make_float2(o[0], o[1]);
+          const f2_nt t = {o[0], o[1]};
+          __builtin_nontemporal_store(t, (f2_nt*)(yl + 2 * q));
         } else {
 #pragma unroll
           for (int r = 0; r < SC; ++r) st_as<float>(yl, (int64_t)SC * q + r, o[r]);

@@ -282,22 +282,33 @@ __host__ __device__ constexpr int fused_slots(int PF, int P, int TI, int Q, int 
 constexpr int fused_waves(int PF, int M) { return PF <= 1024 && M <= 3 ? 4 : 3; }
 
 // Storage access: two consecutive real samples as one complex value, and four consecutive
-// outputs as one vector store (FP32, or FP16 with round-to-nearest conversion).
-__device__ __forceinline__ float2 ld_pair(const float* r, int p) { return ((const float2*)r)[p]; }
+// outputs as one vector store (FP32, or FP16 with round-to-nearest conversion).  Samples are
+// read once and outputs written once, so both use non-temporal (streaming) accesses, which
+// leave L2 to the plan tables every workgroup reads.
+typedef float f2_nt __attribute__((ext_vector_type(2)));
+typedef float f4_nt __attribute__((ext_vector_type(4)));
+typedef unsigned u2_nt __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_pair(const float* r, int p) {
+  const f2_nt v = __builtin_nontemporal_load((const f2_nt*)r + p);
+  return make_float2(v.x, v.y);
+}
 __device__ __forceinline__ float2 ld_pair(const __half* r, int p) {
-  return __half22float2(((const __half2*)r)[p]);
+  const unsigned u = __builtin_nontemporal_load((const unsigned*)r + p);
+  __half2 h;
+  __builtin_memcpy(&h, &u, sizeof h);
+  return __half22float2(h);
 }
 __device__ __forceinline__ void st_pair(float* y, int q, float2 v) { ((float2*)y)[q] = v; }
 __device__ __forceinline__ void st_pair(__half* y, int q, float2 v) { ((__half2*)y)[q] = __float22half2_rn(v); }
 __device__ __forceinline__ void st_quad(float* y, int q, float2 lo, float2 hi) {
-  ((float4*)y)[q] = make_float4(lo.x, lo.y, hi.x, hi.y);
+  const f4_nt v = {lo.x, lo.y, hi.x, hi.y};
+  __builtin_nontemporal_store(v, (f4_nt*)y + q);
 }
 __device__ __forceinline__ void st_quad(__half* y, int q, float2 lo, float2 hi) {
-  const __half2 a = __float22half2_rn(lo), b = __float22half2_rn(hi);
-  uint2 u;
-  __builtin_memcpy(&u.x, &a, 4);
-  __builtin_memcpy(&u.y, &b, 4);
-  ((uint2*)y)[q] = u;
+  const __half2 h[2] = {__float22half2_rn(lo), __float22half2_rn(hi)};
+  u2_nt u;
+  __builtin_memcpy(&u, h, sizeof u);
+  __builtin_nontemporal_store(u, (u2_nt*)y + q);
 }
 
 // TI: how many of the Q/2 output transforms run side by side (1 or Q/2).  TS: storage type
