@@ -111,10 +111,12 @@ __global__ __launch_bounds__(NG) void k_gather_lds(EvalArgs a) {
   const int64_t L = a.L;
   {
     // 16-byte copies: a row is L sizeof(V) bytes, a multiple of 16 (L is a power of two >= 32)
-    const uint4* src = (const uint4*)((const V*)a.grid + r * L);
-    uint4* dst = (uint4*)row;
+    // the row is read once (non-temporal), leaving L2 to the shared weight table
+    typedef unsigned u4_nt __attribute__((ext_vector_type(4)));
+    const u4_nt* src = (const u4_nt*)((const V*)a.grid + r * L);
+    u4_nt* dst = (u4_nt*)row;
     const int64_t n16 = L * (int64_t)sizeof(V) / 16;
-    for (int64_t q = threadIdx.x; q < n16; q += NG) dst[q] = src[q];
+    for (int64_t q = threadIdx.x; q < n16; q += NG) dst[q] = __builtin_nontemporal_load(src + q);
   }
   __syncthreads();
   const T* wt = (const T*)a.wt;
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(NG) void k_gather_lds(EvalArgs a) {
       T acc = T(0);
 #pragma unroll
       for (int k = 0; k < W; ++k) acc += c[k] * row[(s0 + k) & mask];
-      ((T*)a.y)[r * a.n_t + j] = acc;
+      __builtin_nontemporal_store(acc, (T*)a.y + r * a.n_t + j);
     } else {
       T re = T(0), im = T(0);
 #pragma unroll
@@ -140,8 +142,8 @@ __global__ __launch_bounds__(NG) void k_gather_lds(EvalArgs a) {
         im += c[k] * g.y;
       }
       T* y = (T*)a.y + 2 * (r * a.n_t + j);
-      y[0] = re;
-      y[1] = im;
+      __builtin_nontemporal_store(re, y);
+      __builtin_nontemporal_store(im, y + 1);
     }
   }
 }
