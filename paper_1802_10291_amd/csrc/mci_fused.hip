@@ -72,6 +72,11 @@ struct FusedArgs {
 // LDS index with one padding slot per 16 complex values: the stride-R writes of the first
 // Stockham passes then spread over all banks.
 __device__ __forceinline__ int pad(int x) { return x + (x >> 4); }
+
+// Word 3 of a buffer resource for untyped (raw) access on this architecture: buffer loads
+// then take a byte offset in one VGPR and a uniform one in an SGPR, with no 64-bit address
+// arithmetic per access.
+constexpr int kRawBufferWord3 = 0x00020000;
 constexpr int padded(int n) { return n + (n >> 4) + 1; }
 static_assert(NT % 16 == 0, "pad(tid + NT c) = pad(tid) + c (NT + NT / 16) needs NT % 16 == 0");
 
@@ -113,11 +118,6 @@ __device__ __forceinline__ void dft_r(float2* u) {
 template <int... Rs> struct RList {};
 template <int R0, int... Rs> struct RList<R0, Rs...> { static constexpr int first = R0; };
 
-// T independent length-L transforms (buffer t at lds + t * padded(L)); one Stockham pass of
-// radix R at stage size NS, then the remaining passes.  On entry v[t][c] holds element
-// tid + NT c of transform t's pass input; after the last pass it holds element tid + NT c
-// of the transform.  SX: the transforms share one buffer and exchange one after the other
-// (the butterflies of all T still share their twiddles).
 // Base twiddles of a pass, loaded before the exchange that precedes it so that the load
 // overlaps the barrier waits (at most 2 butterflies per thread for the radices used here).
 struct PassTw {
@@ -138,6 +138,12 @@ __device__ __forceinline__ PassTw load_pass_tw(const float2* __restrict__ tw) {
   return p;
 }
 
+// T independent length-L transforms (buffer t at lds + t * padded(L)); one Stockham pass of
+// radix R at stage size NS, then the remaining passes.  On entry v[t][c] holds element
+// tid + NT c of transform t's pass input; after the last pass it holds element tid + NT c
+// of the transform.  SX: the transforms share one buffer and exchange one after the other
+// (the butterflies of all T still share their twiddles).  ptw: this pass's base twiddles
+// (unused by the first pass, NS = 1).
 template <int L, int S, int T, bool SX, int NS, int R, int... Rest>
 __device__ __forceinline__ void fft_passes(float2* __restrict__ lds, float2 (&v)[T][L / NT],
                                            const float2* __restrict__ tw, RList<R, Rest...>, const PassTw& ptw) {
@@ -445,7 +451,7 @@ void k_mci1d_fused(FusedArgs a) {
     __syncthreads();   // S zeroed before the apply writes it
     // the apply table [M][M][N] as a buffer: every load takes one per-residue VGPR offset
     const __amdgpu_buffer_rsrc_t trs =
-        __builtin_amdgcn_make_buffer_rsrc((void*)a.tab, (short)0, M * M * N * 8, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.tab, (short)0, M * M * N * 8, kRawBufferWord3);
     // ---------------- 2. apply, residue pairs -> S
     for (int it = tid; it < a.n_items; it += NT) {
       const int i = it <= a.Ch ? it : a.C + 1 + (it - a.Ch - 1);
@@ -540,7 +546,7 @@ void k_mci1d_fused(FusedArgs a) {
     // b - P; its multiplier comes from a per-b table that is zero where neither position is
     // in the band.  Both are in the band only on [P - K, K], where the second term is added.
     const __amdgpu_buffer_rsrc_t urs =
-        __builtin_amdgcn_make_buffer_rsrc((void*)a.Ub, (short)0, (Q / 2) * P * 8, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.Ub, (short)0, (Q / 2) * P * 8, kRawBufferWord3);
     float2 vin[Q / 2][EI];
     // in groups of GW elements: the second term's branch after each group bounds how many of
     // the table loads the compiler hoists (registers)
