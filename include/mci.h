@@ -25,6 +25,11 @@
  *  - Array pointers passed to mci_reconstruct_1d / mci_upsample_2d are DEVICE pointers
  *    owned by the caller; the library never frees them.  Descriptor pointers (channel
  *    tables) are HOST pointers, read during the call and copied.
+ *  - Device data pointers and workspaces given to mci_reconstruct_1d, mci_upsample_2d,
+ *    mci_reconstruct_batch, mci_evaluate_1d and mci_averaged_error must be 16-byte aligned
+ *    (the kernels use 8- and 16-byte vector accesses); otherwise the call returns
+ *    MCI_E_INVALID_ARG.  hipMalloc'd memory always is; a view at an odd element offset may
+ *    not be.
  *  - Argument errors are reported synchronously, before any work is queued.
  *  - A singular or ill-conditioned channel system is reported by mci_plan, never by a
  *    reconstruction call.

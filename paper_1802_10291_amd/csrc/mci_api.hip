@@ -586,6 +586,8 @@ mci_status mci_reconstruct_1d(mci_plan_t p, const void* g, void* y, int64_t batc
   if (batch < 0) return fail(MCI_E_INVALID_ARG, "batch < 0");
   if (batch == 0) return MCI_OK;
   if (!g || !y) return fail(MCI_E_INVALID_ARG, "NULL data pointer");
+  if (!aligned16(g) || !aligned16(y) || !aligned16(workspace))
+    return fail(MCI_E_INVALID_ARG, "data pointers and workspace must be 16-byte aligned");
   if (batch > ((int64_t)1 << 40) / std::max<int64_t>(p->mu, p->d.n_out * p->d.n_ops))
     return fail(MCI_E_INVALID_ARG, "batch too large");
   const size_t need = ws_1d(p, batch);
@@ -663,6 +665,8 @@ mci_status mci_upsample_2d(mci_plan_t p, const void* lr, void* hr, int64_t batch
   if (batch < 0) return fail(MCI_E_INVALID_ARG, "batch < 0");
   if (batch == 0) return MCI_OK;
   if (!lr || !hr) return fail(MCI_E_INVALID_ARG, "NULL data pointer");
+  if (!aligned16(lr) || !aligned16(hr) || !aligned16(workspace))
+    return fail(MCI_E_INVALID_ARG, "data pointers and workspace must be 16-byte aligned");
   if (batch > ((int64_t)1 << 40) / instance_out_elems(p)) return fail(MCI_E_INVALID_ARG, "batch too large");
   const size_t need = ws_2d(p, batch);
   if (!workspace || ws_bytes < need) return fail(MCI_E_INVALID_ARG, "workspace too small: need " + std::to_string(need));

@@ -276,6 +276,8 @@ mci_status mci_reconstruct_batch(mci_batch_t b, const void* in, void* out, void*
   if (!b) return fail(MCI_E_INVALID_ARG, "NULL batch");
   if (b->cls.empty()) return MCI_OK;
   if (!in || !out) return fail(MCI_E_INVALID_ARG, "NULL data pointer");
+  if (!aligned16(in) || !aligned16(out) || !aligned16(workspace))
+    return fail(MCI_E_INVALID_ARG, "data pointers and workspace must be 16-byte aligned");
   std::vector<size_t> lane_off;
   const size_t need = batch_layout(b, lane_off);
   if (need && (!workspace || ws_bytes < need))

@@ -225,6 +225,8 @@ mci_status mci_averaged_error(const mci_plan_t* plans, int32_t n_plans, const vo
     return MCI_OK;
   }
   if (!a || !eps || !workspace) return fail(MCI_E_INVALID_ARG, "NULL array");
+  if (!aligned16(a) || !aligned16(workspace) || ((uintptr_t)eps & 7) || ((uintptr_t)best & 3))
+    return fail(MCI_E_INVALID_ARG, "a and workspace must be 16-byte aligned");
   size_t need = 0;
   mci_status st = mci_averaged_error_workspace_size(n_plans, n_span, precision, &need);
   if (st != MCI_OK) return st;

@@ -364,6 +364,8 @@ mci_status mci_evaluate_1d(mci_offgrid_t p, const void* g, const double* t, int6
   if (batch < 0 || n_t < 0) return fail(MCI_E_INVALID_ARG, "batch and n_t must be >= 0");
   if (batch == 0 || n_t == 0) return MCI_OK;
   if (!g || !t || !y) return fail(MCI_E_INVALID_ARG, "NULL array");
+  if (!aligned16(g) || !aligned16(y) || !aligned16(workspace) || ((uintptr_t)t & 7))
+    return fail(MCI_E_INVALID_ARG, "g, y and workspace must be 16-byte aligned, t 8-byte aligned");
   const size_t gb = grid_bytes(p, batch), tb = table_bytes(p, n_t), need = gb + tb + plan_workspace(p->grid, batch);
   if (!workspace || ws_bytes < need) return fail(MCI_E_INVALID_ARG, "workspace too small");
   if (n_t > 0x7fffffffLL * NT) return fail(MCI_E_INVALID_ARG, "too many points");

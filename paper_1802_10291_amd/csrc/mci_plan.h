@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <complex>
+#include <cstdint>
 #include <string>
 #include <vector>
 
@@ -48,6 +49,9 @@ struct mci_plan_s {
 namespace mci {
 
 mci_status fail(mci_status s, const std::string& msg);
+// data buffers are accessed with 8- and 16-byte vector loads and stores: every entry point
+// requires 16-byte-aligned data pointers and workspaces
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 // bytes of one storage element, and per-instance input / output sizes in elements
 int store_bytes(int store);

@@ -180,6 +180,27 @@ def test_batch_zero_is_noop(torch_cuda):
     assert p.reconstruct(g).shape == (0, 1, 64)
 
 
+def test_misaligned_buffers_rejected(torch_cuda):
+    """Device buffers must be 16-byte aligned (the kernels use vector accesses): a contiguous
+    view that starts one element into its allocation is refused with an argument error, and
+    the same values at an aligned address reconstruct normally."""
+    from paper_1802_10291_amd import MCIError, Plan1D, Plan2D
+    torch = torch_cuda
+    p = Plan1D(N=1366, n_out=16384, channels=[("deriv", 0), ("deriv", 1), ("deriv", 2)])
+    raw = torch.randn(2 * 3 * 1366 + 1, device="cuda")
+    g_bad = raw[1:].view(2, 3, 1366)
+    assert g_bad.is_contiguous() and g_bad.data_ptr() % 16 != 0
+    with pytest.raises(MCIError, match="INVALID_ARG"):
+        p.reconstruct(g_bad)
+    y = p.reconstruct(g_bad.clone())
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(y).all())
+    q = Plan2D(64, 64, 2)
+    raw2 = torch.rand(64 * 64 + 1, device="cuda")
+    with pytest.raises(MCIError, match="INVALID_ARG"):
+        q.upsample(raw2[1:].view(1, 64, 64))
+
+
 # ----------------------------------------------------------------------- batched FP32 workload
 def test_batched_fp32_small_batch_full_parity(torch_cuda):
     """The batched FP32 workload's shape (M = 3 derivative channels, N = 1366, band
