@@ -117,7 +117,7 @@ template <> struct LineFFT<32> { static constexpr int E = 8; using type = RList<
 template <> struct LineFFT<48> { static constexpr int E = 12; using type = RList<12, 4>; };
 template <> struct LineFFT<64> { static constexpr int E = 16; using type = RList<16, 4>; };
 template <> struct LineFFT<96> { static constexpr int E = 12; using type = RList<12, 4, 2>; };
-template <> struct LineFFT<128> { static constexpr int E = 16; using type = RList<16, 8>; };
+template <> struct LineFFT<128> { static constexpr int E = 8; using type = RList<8, 8, 2>; };
 template <> struct LineFFT<192> { static constexpr int E = 12; using type = RList<12, 4, 4>; };
 template <> struct LineFFT<256> { static constexpr int E = 16; using type = RList<16, 16>; };
 template <> struct LineFFT<384> { static constexpr int E = 12; using type = RList<12, 4, 4, 2>; };
