@@ -115,13 +115,13 @@ __device__ __forceinline__ void gfft_passes(float2* __restrict__ buf, int l, flo
 template <int L> struct LineFFT;
 template <> struct LineFFT<32> { static constexpr int E = 8; using type = RList<8, 4>; };
 template <> struct LineFFT<48> { static constexpr int E = 12; using type = RList<12, 4>; };
-template <> struct LineFFT<64> { static constexpr int E = 16; using type = RList<16, 4>; };
+template <> struct LineFFT<64> { static constexpr int E = 8; using type = RList<8, 8>; };
 template <> struct LineFFT<96> { static constexpr int E = 12; using type = RList<12, 4, 2>; };
 template <> struct LineFFT<128> { static constexpr int E = 8; using type = RList<8, 8, 2>; };
 template <> struct LineFFT<192> { static constexpr int E = 12; using type = RList<12, 4, 4>; };
 template <> struct LineFFT<256> { static constexpr int E = 16; using type = RList<16, 16>; };
 template <> struct LineFFT<384> { static constexpr int E = 12; using type = RList<12, 4, 4, 2>; };
-template <> struct LineFFT<512> { static constexpr int E = 16; using type = RList<16, 8, 4>; };
+template <> struct LineFFT<512> { static constexpr int E = 8; using type = RList<8, 8, 8>; };
 
 template <int L, int S>
 __device__ __forceinline__ void gfft(float2* buf, int l, float2 (&v)[LineFFT<L>::E], const float2* tw) {
