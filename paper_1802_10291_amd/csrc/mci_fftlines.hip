@@ -27,7 +27,7 @@ using namespace lfft;
 
 constexpr int FL = 16;   // lines per workgroup
 
-template <int N> constexpr int threads() { return FL * (N / LineFFT<N>::E); }
+template <int N> constexpr int threads() { return FL * (N / LinesFFT<N>::E); }
 
 // Where transform t of a side (input or output) starts, in complex elements: with a table,
 // offs[2 (t / per) + side] / 2 + (t % per) tr (offs in real elements, even); else
@@ -84,7 +84,7 @@ __device__ __forceinline__ void store_out(const LinesArgs& a, int64_t q, float2 
 // u u_out + k e_out.
 template <int N, int S, bool IN_T, bool OUT_T>
 __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
-  constexpr int E = LineFFT<N>::E, G = N / E, NT = threads<N>();
+  constexpr int E = LinesFFT<N>::E, G = N / E, NT = threads<N>();
   constexpr int TS = N + 1;
   extern __shared__ float2 sml[];
   const int tid = threadIdx.x;
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
 #pragma unroll
   for (int c = 0; c < E; ++c) v[c] = sml[g * TS + l + G * c];
   // the tile and the scratch share LDS: the line FFT's first store waits on a barrier
-  gfft<N, S>(sml + g * padded(N), l, v, a.tw);
+  gfft<N, S, LinesFFT<N>>(sml + g * padded(N), l, v, a.tw);
   const int64_t t = t0 + g;
   const int64_t tr = t / a.U, u = t - tr * a.U;
   if (a.twL) {

@@ -123,9 +123,14 @@ template <> struct LineFFT<256> { static constexpr int E = 16; using type = RLis
 template <> struct LineFFT<384> { static constexpr int E = 12; using type = RList<12, 4, 4, 2>; };
 template <> struct LineFFT<512> { static constexpr int E = 8; using type = RList<8, 8, 8>; };
 
-template <int L, int S>
-__device__ __forceinline__ void gfft(float2* buf, int l, float2 (&v)[LineFFT<L>::E], const float2* tw) {
-  gfft_passes<L, L / LineFFT<L>::E, S, 1>(buf, l, v, tw, typename LineFFT<L>::type{});
+// The one- and two-pass transforms hold one transform per lane group (the 2-D passes hold the
+// inputs of several output transforms at once), so they take fewer elements per lane at 256.
+template <int L> struct LinesFFT : LineFFT<L> {};
+template <> struct LinesFFT<256> { static constexpr int E = 8; using type = RList<8, 8, 4>; };
+
+template <int L, int S, typename F = LineFFT<L>>
+__device__ __forceinline__ void gfft(float2* buf, int l, float2 (&v)[F::E], const float2* tw) {
+  gfft_passes<L, L / F::E, S, 1>(buf, l, v, tw, typename F::type{});
 }
 
 // COLS: lines are the columns of x [B][N][W] (blockIdx.x = block of 32 columns, blockIdx.y =
