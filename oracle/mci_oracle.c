@@ -506,6 +506,15 @@ int orc_num_threads(void) {
 /* images, zero padding.  Parameter vector: W1[32][9][3] b1[32] W2[32][9][32] b2[32]   */
 /* W3[32][9][32] b3[32] W4[3][9][32] b4[3], W[co][tap][ci], tap = 3 dy + dx, the tap   */
 /* reading input pixel (y + dy - 1, x + dx - 1).                                      */
+/*                                                                                    */
+/* With bf16 != 0 every operand that a BF16 implementation stores is rounded to BF16  */
+/* (8 significant bits, round to nearest, ties to even) where it is stored: the      */
+/* weights, the network input, each hidden activation after its ReLU, the loss       */
+/* gradient at the output and each back-propagated activation gradient after its     */
+/* ReLU mask.  The arithmetic stays FP64; biases, the residual sum and the loss do    */
+/* not round.  That makes the reference see the same rounded operands as such an      */
+/* implementation, so what remains between the two is accumulation order and         */
+/* precision.                                                                         */
 /* ------------------------------------------------------------------------------ */
 enum { CNN_NPARAM = 32 * 27 + 32 + 2 * (32 * 288 + 32) + 3 * 288 + 3 };
 
@@ -545,24 +554,60 @@ static void relu_inplace(double *a, size_t n) {
   for (size_t i = 0; i < n; ++i) a[i] = a[i] > 0.0 ? a[i] : 0.0;
 }
 
-/* y = u + CNN(u) for `batch` images [3][H][W]; optionally the three hidden activations of
- * the last image ([32][H][W] each, after ReLU) */
-int orc_cnn_forward(const double *p, int64_t batch, int H, int W, const double *u, double *y) {
+/* x rounded to the nearest BF16 value (8 significant bits, exponent range of FP32,
+ * subnormal spacing 2^-133), ties to even.  x = m 2^e with 0.5 <= |m| < 1, so the
+ * spacing of BF16 values around x is 2^(e - 8); rint rounds ties to even. */
+static double bf16_round(double x) {
+  if (x == 0.0 || !isfinite(x)) return x;
+  int e;
+  (void)frexp(x, &e);
+  const int q = e - 8 < -133 ? -133 : e - 8;
+  return ldexp(rint(ldexp(x, -q)), q);
+}
+
+double orc_bf16_round(double x) { return bf16_round(x); }
+
+static void bf16_inplace(double *a, size_t n) {
+  for (size_t i = 0; i < n; ++i) a[i] = bf16_round(a[i]);
+}
+
+/* the parameter vector with its four weight tensors rounded to BF16 (biases kept) */
+static double *cnn_params_bf16(const double *p, const int64_t off[8]) {
+  double *q = (double *)malloc(sizeof(double) * CNN_NPARAM);
+  if (!q) return NULL;
+  memcpy(q, p, sizeof(double) * CNN_NPARAM);
+  bf16_inplace(q + off[0], (size_t)(off[1] - off[0]));
+  bf16_inplace(q + off[2], (size_t)(off[3] - off[2]));
+  bf16_inplace(q + off[4], (size_t)(off[5] - off[4]));
+  bf16_inplace(q + off[6], (size_t)(off[7] - off[6]));
+  return q;
+}
+
+/* y = u + CNN(u) for `batch` images [3][H][W]; bf16 != 0 rounds the stored operands
+ * (see above) */
+int orc_cnn_forward(const double *p0, int64_t batch, int H, int W, const double *u, double *y, int bf16) {
   int64_t off[8];
   cnn_offsets(off);
   const size_t hw = (size_t)H * W;
+  double *pq = bf16 ? cnn_params_bf16(p0, off) : NULL;
+  const double *p = bf16 ? pq : p0;
   double *a1 = (double *)malloc(sizeof(double) * 32 * hw), *a2 = (double *)malloc(sizeof(double) * 32 * hw);
-  double *r = (double *)malloc(sizeof(double) * 3 * hw);
-  if (!a1 || !a2 || !r) { free(a1); free(a2); free(r); return ORC_E_NOMEM; }
+  double *r = (double *)malloc(sizeof(double) * 3 * hw), *x = (double *)malloc(sizeof(double) * 3 * hw);
+  if (!a1 || !a2 || !r || !x || (bf16 && !pq)) { free(a1); free(a2); free(r); free(x); free(pq); return ORC_E_NOMEM; }
   for (int64_t b = 0; b < batch; ++b) {
     const double *ub = u + (size_t)b * 3 * hw;
-    conv3x3(3, 32, H, W, p + off[0], p + off[1], ub, a1); relu_inplace(a1, 32 * hw);
+    memcpy(x, ub, sizeof(double) * 3 * hw);
+    if (bf16) bf16_inplace(x, 3 * hw);
+    conv3x3(3, 32, H, W, p + off[0], p + off[1], x, a1); relu_inplace(a1, 32 * hw);
+    if (bf16) bf16_inplace(a1, 32 * hw);
     conv3x3(32, 32, H, W, p + off[2], p + off[3], a1, a2); relu_inplace(a2, 32 * hw);
+    if (bf16) bf16_inplace(a2, 32 * hw);
     conv3x3(32, 32, H, W, p + off[4], p + off[5], a2, a1); relu_inplace(a1, 32 * hw);
+    if (bf16) bf16_inplace(a1, 32 * hw);
     conv3x3(32, 3, H, W, p + off[6], p + off[7], a1, r);
     for (size_t i = 0; i < 3 * hw; ++i) y[(size_t)b * 3 * hw + i] = ub[i] + r[i];
   }
-  free(a1); free(a2); free(r);
+  free(a1); free(a2); free(r); free(x); free(pq);
   return ORC_OK;
 }
 
@@ -615,13 +660,17 @@ static void conv3x3_backward(int cin, int cout, int H, int W, const double *w, c
 }
 
 /* loss = mean over all batch*3*H*W values of (u + CNN(u) - hr)^2, and its gradient with
- * respect to the parameter vector */
-int orc_cnn_grad(const double *p, int64_t batch, int H, int W, const double *u, const double *hr, double *grad,
-                 double *loss) {
+ * respect to the parameter vector; bf16 != 0 rounds the stored operands (see above) */
+int orc_cnn_grad(const double *p0, int64_t batch, int H, int W, const double *u, const double *hr, double *grad,
+                 double *loss, int bf16) {
   int64_t off[8];
   cnn_offsets(off);
   const size_t hw = (size_t)H * W;
   const double count = (double)batch * 3.0 * (double)hw;
+  double *pq = bf16 ? cnn_params_bf16(p0, off) : NULL;
+  double *x = (double *)malloc(sizeof(double) * 3 * hw);
+  if ((bf16 && !pq) || !x) { free(pq); free(x); return ORC_E_NOMEM; }
+  const double *p = bf16 ? pq : p0;
   double *z1 = malloc(sizeof(double) * 32 * hw), *a1 = malloc(sizeof(double) * 32 * hw);
   double *z2 = malloc(sizeof(double) * 32 * hw), *a2 = malloc(sizeof(double) * 32 * hw);
   double *z3 = malloc(sizeof(double) * 32 * hw), *a3 = malloc(sizeof(double) * 32 * hw);
@@ -629,34 +678,45 @@ int orc_cnn_grad(const double *p, int64_t batch, int H, int W, const double *u, 
   double *ga = malloc(sizeof(double) * 32 * hw), *gb = malloc(sizeof(double) * 32 * hw);
   if (!z1 || !a1 || !z2 || !a2 || !z3 || !a3 || !r || !g4 || !ga || !gb) {
     free(z1); free(a1); free(z2); free(a2); free(z3); free(a3); free(r); free(g4); free(ga); free(gb);
+    free(pq); free(x);
     return ORC_E_NOMEM;
   }
   for (int i = 0; i < CNN_NPARAM; ++i) grad[i] = 0.0;
   double se = 0.0;
   for (int64_t b = 0; b < batch; ++b) {
     const double *ub = u + (size_t)b * 3 * hw, *hb = hr + (size_t)b * 3 * hw;
-    conv3x3(3, 32, H, W, p + off[0], p + off[1], ub, z1);
+    memcpy(x, ub, sizeof(double) * 3 * hw);
+    if (bf16) bf16_inplace(x, 3 * hw);
+    conv3x3(3, 32, H, W, p + off[0], p + off[1], x, z1);
     for (size_t i = 0; i < 32 * hw; ++i) a1[i] = z1[i] > 0 ? z1[i] : 0.0;
+    if (bf16) bf16_inplace(a1, 32 * hw);
     conv3x3(32, 32, H, W, p + off[2], p + off[3], a1, z2);
     for (size_t i = 0; i < 32 * hw; ++i) a2[i] = z2[i] > 0 ? z2[i] : 0.0;
+    if (bf16) bf16_inplace(a2, 32 * hw);
     conv3x3(32, 32, H, W, p + off[4], p + off[5], a2, z3);
     for (size_t i = 0; i < 32 * hw; ++i) a3[i] = z3[i] > 0 ? z3[i] : 0.0;
+    if (bf16) bf16_inplace(a3, 32 * hw);
     conv3x3(32, 3, H, W, p + off[6], p + off[7], a3, r);
     for (size_t i = 0; i < 3 * hw; ++i) {
       const double d = ub[i] + r[i] - hb[i];
       se += d * d;
       g4[i] = 2.0 * d / count;
     }
+    if (bf16) bf16_inplace(g4, 3 * hw);
     conv3x3_backward(32, 3, H, W, p + off[6], a3, g4, grad + off[6], grad + off[7], ga);
     for (size_t i = 0; i < 32 * hw; ++i) ga[i] = z3[i] > 0 ? ga[i] : 0.0;
+    if (bf16) bf16_inplace(ga, 32 * hw);
     conv3x3_backward(32, 32, H, W, p + off[4], a2, ga, grad + off[4], grad + off[5], gb);
     for (size_t i = 0; i < 32 * hw; ++i) gb[i] = z2[i] > 0 ? gb[i] : 0.0;
+    if (bf16) bf16_inplace(gb, 32 * hw);
     conv3x3_backward(32, 32, H, W, p + off[2], a1, gb, grad + off[2], grad + off[3], ga);
     for (size_t i = 0; i < 32 * hw; ++i) ga[i] = z1[i] > 0 ? ga[i] : 0.0;
-    conv3x3_backward(3, 32, H, W, p + off[0], ub, ga, grad + off[0], grad + off[1], NULL);
+    if (bf16) bf16_inplace(ga, 32 * hw);
+    conv3x3_backward(3, 32, H, W, p + off[0], x, ga, grad + off[0], grad + off[1], NULL);
   }
   *loss = se / count;
   free(z1); free(a1); free(z2); free(a2); free(z3); free(a3); free(r); free(g4); free(ga); free(gb);
+  free(pq); free(x);
   return ORC_OK;
 }
 

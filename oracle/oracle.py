@@ -324,32 +324,73 @@ def _cnn_lib():
     if not hasattr(lib, "_cnn_ready"):
         P = ctypes.POINTER
         pd = P(ctypes.c_double)
-        lib.orc_cnn_forward.argtypes = [pd, ctypes.c_int64, ctypes.c_int, ctypes.c_int, pd, pd]
-        lib.orc_cnn_grad.argtypes = [pd, ctypes.c_int64, ctypes.c_int, ctypes.c_int, pd, pd, pd, pd]
+        lib.orc_cnn_forward.argtypes = [pd, ctypes.c_int64, ctypes.c_int, ctypes.c_int, pd, pd, ctypes.c_int]
+        lib.orc_cnn_grad.argtypes = [pd, ctypes.c_int64, ctypes.c_int, ctypes.c_int, pd, pd, pd, pd, ctypes.c_int]
         lib.orc_cnn_forward.restype = ctypes.c_int
         lib.orc_cnn_grad.restype = ctypes.c_int
+        lib.orc_bf16_round.argtypes = [ctypes.c_double]
+        lib.orc_bf16_round.restype = ctypes.c_double
         lib._cnn_ready = True
     return lib
 
 
-def cnn_forward(params: np.ndarray, u: np.ndarray) -> np.ndarray:
-    """y = u + CNN(u) for images u [B][3][H][W] (FP64, zero padding)."""
+def bf16_round(x: float) -> float:
+    """x rounded to the nearest BF16 value, ties to even (the rounding of ``bf16=True``)."""
+    return float(_cnn_lib().orc_bf16_round(float(x)))
+
+
+def cnn_forward(params: np.ndarray, u: np.ndarray, bf16: bool = False) -> np.ndarray:
+    """y = u + CNN(u) for images u [B][3][H][W] (FP64, zero padding).  With ``bf16`` the
+    weights, the network input and the hidden activations are rounded to BF16 where a BF16
+    implementation stores them; the arithmetic stays FP64."""
     p = np.ascontiguousarray(params, dtype=np.float64)
     assert p.size == CNN_NPARAM
     u = np.ascontiguousarray(u, dtype=np.float64)
     B, c, H, W = u.shape
     y = np.empty_like(u)
-    _check(_cnn_lib().orc_cnn_forward(_pd(p), B, H, W, _pd(u), _pd(y)))
+    _check(_cnn_lib().orc_cnn_forward(_pd(p), B, H, W, _pd(u), _pd(y), int(bool(bf16))))
     return y
 
 
-def cnn_grad(params: np.ndarray, u: np.ndarray, hr: np.ndarray):
-    """(loss, grad): loss = mean((u + CNN(u) - hr)^2), grad = dloss/dparams (FP64)."""
+def cnn_grad(params: np.ndarray, u: np.ndarray, hr: np.ndarray, bf16: bool = False):
+    """(loss, grad): loss = mean((u + CNN(u) - hr)^2), grad = dloss/dparams (FP64).  With
+    ``bf16`` the stored operands of the forward pass and the back-propagated gradients (the
+    output gradient and each activation gradient after its ReLU mask) are rounded to BF16."""
     p = np.ascontiguousarray(params, dtype=np.float64)
     u = np.ascontiguousarray(u, dtype=np.float64)
     hr = np.ascontiguousarray(hr, dtype=np.float64)
     B, c, H, W = u.shape
     g = np.zeros(CNN_NPARAM)
     loss = ctypes.c_double(0.0)
-    _check(_cnn_lib().orc_cnn_grad(_pd(p), B, H, W, _pd(u), _pd(hr), _pd(g), ctypes.byref(loss)))
+    _check(_cnn_lib().orc_cnn_grad(_pd(p), B, H, W, _pd(u), _pd(hr), _pd(g), ctypes.byref(loss), int(bool(bf16))))
     return loss.value, g
+
+
+def omega(ch: Channels) -> np.ndarray:
+    """Omega_m(L) = sup over the band of |r_m|^2 (the definition after Theorem 4.4); by
+    eq. defrm r_m takes the values q_mk(n) of the inverse tables, k over the blocks and n
+    over I_1, so Omega_m is the largest |q_mk(n)|^2.  Returns Omega_1..Omega_M."""
+    q, sing = inverse_tables(ch)
+    if sing.any():
+        raise OracleError(2)
+    return (np.abs(q) ** 2).max(axis=(0, 2))
+
+
+def error_bound(ch: Channels, coeff_n: np.ndarray, coeff_a: np.ndarray) -> float:
+    """The bound of eq. errorestimate on epsilon(f, N) (its square root):
+
+      eps^2 <= sum_{n not in band} |a(n)|^2
+             + M (sum_k Omega_k) sum_{n not in band} sum_m |a(n) b_m(n)|^2 .
+
+    Cauchy-Schwarz on each |sum_m r_m b_m|^2 of eq. averageerror gives the factor
+    sum_m sup |r_m|^2 = sum_m Omega_m once per l = 1..M.  The printed bound squares Omega_k,
+    which the definition already makes a square; read literally that is no bound where
+    Omega_k < 1 (derivative channels), so Omega_k enters once here."""
+    om = omega(ch)
+    n = np.asarray(coeff_n, dtype=np.int64)
+    a2 = np.abs(np.asarray(coeff_a)) ** 2
+    outside = ~((n >= ch.n1) & (n < ch.n1 + ch.mu))
+    b2 = sum(np.abs(ch.multiplier(m, n)) ** 2 for m in range(ch.M))
+    s1 = float(a2[outside].sum())
+    s2 = float((a2[outside] * b2[outside]).sum())
+    return float(np.sqrt(s1 + ch.M * float(om.sum()) * s2))

@@ -34,6 +34,29 @@ def test_phi_series_matches_closed_form():
     assert np.abs(ser - _phi(np.exp(1j * t))).max() < 1e-13
 
 
+@pytest.mark.parametrize("N,n1", [(12, -17), (13, 5), (1, 0), (7, -3)])
+@pytest.mark.parametrize("real", [True, False])
+def test_channel_dft_equals_numpy_fft(N, n1, real):
+    """Lemma 3.1's d_m(n) = (1/N) sum_p g_m[p] e^{-2 pi i n p / N} for n = n1 + i: NumPy's FFT
+    divided by N, read at n mod N, for every (signal, channel) of a batch; and a single
+    exponential e^{i k t_p} has d(n) = 1 exactly where n = k mod N."""
+    rng = np.random.default_rng(N + 100 * real)
+    B, M = 3, 4
+    g = rng.standard_normal((B, M, N))
+    if not real:
+        g = g + 1j * rng.standard_normal((B, M, N))
+    d = O.channel_dft(g, N, n1)
+    idx = np.mod(n1 + np.arange(N), N)
+    want = np.fft.fft(g, axis=-1)[..., idx] / N
+    assert d.shape == (B, M, N)
+    assert np.abs(d - want).max() <= 1e-13
+    k = 5
+    e = np.exp(1j * k * 2 * np.pi * np.arange(N) / N)[None, None]
+    d1 = O.channel_dft(e, N, n1)[0, 0]
+    hit = np.mod(n1 + np.arange(N) - k, N) == 0
+    assert np.abs(d1[hit] - 1).max() <= 1e-13 and np.abs(d1[~hit]).max(initial=0.0) <= 1e-13
+
+
 def _load_table1():
     rows = []
     with open(os.path.join(GOLDEN, "table1.txt")) as fh:
@@ -428,6 +451,51 @@ def test_theorem_4_4_averaged_error(setup):
     assert eps_avg == pytest.approx(eps_formula, rel=1e-10)
     # and it vanishes for a bandlimited signal
     assert O.averaged_error(ch, n[inband], a[inband]) == 0.0
+
+
+def test_omega_closed_forms():
+    """Omega_m(L) = sup |r_m|^2 from the closed-form inverses: Example 3.6 ({f, f', f''}) and
+    the two-derivative set, whose entries are read off H_n^{-1} over n in I_1; Example
+    3.10's {f, Hf} has Omega = (1, 1) (entries 1/2 and, at n = 0, 1 and |-i| = 1)."""
+    L = 9
+    ch = O.Channels(N=L, kinds=[O.MULT_DERIV] * 3, orders=[0, 1, 2])
+    n = ch.n1 + np.arange(L)
+    rows = [np.stack([(2 * L**2 + 3 * L * n + n**2) / (2 * L**2), -n * (2 * L + n) / L**2, n * (L + n) / (2 * L**2)]),
+            np.stack([(3 * L + 2 * n) / (2 * L**2), -2 * (L + n) / L**2, (L + 2 * n) / (2 * L**2)]),
+            np.stack([np.full(L, -1 / (2 * L**2)), np.full(L, 1 / L**2), np.full(L, -1 / (2 * L**2))])]
+    want = np.array([(np.abs(r) ** 2).max() for r in rows])
+    assert np.allclose(O.omega(ch), want, rtol=1e-13, atol=0)
+    N = 20
+    ch2 = O.Channels(N=N, kinds=[O.MULT_DERIV] * 2, orders=[0, 1])
+    n2 = ch2.n1 + np.arange(N)
+    want2 = [max((((n2 + N) / N) ** 2).max(), ((n2 / N) ** 2).max()), 1 / N**2]
+    assert np.allclose(O.omega(ch2), want2, rtol=1e-13, atol=0)
+    ch3 = O.Channels(N=7, kinds=[O.MULT_DERIV, O.MULT_HILBERT], orders=[0, 0])
+    assert np.allclose(O.omega(ch3), [1.0, 1.0], rtol=1e-14)
+
+
+@pytest.mark.parametrize("setup", ["deriv2", "deriv3", "hilbert2", "plain"])
+def test_theorem_4_4_error_bound(setup):
+    """eq. errorestimate bounds eq. averageerror for random non-bandlimited spectra; both
+    vanish for a bandlimited signal; with one plain channel (b = 1, r = 1, Omega = 1) the
+    bound is attained: both equal 2 sum_{n outside the band} |a(n)|^2."""
+    N = 10
+    kinds, orders = {"deriv2": ([O.MULT_DERIV] * 2, [0, 1]), "deriv3": ([O.MULT_DERIV] * 3, [0, 1, 2]),
+                     "hilbert2": ([O.MULT_DERIV, O.MULT_HILBERT], [0, 0]), "plain": ([O.MULT_DERIV], [0])}[setup]
+    ch = O.Channels(N=N, kinds=kinds, orders=orders)
+    rng = np.random.default_rng(len(setup))
+    n = np.arange(ch.n1 - 4 * N, ch.n1 + ch.mu + 4 * N)
+    inband = (n >= ch.n1) & (n < ch.n1 + ch.mu)
+    for trial in range(20):
+        a = (rng.standard_normal(n.size) + 1j * rng.standard_normal(n.size)) * \
+            np.exp(-rng.uniform(0.01, 0.5) * np.abs(n))
+        eps, bound = O.averaged_error(ch, n, a), O.error_bound(ch, n, a)
+        assert bound >= eps * (1 - 1e-12), (trial, eps, bound)
+        if setup == "plain":
+            out2 = np.sum(np.abs(a[~inband]) ** 2)
+            assert eps == pytest.approx(np.sqrt(2 * out2), rel=1e-12)
+            assert bound == pytest.approx(np.sqrt(2 * out2), rel=1e-12)
+    assert O.error_bound(ch, n[inband], a[inband]) == 0.0 and O.averaged_error(ch, n[inband], a[inband]) == 0.0
 
 
 # ---------------------------------------------------------------- singular systems (Remark 3.4)
