@@ -320,8 +320,8 @@ mci_status mci_evaluate_1d(mci_offgrid_t plan, const void* g, const double* t, i
 /* ----------------------------------------------------------------------------------- */
 #define MCI_MAX_ERROR_PLANS 16
 
-/* Device bytes of the weight table: (n_plans rounded up to a power of two) x n_span
- * values of the given precision. */
+/* Device bytes of the workspace: the weight table, (n_plans rounded up to a power of two)
+ * x n_span values of the given precision, plus 256 bytes for per-plan constants. */
 mci_status mci_averaged_error_workspace_size(int32_t n_plans, int64_t n_span, int32_t precision, size_t* bytes);
 
 /* mci_averaged_error -- eps[s][c] = epsilon(f_s, plan c) for n_sig signals and n_plans plans.
@@ -339,6 +339,24 @@ mci_status mci_averaged_error_workspace_size(int32_t n_plans, int64_t n_span, in
 mci_status mci_averaged_error(const mci_plan_t* plans, int32_t n_plans, const void* a, int64_t n_lo, int64_t n_span,
                               int64_t n_sig, int32_t precision, double* eps, int32_t* best, void* workspace,
                               size_t ws_bytes, hipStream_t stream);
+
+/* mci_error_bound -- the bound of eq. errorestimate (Theorem 4.4 and the definition of
+ * Omega_m after it) on eps, for the same arguments:
+ *   bound[s][c]^2 = sum_{n outside the band} |a(n)|^2 (1 + M (sum_k Omega_k) sum_m |b_m(n)|^2),
+ *   Omega_k = sup over the band of |r_k|^2 = max over residues and blocks of |q_{k,l}(n)|^2.
+ * Cauchy-Schwarz on eq. averageerror gives this form, with Omega_k entering once; the
+ * printed bound squares Omega_k, which its definition already makes a square, and read
+ * literally that is no bound when Omega_k < 1.  bound: device [n_sig][n_plans] double.
+ * Same plan restrictions, layout of a, workspace and errors as mci_averaged_error.
+ * Asynchronous on stream; no allocation. */
+mci_status mci_error_bound(const mci_plan_t* plans, int32_t n_plans, const void* a, int64_t n_lo, int64_t n_span,
+                           int64_t n_sig, int32_t precision, double* bound, void* workspace, size_t ws_bytes,
+                           hipStream_t stream);
+
+/* mci_plan_omega -- Omega_1..Omega_M of a 1-D plan (the definition after Theorem 4.4),
+ * computed on the host from the plan's FP64 inverse entries (synchronous).  omega: host
+ * array of len >= M doubles.  MCI_E_SINGULAR for a plan with singular residues. */
+mci_status mci_plan_omega(mci_plan_t plan, double* omega, int32_t len);
 
 /* ----------------------------------------------------------------------------------- */
 /* Learned residual refiner (not part of the paper; its closing remarks on Section 5.2   */

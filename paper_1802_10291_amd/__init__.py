@@ -40,6 +40,26 @@ def _stream_handle(device) -> int:
     return int(torch.cuda.current_stream(device).cuda_stream)
 
 
+class _Workspaces:
+    """Caller-side workspaces of one library object, one buffer per stream.  Calls queued on
+    different streams never share scratch memory, and each buffer is allocated (or replaced
+    when it must grow) while its own stream is current, so PyTorch's caching allocator hands
+    it out again only in that stream's order, after the kernels queued on it."""
+
+    def __init__(self, device: int):
+        self.device = device
+        self.bufs = {}
+
+    def get(self, need: int):
+        torch = _torch()
+        key = _stream_handle(self.device)
+        buf = self.bufs.get(key)
+        if buf is None or buf.numel() < need:
+            buf = torch.empty(max(int(need), 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+            self.bufs[key] = buf
+        return buf
+
+
 class _Variants:
     """Kernel variants and the autotuner (``mci_plan_variants`` / ``mci_plan_set_variant`` /
     ``mci_plan_autotune``), shared by 1-D and 2-D plans."""
@@ -111,11 +131,15 @@ class Plan1D(_Variants):
         self.M, self.N, self.n_out, self.n_ops, self.real = d.M, int(N), int(n_out), d.n_ops, real
         self.precision, self.storage, self.device = precision, storage, device
         self.handle = mci_plan(d, device)
-        self._ws = None
+        self._ws = _Workspaces(device)
 
     @property
     def info(self):
         return mci_plan_info(self.handle)
+
+    def omega(self):
+        """Omega_1..Omega_M of the error bound (``mci_plan_omega``, after Theorem 4.4)."""
+        return _lib.mci_plan_omega(self.handle, self.M)
 
     def instance_sizes(self) -> Tuple[int, int]:
         c = 1 if self.real else 2
@@ -128,11 +152,9 @@ class Plan1D(_Variants):
         return torch.float64 if self.precision == "f64" else torch.float32
 
     def workspace(self, batch: int):
-        torch = _torch()
+        """(buffer, bytes) of the workspace for the current stream (None when none is needed)."""
         need = mci_workspace_size(self.handle, batch)
-        if need and (self._ws is None or self._ws.numel() < need):
-            self._ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
-        return self._ws if need else None, need
+        return (self._ws.get(need) if need else None), need
 
     def reconstruct(self, g, out=None):
         """g: cuda tensor [batch, M, N] (real) or [batch, M, N, 2] (complex, re/im).
@@ -181,7 +203,7 @@ class OffGrid:
         self.precision, self.device = precision, device
         self.handle = _lib.mci_offgrid_plan(d, width, device)
         self.grid_len, self.width, self.beta, grid_plan = _lib.mci_offgrid_info(self.handle)
-        self._ws = None
+        self._ws = _Workspaces(device)
 
     def io_dtype(self):
         torch = _torch()
@@ -208,10 +230,9 @@ class OffGrid:
         elif tuple(out.shape) != shape or out.dtype != self.io_dtype() or not out.is_contiguous():
             raise ValueError("bad out tensor")
         need = _lib.mci_offgrid_workspace_size(self.handle, batch, n_t)
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = torch.empty(max(need, 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+        ws = self._ws.get(need)
         _lib.mci_evaluate_1d(self.handle, g.data_ptr(), t.data_ptr(), n_t, t.dim() == 1, out.data_ptr(), batch,
-                             self._ws.data_ptr(), need, _stream_handle(g.device))
+                             ws.data_ptr(), need, _stream_handle(g.device))
         return out
 
     def close(self):
@@ -244,6 +265,22 @@ def averaged_error(plans: Sequence["Plan1D"], a, n_lo: int):
     return eps, best
 
 
+def error_bound(plans: Sequence["Plan1D"], a, n_lo: int):
+    """The bound of eq. errorestimate on the averaged error of every signal under every plan
+    (``mci_error_bound``); a as for :func:`averaged_error`.  Returns float64 [n_sig, n_plans]."""
+    torch = _torch()
+    if not a.is_cuda or a.dim() != 2 or not a.is_contiguous() or a.dtype not in (torch.complex64, torch.complex128):
+        raise ValueError("a must be a contiguous complex64/complex128 cuda tensor [n_sig, n_span]")
+    prec = _lib.MCI_F64 if a.dtype == torch.complex128 else _lib.MCI_F32
+    n_sig, n_span = a.shape
+    bound = torch.empty((n_sig, len(plans)), dtype=torch.float64, device=a.device)
+    need = _lib.mci_averaged_error_workspace_size(len(plans), n_span, prec)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=a.device)
+    _lib.mci_error_bound([p.handle for p in plans], a.data_ptr(), int(n_lo), n_span, n_sig, prec, bound.data_ptr(),
+                         ws.data_ptr(), need, _stream_handle(a.device))
+    return bound
+
+
 class Plan2D(_Variants):
     """A 2-D separable upsampling plan (``mci_plan_2d``): lr [batch, h, w] -> hr [batch, s h, s w],
     with channels {x, Dx} (channels=2) or {x, Dx, D2x} (channels=3) per line."""
@@ -259,7 +296,7 @@ class Plan2D(_Variants):
         self.h, self.w, self.scale = int(h), int(w), int(scale)
         self.precision, self.storage, self.device = precision, storage, device
         self.handle = mci_plan_2d(d, device)
-        self._ws = None
+        self._ws = _Workspaces(device)
 
     @property
     def info(self):
@@ -275,11 +312,9 @@ class Plan2D(_Variants):
         return torch.float64 if self.precision == "f64" else torch.float32
 
     def workspace(self, batch: int):
-        torch = _torch()
+        """(buffer, bytes) of the workspace for the current stream (None when none is needed)."""
         need = mci_workspace_size(self.handle, batch)
-        if need and (self._ws is None or self._ws.numel() < need):
-            self._ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
-        return self._ws if need else None, need
+        return (self._ws.get(need) if need else None), need
 
     def upsample(self, lr, out=None):
         torch = _torch()
@@ -334,17 +369,15 @@ class Batch:
                                         zip(self.plans, self.in_offsets, self.out_offsets)], lanes)
         self.in_elems, self.out_elems, self.ws_bytes = mci_batch_sizes(self.handle)
         self.device = self.plans[0].device if self.plans else 0
-        self._ws = None
+        self._ws = _Workspaces(self.device)
 
     def dtype(self):
         return self.plans[0].io_dtype()
 
     def workspace(self):
-        torch = _torch()
+        """(buffer, bytes) of the workspace for the current stream (None when none is needed)."""
         _, _, need = mci_batch_sizes(self.handle)
-        if need and (self._ws is None or self._ws.numel() < need):
-            self._ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
-        return self._ws if need else None, need
+        return (self._ws.get(need) if need else None), need
 
     def run(self, packed_in, packed_out=None):
         """packed_in: flat device tensor of >= in_elems elements; returns the packed output."""
@@ -383,16 +416,13 @@ class Refiner:
         _lib.rcheck(lib.mci_refiner_create(device, seed, ctypes.byref(h)), "mci_refiner_create")
         self.handle, self.device = h.value, device
         self.n_params = int(lib.mci_refiner_num_params())
-        self._ws = None
+        self._ws = _Workspaces(device)
         self._lp = None
 
     def _workspace(self, B, H, W):
-        torch = _torch()
         n = ctypes.c_size_t()
         _lib.rcheck(_lib.load_refiner().mci_refiner_workspace_size(B, H, W, ctypes.byref(n)), "workspace_size")
-        if self._ws is None or self._ws.numel() < n.value:
-            self._ws = torch.empty(n.value, dtype=torch.uint8, device=f"cuda:{self.device}")
-        return self._ws, n.value
+        return self._ws.get(n.value), n.value
 
     @staticmethod
     def _check_img(t):

@@ -73,7 +73,7 @@ EXPORTS = ["mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_workspace_size"
            "mci_plan_set_variant", "mci_plan_autotune", "mci_batch_create", "mci_batch_destroy", "mci_batch_sizes",
            "mci_reconstruct_batch", "mci_offgrid_plan", "mci_offgrid_destroy", "mci_offgrid_info",
            "mci_offgrid_workspace_size", "mci_evaluate_1d", "mci_averaged_error_workspace_size",
-           "mci_averaged_error"]
+           "mci_averaged_error", "mci_error_bound", "mci_plan_omega"]
 
 _lib = None
 
@@ -124,8 +124,11 @@ def load(path: str = LIB_PATH):
     lib.mci_evaluate_1d.argtypes = [vp, vp, vp, i64, i32, vp, i64, vp, sz, vp]
     lib.mci_averaged_error_workspace_size.argtypes = [i32, i64, i32, P(sz)]
     lib.mci_averaged_error.argtypes = [P(vp), i32, vp, i64, i64, i64, i32, vp, vp, vp, sz, vp]
+    lib.mci_error_bound.argtypes = [P(vp), i32, vp, i64, i64, i64, i32, vp, vp, sz, vp]
+    lib.mci_plan_omega.argtypes = [vp, P(ctypes.c_double), i32]
     for name in ("mci_offgrid_plan", "mci_offgrid_destroy", "mci_offgrid_info", "mci_offgrid_workspace_size",
-                 "mci_evaluate_1d", "mci_averaged_error_workspace_size", "mci_averaged_error"):
+                 "mci_evaluate_1d", "mci_averaged_error_workspace_size", "mci_averaged_error", "mci_error_bound",
+                 "mci_plan_omega"):
         getattr(lib, name).restype = i32
     for name in ("mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_workspace_size", "mci_reconstruct_1d",
                  "mci_plan_2d", "mci_upsample_2d", "mci_plan_variants", "mci_plan_set_variant", "mci_plan_autotune",
@@ -263,6 +266,19 @@ def mci_averaged_error(plans, a_ptr: int, n_lo: int, n_span: int, n_sig: int, pr
     arr = (ctypes.c_void_p * max(1, len(plans)))(*plans)
     check(load().mci_averaged_error(arr, len(plans), a_ptr, n_lo, n_span, n_sig, precision, eps_ptr, best_ptr,
                                     ws_ptr, ws_bytes, stream), "mci_averaged_error")
+
+
+def mci_error_bound(plans, a_ptr: int, n_lo: int, n_span: int, n_sig: int, precision: int, bound_ptr: int,
+                    ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    arr = (ctypes.c_void_p * max(1, len(plans)))(*plans)
+    check(load().mci_error_bound(arr, len(plans), a_ptr, n_lo, n_span, n_sig, precision, bound_ptr, ws_ptr,
+                                 ws_bytes, stream), "mci_error_bound")
+
+
+def mci_plan_omega(plan, M: int):
+    out = (ctypes.c_double * max(1, M))()
+    check(load().mci_plan_omega(plan, out, M), "mci_plan_omega")
+    return list(out)[:M]
 
 
 # ----------------------------------------------------------------------------- refiner

@@ -12,12 +12,21 @@
 // sum.  The pass reads each coefficient once (8 bytes in FP32) for about 2 C + 3 flops, far
 // below the ratio where arithmetic would bound it, so it is written for HBM bandwidth:
 // coalesced row loads, several signals per workgroup sharing each weight load.
+//
+// The bound of eq. errorestimate has the same form with another weight: Cauchy-Schwarz on
+// each |sum_m r_m b_m|^2 gives
+//   eps^2 <= sum_{n outside the band} |a(n)|^2 (1 + M (sum_k Omega_k) sum_m |b_m(n)|^2),
+// Omega_k = sup over the band of |r_k|^2 = the largest |q_{k,l}(n)|^2 over residues and
+// blocks (the definition after Theorem 4.4 with eq. defrm).  A small kernel reduces each
+// plan's sum_k Omega_k from the inverse table; the weight and reduction kernels then run as
+// for the error itself.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "mci_plan.h"
 
@@ -34,15 +43,50 @@ struct PlanRef {
   int kinds[MCI_MAX_CHANNELS], orders[MCI_MAX_CHANNELS];
 };
 
+enum { Q_AVERAGED = 0, Q_BOUND = 1 };
+
 struct ErrArgs {
   PlanRef plans[MAX_PLANS];
   int n_plans, cp;      // plans, and the padded count the weight table holds
+  int quantity;         // Q_AVERAGED: eq. averageerror; Q_BOUND: eq. errorestimate
   int64_t n_lo, n_span, n_sig;
   const void* a;        // [n_sig][n_span] complex
   void* w;              // [cp][n_span] weights
+  double* omsum;        // [MAX_PLANS] sum_k Omega_k per plan (Q_BOUND)
   double* eps;          // [n_sig][n_plans]
   int* best;            // [n_sig] or null
 };
+
+// sum_k Omega_k of plan blockIdx.x: per channel k the largest |q_{k,l}(n)|^2 over the
+// residues n and blocks l, then the sum over k
+__global__ __launch_bounds__(NT) void k_omega(ErrArgs a) {
+  const PlanRef& p = a.plans[blockIdx.x];
+  double mx[MCI_MAX_CHANNELS];
+  for (int m = 0; m < MCI_MAX_CHANNELS; ++m) mx[m] = 0.0;
+  const int64_t cnt = p.N * p.M * p.M;
+  for (int64_t e = threadIdx.x; e < cnt; e += NT) {
+    const int m = (int)((e / p.M) % p.M);   // [N][M][M]: row m, column l
+    const double2 q = p.q[e];
+    mx[m] = fmax(mx[m], q.x * q.x + q.y * q.y);
+  }
+  __shared__ double red[NT / 64][MCI_MAX_CHANNELS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int m = 0; m < p.M; ++m) {
+    double v = mx[m];
+    for (int d = 32; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d));
+    if (lane == 0) red[wave][m] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int m = 0; m < p.M; ++m) {
+      double v = red[0][m];
+      for (int k = 1; k < NT / 64; ++k) v = fmax(v, red[k][m]);
+      sum += v;
+    }
+    a.omsum[blockIdx.x] = sum;
+  }
+}
 
 __device__ inline double2 mult_b(int kind, int order, int64_t n) {
   if (kind == MCI_MULT_HILBERT) return make_double2(0.0, n > 0 ? -1.0 : (n < 0 ? 1.0 : 0.0));
@@ -77,6 +121,12 @@ __global__ __launch_bounds__(NT) void k_weights(ErrArgs a) {
   const int64_t res = ((off % p.N) + p.N) % p.N;
   double2 b[MCI_MAX_CHANNELS];
   for (int m = 0; m < p.M; ++m) b[m] = mult_b(p.kinds[m], p.orders[m], n);
+  if (a.quantity == Q_BOUND) {
+    double b2 = 0.0;
+    for (int m = 0; m < p.M; ++m) b2 += b[m].x * b[m].x + b[m].y * b[m].y;
+    w[i] = (T)(1.0 + p.M * a.omsum[c] * b2);
+    return;
+  }
   double acc = 1.0;
   for (int l = 0; l < p.M; ++l) {
     double sx = 0.0, sy = 0.0;
@@ -157,6 +207,7 @@ __global__ __launch_bounds__(NT) void k_reduce(ErrArgs a) {
 
 template <typename T>
 static hipError_t launch(const ErrArgs& a, hipStream_t s) {
+  if (a.quantity == Q_BOUND) hipLaunchKernelGGL(k_omega, dim3((unsigned)a.n_plans), dim3(NT), 0, s, a);
   hipLaunchKernelGGL(k_weights<T>, dim3((unsigned)((a.n_span + NT - 1) / NT), (unsigned)a.cp), dim3(NT), 0, s, a);
   const int64_t sb = a.cp <= 4 ? 8 : 4;
   const dim3 grid((unsigned)((a.n_sig + sb - 1) / sb));
@@ -187,13 +238,14 @@ extern "C" {
 mci_status mci_averaged_error_workspace_size(int32_t n_plans, int64_t n_span, int32_t precision, size_t* bytes) {
   if (!bytes || n_plans < 1 || n_plans > MAX_PLANS || n_span < 0) return fail(MCI_E_INVALID_ARG, "n_plans, n_span or bytes");
   if (precision != MCI_F32 && precision != MCI_F64) return fail(MCI_E_INVALID_ARG, "precision");
-  *bytes = (((size_t)padded(n_plans) * n_span * (precision == MCI_F64 ? 8 : 4)) + 255) & ~(size_t)255;
+  // the weight table, then 256 bytes for the per-plan Omega sums of the bound
+  *bytes = ((((size_t)padded(n_plans) * n_span * (precision == MCI_F64 ? 8 : 4)) + 255) & ~(size_t)255) + 256;
   return MCI_OK;
 }
 
-mci_status mci_averaged_error(const mci_plan_t* plans, int32_t n_plans, const void* a, int64_t n_lo, int64_t n_span,
-                              int64_t n_sig, int32_t precision, double* eps, int32_t* best, void* workspace,
-                              size_t ws_bytes, hipStream_t stream) {
+static mci_status error_call(int quantity, const mci_plan_t* plans, int32_t n_plans, const void* a, int64_t n_lo,
+                             int64_t n_span, int64_t n_sig, int32_t precision, double* eps, int32_t* best,
+                             void* workspace, size_t ws_bytes, hipStream_t stream) {
   if (!plans || n_plans < 1 || n_plans > MAX_PLANS) return fail(MCI_E_INVALID_ARG, "plans / n_plans (1..16)");
   if (precision != MCI_F32 && precision != MCI_F64) return fail(MCI_E_INVALID_ARG, "precision");
   if (n_span < 0 || n_sig < 0) return fail(MCI_E_INVALID_ARG, "n_span and n_sig must be >= 0");
@@ -240,10 +292,45 @@ mci_status mci_averaged_error(const mci_plan_t* plans, int32_t n_plans, const vo
   ea.n_sig = n_sig;
   ea.a = a;
   ea.w = workspace;
+  ea.omsum = (double*)((char*)workspace + need - 256);
+  ea.quantity = quantity;
   ea.eps = eps;
   ea.best = best;
   const hipError_t e = precision == MCI_F64 ? launch<double>(ea, stream) : launch<float>(ea, stream);
   if (e != hipSuccess) return fail(MCI_E_DEVICE, std::string("averaged error: ") + hipGetErrorString(e));
+  return MCI_OK;
+}
+
+mci_status mci_averaged_error(const mci_plan_t* plans, int32_t n_plans, const void* a, int64_t n_lo, int64_t n_span,
+                              int64_t n_sig, int32_t precision, double* eps, int32_t* best, void* workspace,
+                              size_t ws_bytes, hipStream_t stream) {
+  return error_call(Q_AVERAGED, plans, n_plans, a, n_lo, n_span, n_sig, precision, eps, best, workspace, ws_bytes,
+                    stream);
+}
+
+mci_status mci_error_bound(const mci_plan_t* plans, int32_t n_plans, const void* a, int64_t n_lo, int64_t n_span,
+                           int64_t n_sig, int32_t precision, double* bound, void* workspace, size_t ws_bytes,
+                           hipStream_t stream) {
+  return error_call(Q_BOUND, plans, n_plans, a, n_lo, n_span, n_sig, precision, bound, nullptr, workspace, ws_bytes,
+                    stream);
+}
+
+mci_status mci_plan_omega(mci_plan_t plan, double* omega, int32_t len) {
+  if (!plan || !omega) return fail(MCI_E_INVALID_ARG, "NULL argument");
+  if (plan->dims != 1 || !plan->qdev) return fail(MCI_E_INVALID_ARG, "Omega is defined for 1-D plans");
+  const int M = plan->d.M;
+  if (len < M) return fail(MCI_E_INVALID_ARG, "omega needs M entries");
+  if (plan->n_sing) return fail(MCI_E_SINGULAR, "a plan with singular residues has no inverse everywhere");
+  const int64_t cnt = plan->d.N * M * M;
+  std::vector<double2> q((size_t)cnt);
+  if (hipSetDevice(plan->device) != hipSuccess ||
+      hipMemcpy(q.data(), plan->qdev, (size_t)cnt * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(MCI_E_DEVICE, "inverse table readback");
+  for (int m = 0; m < M; ++m) omega[m] = 0.0;
+  for (int64_t e = 0; e < cnt; ++e) {
+    const int m = (int)((e / M) % M);
+    omega[m] = std::max(omega[m], q[e].x * q[e].x + q[e].y * q[e].y);
+  }
   return MCI_OK;
 }
 

@@ -1,4 +1,5 @@
-"""Averaged approximation error on the GPU (``mci_averaged_error``) against the FP64 oracle.
+"""Averaged approximation error on the GPU (``mci_averaged_error``) and its bound
+(``mci_error_bound``, eq. errorestimate) against the FP64 oracle.
 
 The oracle's ``averaged_error`` evaluates eq. averageerror term by term and is pinned in the
 CPU suite against Theorem 4.4 itself (the phase average of actual reconstruction errors).
@@ -145,3 +146,63 @@ def test_averaged_error_full_size_sampled(torch_cuda):
         want = np.array([O.averaged_error(ch, n, ref) for _, ch in plans])
         assert np.all(np.abs(eps[s] - want) <= 1e-5 * want), (s, eps[s], want)
     assert np.isfinite(eps).all()
+
+
+# ------------------------------------------------------------------ the bound (eq. errorestimate)
+def test_plan_omega_matches_oracle(torch_cuda):
+    """Omega_m of every candidate plan (the definition after Theorem 4.4) from the GPU's FP64
+    inverse tables equals the oracle's, whose closed forms are pinned in the CPU suite."""
+    for plan, ch in _plans(CANDIDATES, "f64"):
+        got = np.array(plan.omega())
+        want = O.omega(ch)
+        assert np.allclose(got, want, rtol=1e-12, atol=0), (got, want)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_error_bound_matches_oracle(torch_cuda, precision, tol):
+    """The bound of eq. errorestimate per (signal, plan) against the oracle's term-by-term
+    evaluation, 11 signals (a full and a ragged workgroup) x 5 plans; it bounds the averaged
+    error computed by the same call's sibling, and is 0 for a bandlimited signal."""
+    from paper_1802_10291_amd import averaged_error, error_bound
+    torch = torch_cuda
+    plans = _plans(CANDIDATES)
+    n_lo, n_span, n_sig = -150, 301, 11
+    n, a = _spectra(n_sig, n_lo, n_span, seed=6)
+    cdt = np.complex128 if precision == "f64" else np.complex64
+    a_dev = torch.from_numpy(a.astype(cdt)).cuda()
+    bound = error_bound([p for p, _ in plans], a_dev, n_lo).cpu().numpy()
+    eps, _ = averaged_error([p for p, _ in plans], a_dev, n_lo)
+    eps = eps.cpu().numpy()
+    a_ref = a.astype(cdt).astype(np.complex128)
+    want = np.array([[O.error_bound(ch, n, a_ref[s]) for _, ch in plans] for s in range(n_sig)])
+    assert np.all(np.abs(bound - want) <= tol * want), np.abs(bound / want - 1).max()
+    assert np.all(bound >= eps * (1 - 2 * tol))
+    inband = (n >= -23) & (n <= 24)
+    a0 = np.where(inband, a[1], 0)[None].astype(cdt)
+    b0 = error_bound([plans[1][0]], torch.from_numpy(a0).cuda(), n_lo).cpu().numpy()
+    assert b0[0, 0] == 0.0
+
+
+def test_error_bound_full_size_sampled(torch_cuda):
+    """The averaged-error benchmark's shape for the bound: 4096 signals x 16385 coefficients x
+    4 plans of about 4098 samples; 3 sampled signals against the oracle, all finite."""
+    from paper_1802_10291_amd import error_bound
+    from synth import signals as S
+    torch = torch_cuda
+    cands = [(4098, [("deriv", 0)], 0), (2049, [("deriv", 0), ("deriv", 1)], 0),
+             (1366, [("deriv", 0), ("deriv", 1), ("deriv", 2)], 0), (2049, [("deriv", 0), ("hilbert", 0)], 0)]
+    plans = _plans(cands)
+    n_max, n_sig, pool = 8192, 4096, 32
+    n_lo, n_span = -n_max, 2 * n_max + 1
+    rng = np.random.default_rng(78)
+    host = np.empty((pool, n_span), dtype=np.complex64)
+    for s in range(pool):
+        host[s] = S.smooth_noisy_spectrum(rng, n_max)[1]
+    a = torch.from_numpy(host).cuda().repeat(n_sig // pool, 1)
+    bound = error_bound([p for p, _ in plans], a, n_lo).cpu().numpy()
+    n = np.arange(n_lo, n_lo + n_span)
+    for s in (0, 1001, 4095):
+        ref = host[s % pool].astype(np.complex128)
+        want = np.array([O.error_bound(ch, n, ref) for _, ch in plans])
+        assert np.all(np.abs(bound[s] - want) <= 1e-5 * want), (s, bound[s], want)
+    assert np.isfinite(bound).all()

@@ -176,8 +176,12 @@ def test_averaged_error_arguments_rejected_without_device():
     assert lib.mci_averaged_error_workspace_size(17, 10, 0, ctypes.byref(n)) == 1    # above 16
     assert lib.mci_averaged_error_workspace_size(3, 10, 5, ctypes.byref(n)) == 1     # precision
     assert lib.mci_averaged_error_workspace_size(3, 10, 1, ctypes.byref(n)) == 0
-    assert n.value == 4 * 10 * 8 + (256 - (4 * 10 * 8) % 256)                        # 4 padded rows, FP64
+    assert n.value == 4 * 10 * 8 + (256 - (4 * 10 * 8) % 256) + 256                  # 4 padded rows, FP64, constants
     arr = (ctypes.c_void_p * 1)(None)
     assert lib.mci_averaged_error(arr, 1, None, 0, 10, 1, 0, None, None, None, 0, None) == 1   # NULL plan
     assert lib.mci_averaged_error(None, 1, None, 0, 10, 1, 0, None, None, None, 0, None) == 1
     assert lib.mci_averaged_error(arr, 0, None, 0, 10, 1, 0, None, None, None, 0, None) == 1
+    assert lib.mci_error_bound(arr, 1, None, 0, 10, 1, 0, None, None, 0, None) == 1      # NULL plan
+    assert lib.mci_error_bound(None, 1, None, 0, 10, 1, 0, None, None, 0, None) == 1
+    om = (ctypes.c_double * 4)()
+    assert lib.mci_plan_omega(None, om, 4) == 1
