@@ -340,6 +340,19 @@ mci_status mci_averaged_error(const mci_plan_t* plans, int32_t n_plans, const vo
                               int64_t n_sig, int32_t precision, double* eps, int32_t* best, void* workspace,
                               size_t ws_bytes, hipStream_t stream);
 
+/* mci_averaged_error_noalloc -- mci_averaged_error for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments and results, without the workspace.  The weight table lives in a
+ * static 4 MiB device array, one per GPU, whose address is looked up on the first call on
+ * each device.  The call allocates nothing; it fails with MCI_E_INVALID_ARG when
+ * mci_averaged_error_workspace_size(n_plans, n_span, precision) exceeds 4 MiB (for FP32,
+ * n_span up to 65532 with 16 plans).  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (different streams, or host threads) race and give wrong results;
+ * calls in one stream's order are safe.  Nothing in the array needs to start at zero. */
+mci_status mci_averaged_error_noalloc(const mci_plan_t* plans, int32_t n_plans, const void* a, int64_t n_lo,
+                                      int64_t n_span, int64_t n_sig, int32_t precision, double* eps, int32_t* best,
+                                      hipStream_t stream);
+
 /* mci_error_bound -- the bound of eq. errorestimate (Theorem 4.4 and the definition of
  * Omega_m after it) on eps, for the same arguments:
  *   bound[s][c]^2 = sum_{n outside the band} |a(n)|^2 (1 + M (sum_k Omega_k) sum_m |b_m(n)|^2),

@@ -73,7 +73,7 @@ EXPORTS = ["mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_workspace_size"
            "mci_plan_set_variant", "mci_plan_autotune", "mci_batch_create", "mci_batch_destroy", "mci_batch_sizes",
            "mci_reconstruct_batch", "mci_offgrid_plan", "mci_offgrid_destroy", "mci_offgrid_info",
            "mci_offgrid_workspace_size", "mci_evaluate_1d", "mci_averaged_error_workspace_size",
-           "mci_averaged_error", "mci_error_bound", "mci_plan_omega"]
+           "mci_averaged_error", "mci_error_bound", "mci_plan_omega", "mci_averaged_error_noalloc"]
 
 _lib = None
 
@@ -126,9 +126,10 @@ def load(path: str = LIB_PATH):
     lib.mci_averaged_error.argtypes = [P(vp), i32, vp, i64, i64, i64, i32, vp, vp, vp, sz, vp]
     lib.mci_error_bound.argtypes = [P(vp), i32, vp, i64, i64, i64, i32, vp, vp, sz, vp]
     lib.mci_plan_omega.argtypes = [vp, P(ctypes.c_double), i32]
+    lib.mci_averaged_error_noalloc.argtypes = [P(vp), i32, vp, i64, i64, i64, i32, vp, vp, vp]
     for name in ("mci_offgrid_plan", "mci_offgrid_destroy", "mci_offgrid_info", "mci_offgrid_workspace_size",
                  "mci_evaluate_1d", "mci_averaged_error_workspace_size", "mci_averaged_error", "mci_error_bound",
-                 "mci_plan_omega"):
+                 "mci_plan_omega", "mci_averaged_error_noalloc"):
         getattr(lib, name).restype = i32
     for name in ("mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_workspace_size", "mci_reconstruct_1d",
                  "mci_plan_2d", "mci_upsample_2d", "mci_plan_variants", "mci_plan_set_variant", "mci_plan_autotune",
@@ -273,6 +274,13 @@ def mci_error_bound(plans, a_ptr: int, n_lo: int, n_span: int, n_sig: int, preci
     arr = (ctypes.c_void_p * max(1, len(plans)))(*plans)
     check(load().mci_error_bound(arr, len(plans), a_ptr, n_lo, n_span, n_sig, precision, bound_ptr, ws_ptr,
                                  ws_bytes, stream), "mci_error_bound")
+
+
+def mci_averaged_error_noalloc(plans, a_ptr: int, n_lo: int, n_span: int, n_sig: int, precision: int, eps_ptr: int,
+                               best_ptr: int, stream: int) -> None:
+    arr = (ctypes.c_void_p * max(1, len(plans)))(*plans)
+    check(load().mci_averaged_error_noalloc(arr, len(plans), a_ptr, n_lo, n_span, n_sig, precision, eps_ptr,
+                                            best_ptr, stream), "mci_averaged_error_noalloc")
 
 
 def mci_plan_omega(plan, M: int):

@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -227,6 +228,31 @@ static int padded(int n) {
   return c;
 }
 
+// Workspace of mci_averaged_error_noalloc: a file-scope device array, one copy per GPU.  In
+// host code its name is only a stand-in; the device address comes from hipGetSymbolAddress
+// (once per device, with that device current) and only that address is passed on.
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 256;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static mci_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(MCI_E_INVALID_ARG, "device index");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    if (hipSetDevice(dev) != hipSuccess) return fail(MCI_E_DEVICE, "hipSetDevice");
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MCI_E_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MCI_OK;
+}
+
 }  // namespace err
 }  // namespace mci
 
@@ -305,6 +331,22 @@ mci_status mci_averaged_error(const mci_plan_t* plans, int32_t n_plans, const vo
                               int64_t n_sig, int32_t precision, double* eps, int32_t* best, void* workspace,
                               size_t ws_bytes, hipStream_t stream) {
   return error_call(Q_AVERAGED, plans, n_plans, a, n_lo, n_span, n_sig, precision, eps, best, workspace, ws_bytes,
+                    stream);
+}
+
+mci_status mci_averaged_error_noalloc(const mci_plan_t* plans, int32_t n_plans, const void* a, int64_t n_lo,
+                                      int64_t n_span, int64_t n_sig, int32_t precision, double* eps, int32_t* best,
+                                      hipStream_t stream) {
+  size_t need = 0;
+  mci_status st = mci_averaged_error_workspace_size(n_plans, n_span, precision, &need);
+  if (st != MCI_OK) return st;
+  if (need > kScratchBytes)
+    return fail(MCI_E_INVALID_ARG, "weight table of " + std::to_string(need) + " bytes exceeds the " +
+                                       std::to_string(kScratchBytes) + "-byte static workspace (use mci_averaged_error)");
+  if (!plans || !plans[0]) return fail(MCI_E_INVALID_ARG, "NULL plan");
+  void* ws = nullptr;
+  if ((st = scratch_address(plans[0]->device, &ws)) != MCI_OK) return st;
+  return error_call(Q_AVERAGED, plans, n_plans, a, n_lo, n_span, n_sig, precision, eps, best, ws, kScratchBytes,
                     stream);
 }
 
