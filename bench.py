@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--epochs", type=int, default=3, help="refiner: training epochs")
     ap.add_argument("--batch", type=int, default=0, help="override the batch size (0 = workload default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/mci1d_batched_fp32_traffic.json from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--no-2d", action="store_true",
                     help="batched1d: skip the 2-D x2 and x4 workloads that the default line also carries")
     ap.add_argument("--cpu-sample", type=int, default=0, help="signals/images in the CPU sample (0 = default)")
@@ -77,6 +79,45 @@ def source_hash(paths):
         with open(os.path.join(ROOT, p), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+FUSED_SOURCES = ["paper_1802_10291_amd/csrc/mci_fused.hip", "paper_1802_10291_amd/csrc/mci_device.h"]
+FUSED_KERNEL = "void mci::k_mci1d_fused<1024, 2, 4096, 4, 3, 1, float>(mci::FusedArgs)"
+
+
+def write_traffic(fetch_dir, write_dir, units=65536):
+    """HBM traffic of the batched workload's fused kernel from two rocprofv3 --pmc runs of this
+    script (FETCH_SIZE, then WRITE_SIZE; counter_collection.csv in each directory), each scaled
+    by what the counter reads for the 2 GiB device-to-device copy of copy_bandwidth() in the same
+    run; written to profiles/ with the hash of the kernel's source.  No GPU is used."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        fused, copy = [], []
+        for f in files:
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"]) * 1024.0          # KiB per dispatch
+                if "k_mci1d_fused" in r["Kernel_Name"]:
+                    fused.append(v)
+                elif "copyBuffer" in r["Kernel_Name"]:               # the runtime's device-to-device copy
+                    copy.append((int(r["Grid_Size"]), v))
+        big = max(g for g, _ in copy)                            # the 2 GiB copy has the largest grid
+        return float(np.mean(fused)), float(np.median([v for g, v in copy if g == big]))
+
+    nbytes = 2 << 30
+    f_fused, f_copy = per_kernel(fetch_dir, "FETCH_SIZE")
+    w_fused, w_copy = per_kernel(write_dir, "WRITE_SIZE")
+    fc, wc = nbytes / f_copy, nbytes / w_copy
+    doc = {"kernel": FUSED_KERNEL, "units_per_launch": units, "hbm_bytes_per_launch": f_fused * fc + w_fused * wc,
+           "read_bytes": f_fused * fc, "write_bytes": w_fused * wc, "fetch_calibration": fc, "write_calibration": wc,
+           "kernel_source_hash": source_hash(FUSED_SOURCES)}
+    with open(os.path.join(ROOT, "profiles", "mci1d_batched_fp32_traffic.json"), "w") as fh:
+        json.dump(doc, fh, indent=1)
+    print(json.dumps(doc))
 
 
 def load_traffic(name, khash, per_launch_units):
@@ -177,7 +218,7 @@ def bench_batched1d(args, torch):
     value = samples * args.steps / (sum(per) * 1e-3)
     alg_bytes = B * (M * N * 4 + n_out * 4)
     achieved = alg_bytes / (ms * 1e-3) / 1e9
-    kernel_src = ["paper_1802_10291_amd/csrc/mci_fused.hip", "paper_1802_10291_amd/csrc/mci_device.h"] if info.path \
+    kernel_src = FUSED_SOURCES if info.path \
         else ["paper_1802_10291_amd/csrc/mci_kernels.hip", "paper_1802_10291_amd/csrc/mci_device.h"]
     khash = source_hash(kernel_src)
     traffic = load_traffic("mci1d_batched_fp32", khash, B) if info.path else None
@@ -655,12 +696,15 @@ def bench_refiner(args, torch):
     from paper_1802_10291_amd import refiner_train as RT
 
     r = Refiner(seed=0)
-    hist, tau = RT.train(r, n_pairs=args.pairs, batch=16, size=128, lr=1e-3, epochs=args.epochs, log=log)
-    p_mci, p_ref, frac = RT.evaluate(r, n_images=16, size=512)
-    log(f"held-out PSNR: MCI {p_mci:.3f} dB, MCI + CNN {p_ref:.3f} dB, refined {frac:.2f}")
+    t_train = time.perf_counter()
+    hist, tau = RT.train(r, n_pairs=args.pairs, batch=16, size=512, lr=1e-3, epochs=args.epochs, log=log)
+    t_train = time.perf_counter() - t_train
+    n_eval = 512
+    p_mci, p_ref, frac = RT.evaluate(r, n_images=n_eval, size=512)
+    log(f"held-out PSNR over {n_eval} images: MCI {p_mci:.3f} dB, MCI + CNN {p_ref:.3f} dB, refined {frac:.2f}")
     B = args.batch or 64
-    hr = RT.make_hr(0, min(B, 16), 512, 7_000_000)
-    hr_dev = torch.from_numpy(hr).cuda().repeat((B + hr.shape[0] - 1) // hr.shape[0], 1, 1, 1)[:B].contiguous()
+    hr_dev = RT.gpu_rgb_images([7_000_000 + i for i in range(min(B, 16))], 512)
+    hr_dev = hr_dev.repeat((B + hr_dev.shape[0] - 1) // hr_dev.shape[0], 1, 1, 1)[:B].contiguous()
     lr_img = hr_dev[:, :, ::2, ::2].contiguous()
     plan = Plan2D(256, 256, 2)
     u = torch.empty_like(hr_dev)
@@ -682,18 +726,25 @@ def bench_refiner(args, torch):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16", "data": "synthetic",
         "config": {"workload": f"MCI x2 (256^2 -> 512^2, RGB) + residual CNN refiner (4 conv3x3, 32 ch, BF16 MFMA), "
-                               f"trained on {args.pairs} method-generated 128^2 pairs x {args.epochs} epochs",
+                               f"trained on {args.pairs} method-generated 512^2 RGB pairs x {args.epochs} epochs, "
+                               f"PSNR on {n_eval} held-out 512^2 images",
                    "batch": B},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": achieved / 2500.0, "traffic": None, "kernel": "refiner forward (4 conv layers)"},
         "images_per_s": {"mci": B / (ms_mci * 1e-3), "mci_plus_cnn": B / (ms * 1e-3)},
-        "psnr_db": {"mci": p_mci, "mci_plus_cnn": p_ref, "gain": p_ref - p_mci, "images": 16, "refined_fraction": frac},
+        "psnr_db": {"mci": p_mci, "mci_plus_cnn": p_ref, "gain": p_ref - p_mci, "images": n_eval,
+                    "refined_fraction": frac},
+        "training": {"pairs": args.pairs, "size": 512, "epochs": args.epochs, "steps": args.epochs * (args.pairs // 16),
+                     "seconds": t_train},
         "fallback_tau": tau, "train_loss": hist[-1][1] if hist else None, "wall_s": wall,
     }
 
 
 def main():
     args = parse()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (every signal and image is independent, "
               "so a batch would shard by contiguous ranges with no collective). Run with --gpus 1.", file=sys.stderr)

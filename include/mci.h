@@ -141,6 +141,11 @@ mci_status mci_plan_destroy(mci_plan_t plan);
 /* mci_plan_info -- describe a plan. */
 mci_status mci_plan_info(mci_plan_t plan, mci_plan_info_t* info);
 
+/* mci_plan_kernel_name -- a description of the kernels the plan's active variant runs
+ * (e.g. "k_mci1d_fused: forward split-Bluestein 1024-point, output 2 x 4096-point, M=3"),
+ * NUL-terminated and truncated to len bytes.  For the autotuner's record and for profiles. */
+mci_status mci_plan_kernel_name(mci_plan_t plan, char* name, size_t len);
+
 /* mci_workspace_size -- device bytes of scratch a reconstruction of `batch` signals needs
  * (0 for plans that run fused).  The caller allocates it, so reconstruction calls never
  * allocate. */
@@ -252,9 +257,14 @@ typedef struct mci_batch_s* mci_batch_t;
  * device, share one element type (FP32, FP16 or FP64 storage) and outlive the batch.
  * Offsets are >= 0 and multiples of 4 elements (vector access); output extents must not
  * overlap.  Each instance's layout inside its extent is the single-instance layout of
- * mci_reconstruct_1d / mci_upsample_2d.  Allocates (the tables, the lane streams and
- * events): build batches at set-up.  Errors: MCI_E_INVALID_ARG, MCI_E_OUT_OF_MEMORY,
- * MCI_E_DEVICE. */
+ * mci_reconstruct_1d / mci_upsample_2d.  With MCI_BATCH_MERGED=1 in the environment at
+ * creation, the classes whose plans run the single-pass 1-D kernel, the real-mode
+ * line-transform path or the 2-D line passes are recorded as jobs instead: per lane and
+ * step of their launch sequences, one persistent launch per kernel template walks a device
+ * table of the jobs' arguments (opt-in: slower than the classes' own launches on the mixed
+ * workload).  The batch fixes each plan's variant at creation.  Allocates (the tables, the
+ * lane streams and events): build batches at set-up.  Errors: MCI_E_INVALID_ARG,
+ * MCI_E_OUT_OF_MEMORY, MCI_E_DEVICE. */
 mci_status mci_batch_create(const mci_batch_item* items, int64_t n_items, int lanes, mci_batch_t* out);
 mci_status mci_batch_destroy(mci_batch_t batch);
 
@@ -393,6 +403,15 @@ mci_status mci_refiner_get_params(mci_refiner_t r, float* host_params, float* ta
 mci_status mci_refiner_set_params(mci_refiner_t r, const float* host_params, float tau);
 /* Gradient of the last backward / train step, FP32 host copy in the parameter layout. */
 mci_status mci_refiner_get_grads(mci_refiner_t r, float* host_grads);
+/* Training checkpoints: the FP32 parameters, both Adam moments, the Adam step count and the
+ * fallback bound, as one host byte buffer of mci_refiner_state_size() bytes (header
+ * "MCIRFN01", n_params, step, tau, then parameters, first and second moments).  Loading it
+ * into any refiner makes the next train steps continue bit for bit where the saved one
+ * stopped (the training data order is the caller's).  Synchronous.  Errors:
+ * MCI_E_INVALID_ARG (NULL, short buffer, not a checkpoint of this network), MCI_E_DEVICE. */
+size_t mci_refiner_state_size(void);
+mci_status mci_refiner_save_state(mci_refiner_t r, void* host, size_t len);
+mci_status mci_refiner_load_state(mci_refiner_t r, const void* host, size_t len);
 /* Device scratch for a batch of `batch` images of h x w (activations, gradients, partials). */
 mci_status mci_refiner_workspace_size(int64_t batch, int h, int w, size_t* bytes);
 /* y = u + CNN(u).  With ratio != NULL, ratio[b] = ||y_b - u_b|| / ||u_b|| (device, [batch]);

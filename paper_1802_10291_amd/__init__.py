@@ -85,6 +85,10 @@ class _Variants:
         """Elements of one instance's input and output."""
         raise NotImplementedError
 
+    def kernel_name(self) -> str:
+        """The kernels of the active variant (``mci_plan_kernel_name``)."""
+        return _lib.mci_plan_kernel_name(self.handle)
+
 
 def _desc_1d(N, n_out, channels, ops, n1, real, precision, storage, allow_singular_zero, cond_max):
     """An mci_plan_desc, and the host channel tables it points to (kept alive by the caller)."""
@@ -442,6 +446,21 @@ class Refiner:
             raise ValueError("wrong parameter count")
         _lib.rcheck(_lib.load_refiner().mci_refiner_set_params(self.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                                                float(tau)), "set_params")
+
+    def save_state(self) -> bytes:
+        """Checkpoint of the training state (``mci_refiner_save_state``): parameters, Adam
+        moments and step count, fallback bound."""
+        lib = _lib.load_refiner()
+        n = int(lib.mci_refiner_state_size())
+        buf = ctypes.create_string_buffer(n)
+        _lib.rcheck(lib.mci_refiner_save_state(self.handle, buf, n), "mci_refiner_save_state")
+        return buf.raw
+
+    def load_state(self, state: bytes) -> None:
+        """Restore a checkpoint written by :meth:`save_state` (``mci_refiner_load_state``)."""
+        lib = _lib.load_refiner()
+        buf = ctypes.create_string_buffer(bytes(state), len(state))
+        _lib.rcheck(lib.mci_refiner_load_state(self.handle, buf, len(state)), "mci_refiner_load_state")
 
     def get_grads(self):
         g = np.empty(self.n_params, dtype=np.float32)

@@ -68,7 +68,7 @@ class mci_batch_item(ctypes.Structure):
 
 
 # every symbol the header declares
-EXPORTS = ["mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_workspace_size", "mci_reconstruct_1d",
+EXPORTS = ["mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_plan_kernel_name", "mci_workspace_size", "mci_reconstruct_1d",
            "mci_plan_2d", "mci_upsample_2d", "mci_status_string", "mci_last_error", "mci_plan_variants",
            "mci_plan_set_variant", "mci_plan_autotune", "mci_batch_create", "mci_batch_destroy", "mci_batch_sizes",
            "mci_reconstruct_batch", "mci_offgrid_plan", "mci_offgrid_destroy", "mci_offgrid_info",
@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
     lib.mci_plan.argtypes = [P(mci_plan_desc), i32, P(vp)]
     lib.mci_plan_destroy.argtypes = [vp]
     lib.mci_plan_info.argtypes = [vp, P(mci_plan_info_t)]
+    lib.mci_plan_kernel_name.argtypes = [vp, ctypes.c_char_p, sz]
+    lib.mci_plan_kernel_name.restype = i32
     lib.mci_workspace_size.argtypes = [vp, i64, P(sz)]
     lib.mci_reconstruct_1d.argtypes = [vp, vp, vp, i64, vp, sz, vp]
     lib.mci_plan_2d.argtypes = [P(mci_plan2d_desc), i32, P(vp)]
@@ -160,6 +162,12 @@ def mci_plan_info(plan: int) -> mci_plan_info_t:
     info = mci_plan_info_t()
     check(load().mci_plan_info(plan, ctypes.byref(info)), "mci_plan_info")
     return info
+
+
+def mci_plan_kernel_name(plan: int) -> str:
+    buf = ctypes.create_string_buffer(256)
+    check(load().mci_plan_kernel_name(plan, buf, 256), "mci_plan_kernel_name")
+    return buf.value.decode()
 
 
 def mci_workspace_size(plan: int, batch: int) -> int:
@@ -292,7 +300,8 @@ def mci_plan_omega(plan, M: int):
 # ----------------------------------------------------------------------------- refiner
 REFINER_EXPORTS = ["mci_refiner_create", "mci_refiner_destroy", "mci_refiner_num_params", "mci_refiner_get_params",
                    "mci_refiner_set_params", "mci_refiner_get_grads", "mci_refiner_workspace_size",
-                   "mci_refiner_forward", "mci_refiner_backward", "mci_refiner_train_step", "mci_refiner_last_error"]
+                   "mci_refiner_forward", "mci_refiner_backward", "mci_refiner_train_step", "mci_refiner_last_error",
+                   "mci_refiner_state_size", "mci_refiner_save_state", "mci_refiner_load_state"]
 EXPORTS += REFINER_EXPORTS
 
 
@@ -315,9 +324,13 @@ def load_refiner():
     lib.mci_refiner_train_step.argtypes = [vp, vp, vp, i64, i32, i32, f32, vp, P(i32), vp, sz, vp]
     lib.mci_refiner_last_error.argtypes = []
     lib.mci_refiner_last_error.restype = ctypes.c_char_p
+    lib.mci_refiner_state_size.argtypes = []
+    lib.mci_refiner_state_size.restype = sz
+    lib.mci_refiner_save_state.argtypes = [vp, vp, sz]
+    lib.mci_refiner_load_state.argtypes = [vp, vp, sz]
     for n in ("mci_refiner_create", "mci_refiner_destroy", "mci_refiner_get_params", "mci_refiner_set_params",
               "mci_refiner_get_grads", "mci_refiner_workspace_size", "mci_refiner_forward", "mci_refiner_backward",
-              "mci_refiner_train_step"):
+              "mci_refiner_train_step", "mci_refiner_save_state", "mci_refiner_load_state"):
         getattr(lib, n).restype = i32
     lib._refiner_ready = True
     return lib

@@ -31,6 +31,7 @@
 #include "mci_2d.h"
 #include "mci_device.h"
 #include "mci_host_util.h"
+#include "mci_jobs.h"
 #include "mci_linefft.h"
 
 namespace mci {
@@ -52,7 +53,7 @@ template <int N> constexpr int line_threads() { return PAIRS * (N / LineFFT<N>::
 template <int N, int SC> constexpr int out_parts() { return SC * N > 1024 ? 4 : 2; }
 
 template <int N, int SC, bool COLS, typename TI, typename TO>
-__global__ __launch_bounds__(line_threads<N>()) void k_line_pass(LinePassArgs a) {
+__device__ __forceinline__ void line_pass_body(const LinePassArgs& a, int64_t bx, int by) {
   constexpr int E = LineFFT<N>::E, G = N / E, NT = line_threads<N>();
   extern __shared__ float2 sm2[];
   float* tile = (float*)sm2;                   // input [32][N + 1] floats
@@ -66,10 +67,10 @@ __global__ __launch_bounds__(line_threads<N>()) void k_line_pass(LinePassArgs a)
   int64_t line0;
   int64_t img = 0, col0 = 0;
   if constexpr (COLS) {
-    col0 = (int64_t)blockIdx.x * LINES;
-    img = blockIdx.y;
+    col0 = bx * LINES;
+    img = by;
   } else {
-    line0 = (int64_t)blockIdx.x * LINES;
+    line0 = bx * LINES;
   }
   // ---- load 32 lines into the tile (line-major)
   const int64_t xoff = COLS ? (a.offs ? a.offs[2 * img] : img * N * (int64_t)a.W) : 0;
@@ -211,6 +212,33 @@ __global__ __launch_bounds__(line_threads<N>()) void k_line_pass(LinePassArgs a)
   }
 }
 
+template <int N, int SC, bool COLS, typename TI, typename TO>
+__global__ __launch_bounds__(line_threads<N>()) void k_line_pass(LinePassArgs a) {
+  line_pass_body<N, SC, COLS, TI, TO>(a, blockIdx.x, blockIdx.y);
+}
+
+// merged form: one persistent launch over the jobs of an uneven batch
+template <int N, int SC, bool COLS, typename TI, typename TO>
+__global__ __launch_bounds__(line_threads<N>()) void k_line_pass_jobs(const LinePassArgs* jobs, const JobGrid* grids,
+                                                                      const int64_t* first, int n_jobs, int64_t total,
+                                                                      JobBases b) {
+  run_jobs(jobs, grids, first, n_jobs, total, [&](const LinePassArgs& j, int64_t bx, int by, int) {
+    LinePassArgs a = j;
+    a.x = rebase(a.x, b);
+    a.y = rebase(a.y, b);
+    line_pass_body<N, SC, COLS, TI, TO>(a, bx, by);
+  });
+}
+
+template <int N, int SC, bool COLS, typename TI, typename TO>
+static hipError_t launch_jobs(const MergedLaunch& m, const JobBases& b, hipStream_t s) {
+  return merged_launch<LinePassArgs>((const void*)k_line_pass_jobs<N, SC, COLS, TI, TO>, line_threads<N>(), m, b, s);
+}
+template <int N, int SC, bool COLS, typename TI, typename TO>
+static int occupancy_jobs(size_t lds) {
+  return occupancy_of((const void*)k_line_pass_jobs<N, SC, COLS, TI, TO>, line_threads<N>(), lds);
+}
+
 template <int N, int SC, bool COLS>
 static size_t lds_bytes() {
   const size_t tile = (size_t)LINES * (N + 1) * sizeof(float);
@@ -225,6 +253,10 @@ static hipError_t launch(const LinePassArgs& a, int64_t images, hipStream_t s) {
   if constexpr (COLS) grid = dim3((unsigned)((a.W + LINES - 1) / LINES), (unsigned)images);
   else grid = dim3((unsigned)((a.lines + LINES - 1) / LINES));
   const size_t lds = lds_bytes<N, SC, COLS>();
+  if (job_recorder()) {
+    record_job(launch_jobs<N, SC, COLS, TI, TO>, occupancy_jobs<N, SC, COLS, TI, TO>, a, grid.x, (int)grid.y, lds);
+    return hipSuccess;
+  }
   const dim3 block(line_threads<N>());
   hipLaunchKernelGGL((k_line_pass<N, SC, COLS, TI, TO>), grid, block, lds, s, a);
   return hipGetLastError();
@@ -235,8 +267,11 @@ template <int N, int SC, bool COLS, typename TI, typename TO>
 static hipError_t prepare(const LinePassArgs&, int64_t, hipStream_t) {
   const size_t lds = lds_bytes<N, SC, COLS>();
   if (lds <= 64 * 1024) return hipSuccess;
-  return hipFuncSetAttribute((const void*)k_line_pass<N, SC, COLS, TI, TO>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
+  hipError_t e = hipFuncSetAttribute((const void*)k_line_pass<N, SC, COLS, TI, TO>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_line_pass_jobs<N, SC, COLS, TI, TO>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <bool COLS, typename TI, typename TO>

@@ -4,6 +4,8 @@
 
 #include <cstdint>
 
+#include "mci_bandgen.h"
+
 namespace mci {
 
 // a line length of the register-staged line FFT: 32, 48, 64, 96, 128, 192, 256, 384, 512
@@ -42,6 +44,9 @@ struct LineXform {
   // FP16 storage of the input (the first pass reads it) or of the output (the last pass
   // writes it); offsets and strides stay in elements of the stored type
   bool in_half = false, out_half = false;
+  // optional: the input is not read but computed, position p of transform t being
+  // band_bin(*gen, t, p) (the real-mode apply); in, pre and the input layout are then unused
+  const BandGen* gen = nullptr;
 };
 hipError_t fft_lines(const LineXform& x, hipStream_t s);
 

@@ -17,6 +17,7 @@
 #include <cmath>
 
 #include "mci_fftlines.h"
+#include "mci_jobs.h"
 #include "mci_linefft.h"
 
 namespace mci {
@@ -58,6 +59,7 @@ struct LinesArgs {
   const float2* post;       // output position k multiplied by post[k], or null
   int real_in;              // input holds real values: position p reads (in[p], 0)
   int in_half, out_half;    // input / output stored as FP16 (half2 pairs, or halves for real input)
+  BandGen gen;              // GEN kernels: input position p of transform t is band_bin(gen, t, p)
 };
 
 // input position p of the transform whose first element is element `base` of the input
@@ -82,17 +84,24 @@ __device__ __forceinline__ void store_out(const LinesArgs& a, int64_t q, float2 
 // e); they then share one transform and U is a multiple of 16.  Otherwise lines are rows
 // (element stride 1).  Positions inside a transform: input u u_in + n e_in, output
 // u u_out + k e_out.
-template <int N, int S, bool IN_T, bool OUT_T>
-__global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
+template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
+__device__ __forceinline__ void lines_body(const LinesArgs& a, int64_t bx) {
   constexpr int E = LinesFFT<N>::E, G = N / E, NT = threads<N>();
   constexpr int TS = N + 1;
   extern __shared__ float2 sml[];
   const int tid = threadIdx.x;
   const int g = tid / G, l = tid % G;
-  const int64_t t0 = (int64_t)blockIdx.x * FL;
+  const int64_t t0 = bx * FL;
   // plain complex input (no chirp, no real or FP16 storage): a bare load per element
   const bool plain = !a.real_in && !a.pre && !a.in_half;
-  if constexpr (IN_T) {
+  if constexpr (IN_T && GEN) {
+    // the tile's 16 lines belong to one transform: positions u0 + c + n e_in
+    const int64_t tr = t0 / a.U, u0 = t0 - tr * a.U;
+    for (int e = tid; e < N * FL; e += NT) {
+      const int n = e / FL, c = e % FL;
+      sml[c * TS + n] = band_bin(a.gen, tr, (int)(u0 + c + n * a.e_in));
+    }
+  } else if constexpr (IN_T) {
     const int64_t tr = t0 / a.U, u0 = t0 - tr * a.U;
     const int64_t base = a.si.base(tr);
     if (plain && ((base + u0) & 1) == 0 && (a.e_in & 1) == 0 && ((uintptr_t)a.in & 15) == 0) {
@@ -124,7 +133,7 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
       int64_t b = -1, pos = 0;
       if (t < a.n_lines) {
         const int64_t tr = t / a.U, u = t - tr * a.U;
-        b = a.si.base(tr);
+        b = GEN ? tr : a.si.base(tr);    // GEN: the transform index
         pos = u * a.u_in;
       }
       lbase[tid] = b;
@@ -135,7 +144,11 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
       const int c = e / N, n = e % N;
       const int64_t b = lbase[c];
       float2 v = make_float2(0.f, 0.f);
-      if (b >= 0) v = plain ? a.in[b + lpos[c] + n] : load_in(a, b, lpos[c] + n);
+      if constexpr (GEN) {
+        if (b >= 0) v = band_bin(a.gen, b, (int)(lpos[c] + n));
+      } else {
+        if (b >= 0) v = plain ? a.in[b + lpos[c] + n] : load_in(a, b, lpos[c] + n);
+      }
       sml[c * TS + n] = v;
     }
   }
@@ -191,6 +204,25 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
   }
 }
 
+template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
+__global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
+  lines_body<N, S, IN_T, OUT_T, GEN>(a, blockIdx.x);
+}
+
+// merged form: one persistent launch over the jobs of an uneven batch
+template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
+__global__ __launch_bounds__(threads<N>()) void k_fft_lines_jobs(const LinesArgs* jobs, const JobGrid* grids,
+                                                                 const int64_t* first, int n_jobs, int64_t total,
+                                                                 JobBases b) {
+  run_jobs(jobs, grids, first, n_jobs, total, [&](const LinesArgs& j, int64_t bx, int, int) {
+    LinesArgs a = j;
+    a.in = rebase(a.in, b);
+    a.out = rebase(a.out, b);
+    if constexpr (GEN) a.gen.Z = rebase(a.gen.Z, b);
+    lines_body<N, S, IN_T, OUT_T, GEN>(a, bx);
+  });
+}
+
 template <int N, bool IN_T, bool OUT_T>
 constexpr size_t lds_bytes() {
   const size_t tile = (size_t)FL * (N + 1) * sizeof(float2);
@@ -199,35 +231,57 @@ constexpr size_t lds_bytes() {
   return std::max(tile, std::max(scratch, otile));
 }
 
-template <int N, int S, bool IN_T, bool OUT_T>
+template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
+static hipError_t launch_jobs(const MergedLaunch& m, const JobBases& b, hipStream_t s) {
+  return merged_launch<LinesArgs>((const void*)k_fft_lines_jobs<N, S, IN_T, OUT_T, GEN>, threads<N>(), m, b, s);
+}
+template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
+static int occupancy_jobs(size_t lds) {
+  return occupancy_of((const void*)k_fft_lines_jobs<N, S, IN_T, OUT_T, GEN>, threads<N>(), lds);
+}
+
+template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
 static hipError_t launch(const LinesArgs& a, hipStream_t s, bool prep) {
   const size_t lds = lds_bytes<N, IN_T, OUT_T>();
-  if (prep)
-    return lds > 64 * 1024 ? hipFuncSetAttribute((const void*)k_fft_lines<N, S, IN_T, OUT_T>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
-                           : hipSuccess;
-  const dim3 grid((unsigned)((a.n_lines + FL - 1) / FL)), block(threads<N>());
-  hipLaunchKernelGGL((k_fft_lines<N, S, IN_T, OUT_T>), grid, block, lds, s, a);
+  if (prep) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)k_fft_lines<N, S, IN_T, OUT_T, GEN>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_fft_lines_jobs<N, S, IN_T, OUT_T, GEN>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  const int64_t blocks = (a.n_lines + FL - 1) / FL;
+  if (job_recorder()) {
+    record_job(launch_jobs<N, S, IN_T, OUT_T, GEN>, occupancy_jobs<N, S, IN_T, OUT_T, GEN>, a, blocks, 1, lds);
+    return hipSuccess;
+  }
+  const dim3 grid((unsigned)blocks), block(threads<N>());
+  hipLaunchKernelGGL((k_fft_lines<N, S, IN_T, OUT_T, GEN>), grid, block, lds, s, a);
   return hipGetLastError();
 }
 
 // mode 0: rows in, rows out (one pass); 1: interleaved in and out (pass 1); 2: rows in,
-// interleaved out (pass 2)
+// interleaved out (pass 2).  gen: the input is computed by the band generator (inverse
+// transforms of the real-mode path, modes 0 and 1).
 template <int S>
-static hipError_t dispatch(int N, int mode, const LinesArgs& a, hipStream_t s, bool prep) {
-#define MCI_FL(NN)                                                  \
-  if (N == NN) {                                                    \
-    if (mode == 0) return launch<NN, S, false, false>(a, s, prep);  \
-    if (mode == 1) return launch<NN, S, true, true>(a, s, prep);    \
-    return launch<NN, S, false, true>(a, s, prep);                  \
+static hipError_t dispatch(int N, int mode, bool gen, const LinesArgs& a, hipStream_t s, bool prep) {
+#define MCI_FL(NN)                                                                                  \
+  if (N == NN) {                                                                                    \
+    if (gen && S > 0 && mode == 0) return launch<NN, S, false, false, (S > 0)>(a, s, prep);         \
+    if (gen && S > 0 && mode == 1) return launch<NN, S, true, true, (S > 0)>(a, s, prep);           \
+    if (gen) return hipErrorInvalidValue;                                                           \
+    if (mode == 0) return launch<NN, S, false, false, false>(a, s, prep);                           \
+    if (mode == 1) return launch<NN, S, true, true, false>(a, s, prep);                             \
+    return launch<NN, S, false, true, false>(a, s, prep);                                           \
   }
   MCI_FL(32) MCI_FL(48) MCI_FL(64) MCI_FL(96) MCI_FL(128) MCI_FL(192) MCI_FL(256) MCI_FL(384) MCI_FL(512)
 #undef MCI_FL
   return hipErrorInvalidValue;
 }
 
-static hipError_t run(int N, int S, int mode, const LinesArgs& a, hipStream_t s, bool prep) {
-  return S < 0 ? dispatch<-1>(N, mode, a, s, prep) : dispatch<+1>(N, mode, a, s, prep);
+static hipError_t run(int N, int S, int mode, const LinesArgs& a, hipStream_t s, bool prep, bool gen = false) {
+  return S < 0 ? dispatch<-1>(N, mode, gen, a, s, prep) : dispatch<+1>(N, mode, gen, a, s, prep);
 }
 
 }  // namespace fl
@@ -271,8 +325,10 @@ hipError_t prepare_two_pass(int A, int B) {
   for (int S : {-1, +1}) {
     if (A == 1) {
       e = fl::run(B, S, 0, fl::LinesArgs{}, nullptr, true);
+      if (e == hipSuccess && S > 0) e = fl::run(B, S, 0, fl::LinesArgs{}, nullptr, true, true);
     } else {
       if ((e = fl::run(B, S, 1, fl::LinesArgs{}, nullptr, true)) != hipSuccess) return e;
+      if (S > 0 && (e = fl::run(B, S, 1, fl::LinesArgs{}, nullptr, true, true)) != hipSuccess) return e;
       e = fl::run(A, S, 2, fl::LinesArgs{}, nullptr, true);
     }
     if (e != hipSuccess) return e;
@@ -286,22 +342,23 @@ hipError_t fft_lines(const LineXform& x, hipStream_t s) {
   fl::Side si, so;
   si.offs = x.in_offs; si.side = 0; si.div = x.real_in ? 1 : 2; si.per = x.in_per; si.sig = x.in_sig; si.tr = x.in_tr;
   so.offs = x.out_offs; so.side = 1; so.per = x.out_per; so.sig = x.out_sig; so.tr = x.out_tr;
+  const BandGen gen = x.gen ? *x.gen : BandGen{};
   if (A == 1) {
     fl::LinesArgs a{x.in, x.out, x.count, 1, si, so, 0, 1, 0, 1, x.twB, nullptr, x.pre, x.len_in, x.post, x.real_in,
-                    x.in_half, x.out_half};
-    return fl::run(B, x.sign, 0, a, s, false);
+                    x.in_half, x.out_half, gen};
+    return fl::run(B, x.sign, 0, a, s, false, x.gen != nullptr);
   }
   const int64_t L = (int64_t)A * B;
   fl::Side dense;
   dense.per = 1; dense.sig = L;
   // pass 1: A lines x[a + A b] of length B, twiddled, to tmp[k_b A + a]
   fl::LinesArgs p1{x.in, x.tmp, x.count * A, A, si, dense, 1, A, 1, A, x.twB, x.twL, x.pre, x.len_in, nullptr,
-                   x.real_in, x.in_half, 0};
-  hipError_t e = fl::run(B, x.sign, 1, p1, s, false);
+                   x.real_in, x.in_half, 0, gen};
+  hipError_t e = fl::run(B, x.sign, 1, p1, s, false, x.gen != nullptr);
   if (e != hipSuccess) return e;
   // pass 2: B contiguous lines tmp[k_b A + a] of length A, to out[k_b + B k_a]
   fl::LinesArgs p2{x.tmp, x.out, x.count * B, B, dense, so, A, 1, 1, B, x.twA, nullptr, nullptr, 0, x.post, 0, 0,
-                   x.out_half};
+                   x.out_half, BandGen{}};
   return fl::run(A, x.sign, 2, p2, s, false);
 }
 

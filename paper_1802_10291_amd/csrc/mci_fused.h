@@ -17,6 +17,7 @@ struct FusedPlan {
   int n_ti = 1;            // 2 when both groupings fit the LDS
   int lds_ti[2] = {0, 0};  // LDS bytes for ti = 1, 2
   int store = ST_F32;      // storage of samples and outputs (ST_F32 or ST_F16)
+  char name[96] = {0};     // the kernel instance, for mci_plan_kernel_name
 };
 
 // Choose a fused kernel for the descriptor (kind stays 0 when none applies).

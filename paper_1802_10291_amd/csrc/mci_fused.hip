@@ -33,6 +33,7 @@
 // of the last pass -- which lets the Bluestein forward FFT, the pointwise product and the
 // inverse FFT run back to back in registers.
 #include <algorithm>
+#include <cstdio>
 #include <cstdint>
 #include <cstdlib>
 #include <complex>
@@ -41,6 +42,7 @@
 #include "mci_device.h"
 #include "mci_fused.h"
 #include "mci_host_util.h"
+#include "mci_jobs.h"
 
 namespace mci {
 
@@ -320,8 +322,7 @@ __device__ __forceinline__ void st_quad(__half* y, int q, float2 lo, float2 hi) 
 // TI: how many of the Q/2 output transforms run side by side (1 or Q/2).  TS: storage type
 // of the samples and outputs (float or __half); all arithmetic is FP32.
 template <int PF, int BLUE, int P, int Q, int M, int TI, typename TS>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves(PF, M))))
-void k_mci1d_fused(FusedArgs a) {
+__device__ __forceinline__ void fused_body(const FusedArgs& a, int64_t sig_index) {
   extern __shared__ float2 sm[];
   constexpr int EF = PF / NT, EI = P / NT;
   const int tid = threadIdx.x;
@@ -336,7 +337,7 @@ void k_mci1d_fused(FusedArgs a) {
   {
     // one signal per workgroup: a persistent loop would keep the loop invariants of every
     // phase live across the whole body and cut the occupancy
-    const int64_t sig = blockIdx.x;
+    const int64_t sig = sig_index;
     const TS* gs = (const TS*)a.g + (a.offs ? a.offs[2 * sig] : sig * (int64_t)M * N);
     // ---------------- 1. channel DFTs, all M channels side by side
     {
@@ -622,10 +623,39 @@ void k_mci1d_fused(FusedArgs a) {
   }
 }
 
+template <int PF, int BLUE, int P, int Q, int M, int TI, typename TS>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves(PF, M))))
+void k_mci1d_fused(FusedArgs a) {
+  fused_body<PF, BLUE, P, Q, M, TI, TS>(a, blockIdx.x);
+}
+
+// merged form: one persistent launch over the jobs of an uneven batch (one signal per
+// virtual workgroup, as above)
+template <int PF, int BLUE, int P, int Q, int M, int TI, typename TS>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves(PF, M))))
+void k_mci1d_fused_jobs(const FusedArgs* jobs, const JobGrid* grids, const int64_t* first, int n_jobs, int64_t total,
+                        JobBases b) {
+  run_jobs(jobs, grids, first, n_jobs, total, [&](const FusedArgs& j, int64_t bx, int, int) {
+    FusedArgs a = j;
+    a.g = rebase(a.g, b);
+    a.y = rebase(a.y, b);
+    fused_body<PF, BLUE, P, Q, M, TI, TS>(a, bx);
+  });
+}
+
 // ---------------------------------------------------------------- host side
 struct FusedTables {
   float2 *twF, *chirp, *bhat, *wN, *twI, *wout;
 };
+
+template <int PF, int BLUE, int P, int Q, int M, int TI, typename TS>
+static hipError_t launch_jobs(const MergedLaunch& m, const JobBases& b, hipStream_t s) {
+  return merged_launch<FusedArgs>((const void*)k_mci1d_fused_jobs<PF, BLUE, P, Q, M, TI, TS>, NT, m, b, s);
+}
+template <int PF, int BLUE, int P, int Q, int M, int TI, typename TS>
+static int occupancy_jobs(size_t lds) {
+  return occupancy_of((const void*)k_mci1d_fused_jobs<PF, BLUE, P, Q, M, TI, TS>, NT, lds);
+}
 
 template <int PF, int BLUE, int P, int Q, int M, int TI, typename TS>
 static hipError_t launch_mt(const FusedPlan& fp, const void* g, void* y, int64_t batch, const int64_t* offs,
@@ -637,6 +667,10 @@ static hipError_t launch_mt(const FusedPlan& fp, const void* g, void* y, int64_t
   a.batch = batch;
   const size_t lds = (size_t)fp.lds_bytes;
   const int64_t grid = batch;   // one signal per workgroup
+  if (job_recorder()) {
+    record_job(launch_jobs<PF, BLUE, P, Q, M, TI, TS>, occupancy_jobs<PF, BLUE, P, Q, M, TI, TS>, a, grid, 1, lds);
+    return hipSuccess;
+  }
   hipLaunchKernelGGL((k_mci1d_fused<PF, BLUE, P, Q, M, TI, TS>), dim3((unsigned)grid), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
@@ -648,10 +682,17 @@ static hipError_t prep_m(const int* lds_ti) {
     hipError_t e = hipFuncSetAttribute((const void*)k_mci1d_fused<PF, BLUE, P, Q, M, 1, TS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_ti[0]);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_mci1d_fused_jobs<PF, BLUE, P, Q, M, 1, TS>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_ti[0]);
+    if (e != hipSuccess) return e;
   }
-  if (lds_ti[1] > 64 * 1024)
-    return hipFuncSetAttribute((const void*)k_mci1d_fused<PF, BLUE, P, Q, M, 2, TS>,
+  if (lds_ti[1] > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_mci1d_fused<PF, BLUE, P, Q, M, 2, TS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_ti[1]);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_mci1d_fused_jobs<PF, BLUE, P, Q, M, 2, TS>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds_ti[1]);
+  }
   return hipSuccess;
 }
 
@@ -836,6 +877,8 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const int per_cu = std::max<int>(1, (int)((160 * 1024) / std::max<int64_t>(lds, 1)));
   fp.grid_cap = std::max(1, cus) * std::min(per_cu, 8);
+  std::snprintf(fp.name, sizeof fp.name, "k_mci1d_fused: forward %s %d-point, output %d x %d-point, M=%d",
+                pick->blue == 2 ? "split-Bluestein" : pick->blue == 1 ? "Bluestein" : "direct", PF, Q / 2, P, (int)M);
   fp.kind = 1;
   return MCI_OK;
 }

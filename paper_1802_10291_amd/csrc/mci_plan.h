@@ -29,7 +29,7 @@ struct mci_plan_s {
   // and n_out/2, and its tables
   mci::FftSide rfwd, rinv;
   void* r_wN = nullptr;
-  void* r_Wo = nullptr;
+  void* r_D = nullptr;      // [n_ops][M][2K + 1] combined apply / real part / gather weights
   mci::RealPath real;
   bool use_real = false;
   int variant = MCI_VARIANT_MULTIPASS_R8;

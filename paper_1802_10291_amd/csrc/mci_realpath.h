@@ -15,9 +15,8 @@ struct RealPath {
   int64_t N = 0, H = 0, n1 = 0, n_out = 0, P = 0, K = 0;
   const FftSide* fwd = nullptr;   // length H (or N), sign -1 (Bluestein when it does not factor)
   const FftSide* inv = nullptr;   // length P = n_out / 2, sign +1, one or two passes
-  const float2* tab = nullptr;    // [n_ops][M][M][N] FP32 apply table
   const float2* wN = nullptr;     // H entries e^{-2 pi i k / N} (half only)
-  const float2* Wo = nullptr;     // 2K + 1 entries 1 + i e^{2 pi i k / n_out}, k = -K..K
+  const float2* D = nullptr;      // [n_ops][M][2K + 1] combined apply / real part / gather weights
 };
 
 size_t real_path_workspace(const RealPath& r, int64_t batch);

@@ -677,6 +677,61 @@ mci_status mci_refiner_set_params(mci_refiner_t r, const float* host, float tau)
   return MCI_OK;
 }
 
+// Checkpoint layout (little-endian, host memory): header {magic "MCIRFN01", int64 n_params,
+// int64 step, float tau, uint32 reserved}, then the FP32 master parameters, the Adam first
+// and second moments, n_params values each.
+namespace {
+struct CkptHeader {
+  char magic[8];
+  int64_t n_params;
+  int64_t step;
+  float tau;
+  uint32_t reserved;
+};
+constexpr char kCkptMagic[8] = {'M', 'C', 'I', 'R', 'F', 'N', '0', '1'};
+}  // namespace
+
+size_t mci_refiner_state_size(void) { return sizeof(CkptHeader) + (size_t)3 * NPARAM * sizeof(float); }
+
+mci_status mci_refiner_save_state(mci_refiner_t r, void* host, size_t len) {
+  if (!r || !host) return rfail(MCI_E_INVALID_ARG, "NULL argument");
+  if (len < mci_refiner_state_size()) return rfail(MCI_E_INVALID_ARG, "buffer smaller than mci_refiner_state_size()");
+  RHIP(hipSetDevice(r->device));
+  RHIP(hipDeviceSynchronize());
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.n_params = NPARAM;
+  h.step = r->step;
+  h.tau = r->tau;
+  char* out = (char*)host;
+  std::memcpy(out, &h, sizeof h);
+  float* body = (float*)(out + sizeof h);
+  RHIP(hipMemcpy(body, r->p, NPARAM * 4, hipMemcpyDeviceToHost));
+  RHIP(hipMemcpy(body + NPARAM, r->m, NPARAM * 4, hipMemcpyDeviceToHost));
+  RHIP(hipMemcpy(body + 2 * NPARAM, r->v, NPARAM * 4, hipMemcpyDeviceToHost));
+  return MCI_OK;
+}
+
+mci_status mci_refiner_load_state(mci_refiner_t r, const void* host, size_t len) {
+  if (!r || !host) return rfail(MCI_E_INVALID_ARG, "NULL argument");
+  if (len < mci_refiner_state_size()) return rfail(MCI_E_INVALID_ARG, "buffer smaller than mci_refiner_state_size()");
+  CkptHeader h;
+  std::memcpy(&h, host, sizeof h);
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.n_params != NPARAM || h.step < 0 || !(h.tau >= 0.f))
+    return rfail(MCI_E_INVALID_ARG, "not a refiner checkpoint of this network");
+  const float* body = (const float*)((const char*)host + sizeof h);
+  RHIP(hipSetDevice(r->device));
+  RHIP(hipDeviceSynchronize());
+  RHIP(hipMemcpy(r->p, body, NPARAM * 4, hipMemcpyHostToDevice));
+  RHIP(hipMemcpy(r->m, body + NPARAM, NPARAM * 4, hipMemcpyHostToDevice));
+  RHIP(hipMemcpy(r->v, body + 2 * NPARAM, NPARAM * 4, hipMemcpyHostToDevice));
+  RHIP(refresh_bf16(r, 0));
+  RHIP(hipDeviceSynchronize());
+  r->step = h.step;
+  r->tau = h.tau;
+  return MCI_OK;
+}
+
 mci_status mci_refiner_get_grads(mci_refiner_t r, float* host) {
   if (!r || !host) return rfail(MCI_E_INVALID_ARG, "NULL argument");
   RHIP(hipSetDevice(r->device));

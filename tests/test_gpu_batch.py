@@ -257,10 +257,16 @@ def _unpack(batch, plans, order, out_host):
     return res
 
 
-@pytest.mark.parametrize("storage,lanes", [("native", 4), ("native", 1), ("f16", 4)])
-def test_uneven_batch_matches_single_calls_and_oracle(torch_cuda, storage, lanes):
+@pytest.mark.parametrize("storage,lanes,merged", [("native", 4, False), ("native", 1, False), ("f16", 4, False),
+                                                  ("native", 4, True), ("native", 1, True), ("f16", 4, True)])
+def test_uneven_batch_matches_single_calls_and_oracle(torch_cuda, monkeypatch, storage, lanes, merged):
+    """Each class's own launches on the lanes, or (merged) persistent launches over job tables
+    for the classes whose kernels record as jobs: both bit-identical to single-plan calls."""
     torch = torch_cuda
+    if merged:
+        monkeypatch.setenv("MCI_BATCH_MERGED", "1")
     batch, plans, data, order, packed = _mixed_batch(torch, storage, lanes)
+    monkeypatch.delenv("MCI_BATCH_MERGED", raising=False)
     dev_in = torch.from_numpy(packed).cuda()
     out = torch.full((batch.out_elems,), float("nan"), dtype=dev_in.dtype, device="cuda")
     batch.run(dev_in, out)
@@ -290,12 +296,16 @@ def test_uneven_batch_matches_single_calls_and_oracle(torch_cuda, storage, lanes
         assert rel(got, oracle_cache[c][k]) <= tol, (MIX[c], k)
 
 
-def test_uneven_batch_graph_capture_replays(torch_cuda):
+@pytest.mark.parametrize("merged", [False, True])
+def test_uneven_batch_graph_capture_replays(torch_cuda, monkeypatch, merged):
     """The whole mixed batch (four lanes forked from and joined into the capture stream) is
     captured as one graph; each replay, with eager work and new input values in between,
     reproduces the eager result for the current input."""
     torch = torch_cuda
+    if merged:
+        monkeypatch.setenv("MCI_BATCH_MERGED", "1")
     batch, plans, data, order, packed = _mixed_batch(torch, "native", 4)
+    monkeypatch.delenv("MCI_BATCH_MERGED", raising=False)
     dev_in = torch.from_numpy(packed).cuda()
     out = torch.zeros(batch.out_elems, dtype=torch.float32, device="cuda")
     side = torch.cuda.Stream()
@@ -369,3 +379,15 @@ def test_uneven_workload_largest_classes_sampled_parity(torch_cuda, key):
             assert rel(got[b], want[b].ravel()) <= 1e-5
     small_want = oracle_1d(small_in, 2, 64, 1024)[0, 0]
     assert rel(out[batch.out_offsets[1]:batch.out_offsets[1] + 1024], small_want) <= 1e-5
+
+
+def test_kernel_names_follow_the_variant(torch_cuda):
+    """mci_plan_kernel_name describes the active variant's kernels."""
+    from paper_1802_10291_amd import Plan1D, Plan2D
+    plan = Plan1D(N=1366, n_out=16384, channels=deriv_channels(3))
+    assert plan.kernel_name().startswith("k_mci1d_fused: forward split-Bluestein 1024-point, output 2 x 4096-point")
+    plan.set_variant("real_two_pass")
+    assert plan.kernel_name().startswith("real two-pass: k_fft_lines forward")
+    plan.set_variant("multipass_r4")
+    assert plan.kernel_name().startswith("multi-pass radix-4 passes")
+    assert Plan2D(128, 128, 2).kernel_name().startswith("k_line_pass: columns 128 -> rows 128, scale 2")

@@ -325,3 +325,50 @@ def test_forward_output_matches_training_loss(torch_cuda, H, W):
     loss = float(r.backward(u, hr))
     want = float(((y.double() - hr.double()) ** 2).mean())
     assert loss == pytest.approx(want, rel=1e-5)
+
+
+def test_training_images_recipe_on_cpu():
+    """The refiner's pair generator (run here on the CPU device): values in [0, 1], seeded and
+    repeatable, different seeds give different images, and painted rectangles show as
+    constant blocks."""
+    import torch
+    from paper_1802_10291_amd.refiner_train import gpu_rgb_images
+    a = gpu_rgb_images([11, 12], 64, device="cpu")
+    b = gpu_rgb_images([11, 12], 64, device="cpu")
+    assert a.shape == (2, 3, 64, 64) and a.dtype == torch.float32
+    assert torch.equal(a, b) and not torch.equal(a[0], a[1])
+    assert float(a.min()) >= 0.0 and float(a.max()) <= 1.0
+    # some plane has a run of equal values from a rectangle (K ~ U{0..20} per plane)
+    runs = (a[..., 1:] == a[..., :-1]).float().mean()
+    assert float(runs) > 0.05
+
+
+@pytest.mark.gpu
+def test_checkpoint_resume_is_bit_identical(torch_cuda, tmp_path):
+    """Training stopped at a checkpoint and resumed in a fresh refiner (other initial
+    weights) continues bit for bit: the same parameters after the same further steps, across
+    an epoch boundary.  The checkpoint bytes round-trip, and a foreign buffer is refused."""
+    from paper_1802_10291_amd import MCIError, Refiner
+    from paper_1802_10291_amd.refiner_train import Trainer
+    r1 = Refiner(seed=4)
+    t1 = Trainer(r1, n_pairs=64, batch=8, size=64, lr=2e-3, epochs=2)
+    t1.run(max_steps=5)
+    path = str(tmp_path / "ck.npz")
+    t1.save(path)
+    t1.run(max_steps=7)                       # steps 5..11 cross the epoch boundary at 8
+    p1, _ = r1.get_params()
+    r2 = Refiner(seed=99)
+    t2 = Trainer(r2, n_pairs=64, batch=8, size=64, lr=2e-3, epochs=2)
+    t2.load(path)
+    assert (t2.epoch, t2.pos, t2.step) == (0, 40, 5)
+    t2.run(max_steps=7)
+    p2, _ = r2.get_params()
+    assert np.array_equal(p1, p2)
+    s1 = r1.save_state()
+    r3 = Refiner(seed=7)
+    r3.load_state(s1)
+    assert r3.save_state() == s1
+    with pytest.raises(MCIError):
+        r3.load_state(b"\0" * len(s1))
+    with pytest.raises(ValueError):
+        Trainer(r3, n_pairs=64, batch=8, size=64, lr=1e-3, epochs=2).load(path)
