@@ -182,7 +182,12 @@ typedef struct {
 mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out);
 
 /* mci_upsample_2d -- lr [batch][h][w] -> hr [batch][s h][s w], row-major, device pointers.
- * workspace of mci_workspace_size(plan, batch) bytes (holds the row-pass result). */
+ * workspace of mci_workspace_size(plan, batch) bytes (holds the columns pass's result).
+ * With the line passes at scale 2 (FP32 storage) the output rows s q are the input rows
+ * (interpolation consistency, Theorem 4.1): the columns pass stores only the other rows and
+ * the rows pass reads the sample rows from lr again, so lr must stay unchanged until the call's
+ * work on the stream is done (as for every input).  MCI_LP_ZR=1 / MCI_LP_FULL_COLUMNS=1 in the
+ * environment at plan creation take that form at every scale / at none. */
 mci_status mci_upsample_2d(mci_plan_t plan, const void* lr, void* hr, int64_t batch, void* workspace,
                            size_t ws_bytes, hipStream_t stream);
 

@@ -52,9 +52,13 @@ template <int N> constexpr int line_threads() { return PAIRS * (N / LineFFT<N>::
 // output row blocks that go through the LDS tile in the columns pass
 template <int N, int SC> constexpr int out_parts() { return SC * N > 1024 ? 4 : 2; }
 
-template <int N, int SC, bool COLS, typename TI, typename TO>
+template <int N, int SC, bool COLS, bool ZR, typename TI, typename TO>
 __device__ __forceinline__ void line_pass_body(const LinePassArgs& a, int64_t bx, int by) {
   constexpr int E = LineFFT<N>::E, G = N / E, NT = line_threads<N>();
+  // ZR: the columns pass leaves out polyphase row 0 (it equals the input), the rows pass
+  // takes those lines from the input image
+  constexpr int R0 = ZR && COLS ? 1 : 0;   // first polyphase component computed
+  constexpr int SR = SC - R0;              // output rows written per q (columns pass)
   extern __shared__ float2 sm2[];
   float* tile = (float*)sm2;                   // input [32][N + 1] floats
   float* otile = (float*)sm2;                  // output block [SC N / OP][32 + 1] floats (columns)
@@ -87,7 +91,9 @@ __device__ __forceinline__ void line_pass_body(const LinePassArgs& a, int64_t bx
         const int64_t col = col0 + c;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (col < a.W) {
-          const f4_nt t = __builtin_nontemporal_load((const f4_nt*)((const float*)x + xoff + n * (int64_t)a.W + col));
+          // read once (non-temporal), or kept for the rows pass, which reads the sample rows again
+          const f4_nt* src = (const f4_nt*)((const float*)x + xoff + n * (int64_t)a.W + col);
+          const f4_nt t = ZR ? *src : __builtin_nontemporal_load(src);
           v = make_float4(t.x, t.y, t.z, t.w);
         }
         tile[c * TS + n] = v.x;
@@ -101,6 +107,49 @@ __device__ __forceinline__ void line_pass_body(const LinePassArgs& a, int64_t bx
         const int64_t col = col0 + c;
         float v = 0.f;
         if (col < a.W) v = ld_as<float>(x, xoff + n * (int64_t)a.W + col);
+        tile[c * TS + n] = v;
+      }
+    }
+  } else if constexpr (ZR) {
+    // line s q + r of image b: row q of the input image for r = 0, else row (s - 1) q + r - 1
+    // of image b's packed intermediate.  The block's lines span at most two images
+    // (lines_per_img = s h >= 64 > 32): their bases are block-uniform, and the per-line
+    // choice is a select between them, so the loads stay branch-free and pipelined.
+    const int lpi = (int)a.lines_per_img, hh = lpi / SC;
+    const int64_t b0 = line0 / lpi;
+    const int R0l = (int)(line0 - b0 * lpi);
+    const float* in_b[2];
+    const float* mid_b[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t b = b0 + j;
+      const int64_t bc = b < a.lines / lpi ? b : a.lines / lpi - 1;   // the block may end in image b0
+      in_b[j] = (const float*)a.x0 + (a.offs ? a.offs[2 * bc] : bc * hh * N);
+      mid_b[j] = (const float*)x + b * hh * (SC - 1) * (int64_t)N;
+    }
+    const bool vec = (((uintptr_t)in_b[0] | (uintptr_t)in_b[1] | (uintptr_t)x) & 15) == 0;
+    auto src = [&](int c) -> const float* {
+      int R = R0l + c;
+      const int j = R >= lpi ? 1 : 0;
+      R -= j * lpi;
+      const int q = R / SC, r = R - q * SC;
+      return r == 0 ? in_b[j] + q * N : mid_b[j] + (q * (SC - 1) + r - 1) * N;
+    };
+    if (vec) {
+      for (int e4 = tid; e4 < N * LINES / 4; e4 += NT) {
+        const int c = (4 * e4) / N, n = (4 * e4) % N;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (line0 + c < a.lines) v = *(const float4*)(src(c) + n);
+        tile[c * TS + n] = v.x;
+        tile[c * TS + n + 1] = v.y;
+        tile[c * TS + n + 2] = v.z;
+        tile[c * TS + n + 3] = v.w;
+      }
+    } else {
+      for (int e = tid; e < N * LINES; e += NT) {
+        const int c = e / N, n = e % N;
+        float v = 0.f;
+        if (line0 + c < a.lines) v = src(c)[n];
         tile[c * TS + n] = v;
       }
     }
@@ -136,7 +185,7 @@ __device__ __forceinline__ void line_pass_body(const LinePassArgs& a, int64_t bx
   gfft<N, -1>(buf, l, z, a.tw);
   float2 out[SC][E];
 #pragma unroll
-  for (int r = 0; r < SC; ++r) {
+  for (int r = R0; r < SC; ++r) {
     float2 v[E];
 #pragma unroll
     for (int c = 0; c < E; ++c) v[c] = cmul(z[c], a.H[r * N + l + G * c]);
@@ -183,8 +232,8 @@ __device__ __forceinline__ void line_pass_body(const LinePassArgs& a, int64_t bx
       for (int c = part * (E / OP); c < (part + 1) * (E / OP); ++c) {
         const int q = l + G * c;
 #pragma unroll
-        for (int r = 0; r < SC; ++r) {
-          const int row = SC * q + r - part * (SC * N / OP);
+        for (int r = R0; r < SC; ++r) {
+          const int row = SR * q + (r - R0) - part * (SR * N / OP);
           otile[row * OT + 2 * g] = out[r][c].x;
           otile[row * OT + 2 * g + 1] = out[r][c].y;
         }
@@ -192,33 +241,33 @@ __device__ __forceinline__ void line_pass_body(const LinePassArgs& a, int64_t bx
       __syncthreads();
       if ((a.W & 3) == 0 && ((uintptr_t)y & 15) == 0) {
         // four consecutive columns of an output row per float4 store
-        for (int e4 = tid; e4 < (SC * N / OP) * LINES / 4; e4 += NT) {
+        for (int e4 = tid; e4 < (SR * N / OP) * LINES / 4; e4 += NT) {
           const int row = e4 / (LINES / 4), c = 4 * (e4 % (LINES / 4));
           const int64_t col = col0 + c;
           if (col < a.W)
-            *(float4*)((float*)y + (img * (SC * N) + part * (SC * N / OP) + row) * (int64_t)a.W + col) =
+            *(float4*)((float*)y + (img * (SR * N) + part * (SR * N / OP) + row) * (int64_t)a.W + col) =
                 make_float4(otile[row * OT + c], otile[row * OT + c + 1], otile[row * OT + c + 2],
                             otile[row * OT + c + 3]);
         }
       } else {
-        for (int e = tid; e < (SC * N / OP) * LINES; e += NT) {
+        for (int e = tid; e < (SR * N / OP) * LINES; e += NT) {
           const int row = e / LINES, c = e % LINES;
           const int64_t col = col0 + c;
           if (col < a.W)
-            st_as<float>(y, (img * (SC * N) + part * (SC * N / OP) + row) * (int64_t)a.W + col, otile[row * OT + c]);
+            st_as<float>(y, (img * (SR * N) + part * (SR * N / OP) + row) * (int64_t)a.W + col, otile[row * OT + c]);
         }
       }
     }
   }
 }
 
-template <int N, int SC, bool COLS, typename TI, typename TO>
+template <int N, int SC, bool COLS, bool ZR, typename TI, typename TO>
 __global__ __launch_bounds__(line_threads<N>()) void k_line_pass(LinePassArgs a) {
-  line_pass_body<N, SC, COLS, TI, TO>(a, blockIdx.x, blockIdx.y);
+  line_pass_body<N, SC, COLS, ZR, TI, TO>(a, blockIdx.x, blockIdx.y);
 }
 
 // merged form: one persistent launch over the jobs of an uneven batch
-template <int N, int SC, bool COLS, typename TI, typename TO>
+template <int N, int SC, bool COLS, bool ZR, typename TI, typename TO>
 __global__ __launch_bounds__(line_threads<N>()) void k_line_pass_jobs(const LinePassArgs* jobs, const JobGrid* grids,
                                                                       const int64_t* first, int n_jobs, int64_t total,
                                                                       JobBases b) {
@@ -226,17 +275,18 @@ __global__ __launch_bounds__(line_threads<N>()) void k_line_pass_jobs(const Line
     LinePassArgs a = j;
     a.x = rebase(a.x, b);
     a.y = rebase(a.y, b);
-    line_pass_body<N, SC, COLS, TI, TO>(a, bx, by);
+    a.x0 = rebase(a.x0, b);
+    line_pass_body<N, SC, COLS, ZR, TI, TO>(a, bx, by);
   });
 }
 
-template <int N, int SC, bool COLS, typename TI, typename TO>
+template <int N, int SC, bool COLS, bool ZR, typename TI, typename TO>
 static hipError_t launch_jobs(const MergedLaunch& m, const JobBases& b, hipStream_t s) {
-  return merged_launch<LinePassArgs>((const void*)k_line_pass_jobs<N, SC, COLS, TI, TO>, line_threads<N>(), m, b, s);
+  return merged_launch<LinePassArgs>((const void*)k_line_pass_jobs<N, SC, COLS, ZR, TI, TO>, line_threads<N>(), m, b, s);
 }
-template <int N, int SC, bool COLS, typename TI, typename TO>
+template <int N, int SC, bool COLS, bool ZR, typename TI, typename TO>
 static int occupancy_jobs(size_t lds) {
-  return occupancy_of((const void*)k_line_pass_jobs<N, SC, COLS, TI, TO>, line_threads<N>(), lds);
+  return occupancy_of((const void*)k_line_pass_jobs<N, SC, COLS, ZR, TI, TO>, line_threads<N>(), lds);
 }
 
 template <int N, int SC, bool COLS>
@@ -247,38 +297,38 @@ static size_t lds_bytes() {
   return std::max(tile, std::max(scratch, otile));
 }
 
-template <int N, int SC, bool COLS, typename TI, typename TO>
+template <int N, int SC, bool COLS, bool ZR, typename TI, typename TO>
 static hipError_t launch(const LinePassArgs& a, int64_t images, hipStream_t s) {
   dim3 grid;
   if constexpr (COLS) grid = dim3((unsigned)((a.W + LINES - 1) / LINES), (unsigned)images);
   else grid = dim3((unsigned)((a.lines + LINES - 1) / LINES));
   const size_t lds = lds_bytes<N, SC, COLS>();
   if (job_recorder()) {
-    record_job(launch_jobs<N, SC, COLS, TI, TO>, occupancy_jobs<N, SC, COLS, TI, TO>, a, grid.x, (int)grid.y, lds);
+    record_job(launch_jobs<N, SC, COLS, ZR, TI, TO>, occupancy_jobs<N, SC, COLS, ZR, TI, TO>, a, grid.x, (int)grid.y, lds);
     return hipSuccess;
   }
   const dim3 block(line_threads<N>());
-  hipLaunchKernelGGL((k_line_pass<N, SC, COLS, TI, TO>), grid, block, lds, s, a);
+  hipLaunchKernelGGL((k_line_pass<N, SC, COLS, ZR, TI, TO>), grid, block, lds, s, a);
   return hipGetLastError();
 }
 
 // raise the dynamic-LDS limit of a kernel that needs more than 64 KB (at plan time)
-template <int N, int SC, bool COLS, typename TI, typename TO>
+template <int N, int SC, bool COLS, bool ZR, typename TI, typename TO>
 static hipError_t prepare(const LinePassArgs&, int64_t, hipStream_t) {
   const size_t lds = lds_bytes<N, SC, COLS>();
   if (lds <= 64 * 1024) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute((const void*)k_line_pass<N, SC, COLS, TI, TO>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_line_pass<N, SC, COLS, ZR, TI, TO>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_line_pass_jobs<N, SC, COLS, TI, TO>,
+  return hipFuncSetAttribute((const void*)k_line_pass_jobs<N, SC, COLS, ZR, TI, TO>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <bool COLS, typename TI, typename TO>
+template <bool COLS, bool ZR, typename TI, typename TO>
 static hipError_t dispatch(int N, int SC, const LinePassArgs& a, int64_t images, hipStream_t s, bool prep) {
 #define MCI_LP(NN, SS)                                                                  \
   if (N == NN && SC == SS)                                                              \
-    return prep ? prepare<NN, SS, COLS, TI, TO>(a, images, s) : launch<NN, SS, COLS, TI, TO>(a, images, s);
+    return prep ? prepare<NN, SS, COLS, ZR, TI, TO>(a, images, s) : launch<NN, SS, COLS, ZR, TI, TO>(a, images, s);
   MCI_LP(32, 2) MCI_LP(32, 3) MCI_LP(32, 4) MCI_LP(48, 2) MCI_LP(48, 3) MCI_LP(48, 4) MCI_LP(64, 2) MCI_LP(64, 3)
   MCI_LP(64, 4) MCI_LP(96, 2) MCI_LP(96, 3) MCI_LP(96, 4) MCI_LP(128, 2) MCI_LP(128, 3) MCI_LP(128, 4)
   MCI_LP(192, 2) MCI_LP(192, 3) MCI_LP(192, 4) MCI_LP(256, 2) MCI_LP(256, 3) MCI_LP(256, 4) MCI_LP(384, 2)
@@ -328,23 +378,28 @@ std::vector<std::complex<double>> line_windows(const std::vector<std::complex<do
   return H;
 }
 
-static hipError_t line_pass(int N, int SC, bool cols, int store_in, int store_out, const LinePassArgs& a,
+static hipError_t line_pass(int N, int SC, bool cols, bool zr, int store_in, int store_out, const LinePassArgs& a,
                             int64_t images, hipStream_t s, bool prep) {
-  if (cols) {
-    if (store_in == ST_F16) return l2d::dispatch<true, __half, float>(N, SC, a, images, s, prep);
-    return l2d::dispatch<true, float, float>(N, SC, a, images, s, prep);
+  if (zr) {
+    if (store_in != ST_F32 || store_out != ST_F32) return hipErrorInvalidValue;
+    return cols ? l2d::dispatch<true, true, float, float>(N, SC, a, images, s, prep)
+                : l2d::dispatch<false, true, float, float>(N, SC, a, images, s, prep);
   }
-  if (store_out == ST_F16) return l2d::dispatch<false, float, __half>(N, SC, a, images, s, prep);
-  return l2d::dispatch<false, float, float>(N, SC, a, images, s, prep);
+  if (cols) {
+    if (store_in == ST_F16) return l2d::dispatch<true, false, __half, float>(N, SC, a, images, s, prep);
+    return l2d::dispatch<true, false, float, float>(N, SC, a, images, s, prep);
+  }
+  if (store_out == ST_F16) return l2d::dispatch<false, false, float, __half>(N, SC, a, images, s, prep);
+  return l2d::dispatch<false, false, float, float>(N, SC, a, images, s, prep);
 }
 
-hipError_t run_line_pass(int N, int SC, bool cols, int store_in, int store_out, const LinePassArgs& a,
+hipError_t run_line_pass(int N, int SC, bool cols, bool zr, int store_in, int store_out, const LinePassArgs& a,
                          int64_t images, hipStream_t s) {
-  return line_pass(N, SC, cols, store_in, store_out, a, images, s, false);
+  return line_pass(N, SC, cols, zr, store_in, store_out, a, images, s, false);
 }
 
-hipError_t prepare_line_pass(int N, int SC, bool cols, int store_in, int store_out) {
-  return line_pass(N, SC, cols, store_in, store_out, LinePassArgs{}, 0, nullptr, true);
+hipError_t prepare_line_pass(int N, int SC, bool cols, bool zr, int store_in, int store_out) {
+  return line_pass(N, SC, cols, zr, store_in, store_out, LinePassArgs{}, 0, nullptr, true);
 }
 
 }  // namespace mci

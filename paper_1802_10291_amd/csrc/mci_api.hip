@@ -450,17 +450,21 @@ static mci_status run_2d(const mci_plan_s* p, const void* lr, void* hr, int64_t 
     // x2 0.134 -> 0.144 ms at 64 MiB chunks, 0.27 ms at 16 MiB.)
     const int64_t h = p->d2.h, w = p->d2.w, sc = p->d2.scale;
     float* mid = (float*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    // with the sample rows passed through, mid holds only the rows s q + r, r >= 1
+    const bool zr = p->lp_zr;
+    const int64_t mid_rows = zr ? (sc - 1) * h : sc * h;
     const int64_t max_y = 65535;   // images per column-pass launch (grid y)
     for (int64_t b0 = 0; b0 < batch; b0 += max_y) {
       const int64_t nb = std::min(max_y, batch - b0);
       const char* x0 = offs ? (const char*)lr : (const char*)lr + b0 * h * w * store_bytes(p->store);
-      LinePassArgs ac{x0, mid + b0 * sc * h * w, 0, w, (const float2*)p->lp_H[0], (const float2*)p->lp_tw[0],
+      LinePassArgs ac{x0, mid + b0 * mid_rows * w, 0, w, (const float2*)p->lp_H[0], (const float2*)p->lp_tw[0],
                       offs ? offs + 2 * b0 : nullptr, 1};
-      hipError_t err = run_line_pass((int)h, (int)sc, true, p->store, ST_F32, ac, nb, stream);
+      hipError_t err = run_line_pass((int)h, (int)sc, true, zr, p->store, ST_F32, ac, nb, stream);
       if (err != hipSuccess) return fail(MCI_E_DEVICE, std::string("column pass: ") + hipGetErrorString(err));
     }
     LinePassArgs ar{mid, hr, batch * sc * h, 0, (const float2*)p->lp_H[1], (const float2*)p->lp_tw[1], offs, sc * h};
-    hipError_t err = run_line_pass((int)w, (int)sc, false, ST_F32, p->store, ar, 0, stream);
+    if (zr) ar.x0 = lr;
+    hipError_t err = run_line_pass((int)w, (int)sc, false, zr, ST_F32, p->store, ar, 0, stream);
     if (err != hipSuccess) return fail(MCI_E_DEVICE, std::string("row pass: ") + hipGetErrorString(err));
     return MCI_OK;
   }
@@ -604,7 +608,8 @@ mci_status mci_plan_kernel_name(mci_plan_t p, char* name, size_t len) {
   if (p->dims == 2) {
     if (p->lp)
       s = "k_line_pass: columns " + std::to_string(p->d2.h) + " -> rows " + std::to_string(p->d2.w) + ", scale " +
-          std::to_string(p->d2.scale) + ", " + std::to_string(p->d2.channels) + " channels";
+          std::to_string(p->d2.scale) + ", " + std::to_string(p->d2.channels) + " channels" +
+          (p->lp_zr ? ", sample rows passed through" : "");
     else
       s = "2-D multi-pass: 1-D multi-pass rows and columns";
   } else if (p->use_fused) {
@@ -683,10 +688,14 @@ mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out)
   if (desc->precision == MCI_F32 && line_pass_supported(desc->h, desc->scale) &&
       line_pass_supported(desc->w, desc->scale) && !std::getenv("MCI_DISABLE_FUSED")) {
     // axis 0: columns (length h), axis 1: rows (length w)
+    double h0_dev = 0.0;   // max |len H_0 - 1| of the columns pass
     for (int axis = 0; axis < 2; ++axis) {
       const mci_plan_s* q = axis == 0 ? p->cols : p->rows;
       const int64_t len = q->d.N;
       std::vector<std::complex<double>> H = line_windows(q->tab_host, len, q->d.n1, desc->scale, M2);
+      // the line passes' transforms are unnormalised: the identity window is 1 / len
+      if (axis == 0)
+        for (int64_t k = 0; k < len; ++k) h0_dev = std::max(h0_dev, std::abs(H[k] * (double)len - 1.0));
       std::vector<std::complex<double>> tw(len);
       for (int64_t k = 0; k < len; ++k) tw[k] = root_of_unity(k, len);
       hipError_t e;
@@ -695,8 +704,17 @@ mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out)
       p->lp_tw[axis] = upload<float2>(tw, e);
       if (!p->lp_tw[axis] || e != hipSuccess) { destroy_plan(p); return fail(MCI_E_DEVICE, "twiddle upload"); }
     }
-    if (prepare_line_pass(desc->h, desc->scale, true, p->store, ST_F32) != hipSuccess ||
-        prepare_line_pass(desc->w, desc->scale, false, ST_F32, p->store) != hipSuccess) {
+    // The columns pass's window H_0 is the identity when the grid's row s q is the sample row
+    // q (interpolation consistency); then that row is the input row itself and the passes
+    // move it straight from the input (FP32 storage).  Measured on one box at 100 steps: x2
+    // 0.1278 -> 0.1226 ms; x3 0.0673 -> 0.0708 and x4 0.1009 -> 0.1024 ms, where the rows pass's
+    // extra reads of the input cost more than the smaller intermediate saves.  So it is the
+    // default at scale 2 only; MCI_LP_ZR=1 takes it at every scale, MCI_LP_FULL_COLUMNS=1 at none.
+    const bool zr_env = std::getenv("MCI_LP_ZR") && std::getenv("MCI_LP_ZR")[0] == '1';
+    p->lp_zr = p->store == ST_F32 && h0_dev <= 1e-9 && (desc->scale == 2 || zr_env) &&
+               !std::getenv("MCI_LP_FULL_COLUMNS");
+    if (prepare_line_pass(desc->h, desc->scale, true, p->lp_zr, p->store, ST_F32) != hipSuccess ||
+        prepare_line_pass(desc->w, desc->scale, false, p->lp_zr, ST_F32, p->store) != hipSuccess) {
       destroy_plan(p);
       return fail(MCI_E_DEVICE, "line-pass LDS attribute");
     }

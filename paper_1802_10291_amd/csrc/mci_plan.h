@@ -38,6 +38,7 @@ struct mci_plan_s {
   // 2-D fused line passes: windows H[SC][len] and twiddles per axis (cols, rows)
   bool lp = false;          // active
   bool lp_avail = false;    // built
+  bool lp_zr = false;       // sample rows passed through (the columns pass's H_0 is the identity)
   void* lp_H[2] = {nullptr, nullptr};
   void* lp_tw[2] = {nullptr, nullptr};
   // 2-D

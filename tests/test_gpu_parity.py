@@ -295,6 +295,32 @@ def test_2d_three_channels_parity(torch_cuda, h, w, s):
     assert np.abs(hr[:, ::s, ::s] - lr).max() <= 1e-5
 
 
+@pytest.mark.parametrize("h,w,s,M", [(256, 256, 2, 2), (128, 128, 4, 2), (64, 96, 3, 3), (48, 32, 2, 2)])
+def test_2d_sample_rows_passed_through(torch_cuda, monkeypatch, h, w, s, M):
+    """Interpolation consistency makes the columns pass's polyphase row 0 the input itself, so
+    the FP32 line passes can skip computing it, with the rows pass reading those lines from the
+    input (the default at scale 2, MCI_LP_ZR=1 at the others).  Against the form that computes
+    every row (MCI_LP_FULL_COLUMNS=1) and the oracle; ragged batch (3 images) so the rows
+    pass's 32-line blocks straddle images."""
+    from paper_1802_10291_amd import Plan2D
+    lr = SI.random_field_images(31, 3, h, w)
+    if s != 2:
+        assert "passed through" not in Plan2D(h, w, s, channels=M).kernel_name()
+        monkeypatch.setenv("MCI_LP_ZR", "1")
+    plan = Plan2D(h, w, s, channels=M)
+    assert "sample rows passed through" in plan.kernel_name()
+    monkeypatch.setenv("MCI_LP_FULL_COLUMNS", "1")
+    full = Plan2D(h, w, s, channels=M)
+    assert "passed through" not in full.kernel_name() and full.info.path == 1
+    x = torch_cuda.from_numpy(lr).cuda()
+    a = plan.upsample(x).cpu().numpy().astype(np.float64)
+    b = full.upsample(x).cpu().numpy().astype(np.float64)
+    want = O.upsample_2d(lr.astype(np.float64), s, M=M)
+    check_rows(a, want, 1e-5)
+    check_rows(a, b, 2e-6)
+    assert np.abs(a[:, ::s, ::s] - lr).max() <= 1e-5
+
+
 def test_2d_three_channels_fp64_exact(torch_cuda):
     from paper_1802_10291_amd import Plan2D
     lr = SI.random_field_images(22, 2, 30, 36).astype(np.float64)
