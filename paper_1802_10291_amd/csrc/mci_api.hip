@@ -82,7 +82,8 @@ static void free_side(FftSide& f) {
   if (f.bhat) (void)hipFree(f.bhat);
   if (f.twA) (void)hipFree(f.twA);
   if (f.twB) (void)hipFree(f.twB);
-  f.tw = f.chirp = f.bhat = f.twA = f.twB = nullptr;
+  if (f.twL) (void)hipFree(f.twL);
+  f.tw = f.chirp = f.bhat = f.twA = f.twB = f.twL = nullptr;
 }
 
 static mci_status build_side(FftSide& f, int64_t len, int sign, int prec, bool force_blue = false) {
@@ -114,6 +115,13 @@ static mci_status build_side(FftSide& f, int64_t len, int sign, int prec, bool f
       if (!d || e != hipSuccess) return fail(MCI_E_DEVICE, "line twiddle upload");
       (which ? f.twB : f.twA) = d;
     }
+    {
+      std::vector<std::complex<double>> t(fl_twiddle_entries(f.lexec), 0.0);
+      for (int64_t j = 0; j < std::min<int64_t>(f.lexec, kTwLo); ++j) t[j] = root_of_unity(j, f.lexec);
+      for (int64_t i = 0; kTwLo * i < f.lexec; ++i) t[kTwLo + i] = root_of_unity(kTwLo * i, f.lexec);
+      f.twL = upload<float2>(t, e);
+      if (!f.twL || e != hipSuccess) return fail(MCI_E_DEVICE, "two-pass twiddle upload");
+    }
     if ((e = prepare_two_pass(f.fa, f.fb)) != hipSuccess) return fail(MCI_E_DEVICE, "two-pass LDS attribute");
   } else {
     f.fa = f.fb = 0;
@@ -130,6 +138,8 @@ static mci_status build_side(FftSide& f, int64_t len, int sign, int prec, bool f
   }
   host_fft(b, f.radices, -1);
   for (auto& v : b) v /= (double)f.lexec;
+  // stored zero-padded to lexec entries, so that a transform's output stage can apply it by position
+  c.resize(f.lexec, 0.0);
   f.chirp = prec == MCI_F64 ? upload<double2>(c, e) : upload<float2>(c, e);
   if (!f.chirp || e != hipSuccess) return fail(MCI_E_DEVICE, "chirp upload");
   f.bhat = prec == MCI_F64 ? upload<double2>(b, e) : upload<float2>(b, e);

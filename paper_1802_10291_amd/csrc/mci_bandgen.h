@@ -25,6 +25,7 @@ struct BandGen {
   const float2* D;       // [n_ops][M][2K + 1]: the apply, real part and gather weight of X_m at k
   int M, n_ops, N, H, n1, K, P;
   int half_rows;         // Z holds half-length transforms (even N)
+  int one;               // P >= 2K + 1: a bin holds at most one band position (k = b or b - P)
 };
 
 // X_m[r] of signal Zs for every channel (r in [0, N)): the transform itself for odd N, else
@@ -82,6 +83,22 @@ __device__ __forceinline__ float2 band_bin(const BandGen& g, int64_t tr, int b) 
   const int P = g.P, K = g.K, N = g.N;
   const float2* Dop = g.D + (int64_t)op * g.M * (2 * K + 1);
   float2 acc = make_float2(0.f, 0.f);
+  if (g.one) {
+    // k = b (b <= K) or b - P (b >= P - K); the bins between hold no band position.  |k| <= K
+    // <= M N, so k mod N takes a few conditional steps instead of a division.
+    const bool hi = b > K;
+    if (hi && b < P - K) return acc;
+    const int k = hi ? b - P : b;
+    int r = k;
+    while (r < 0) r += N;
+    while (r >= N) r -= N;
+    float2 x[MM];
+    chan_x<MM>(g, Zs, r, x);
+#pragma unroll
+    for (int m = 0; m < MM; ++m)
+      if (m < g.M) acc = cadd(acc, cmul(x[m], Dop[(int64_t)m * (2 * K + 1) + k + K]));
+    return acc;
+  }
   for (int k = b - ((b + K) / P) * P; k <= K; k += P) {
     int r = k % N;
     if (r < 0) r += N;

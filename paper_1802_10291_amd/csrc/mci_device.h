@@ -15,6 +15,16 @@
 
 namespace mci {
 
+// The dispatcher hands workgroup b of a launch to XCD b mod 8.  xcd_block renumbers the
+// launch so that each XCD takes one contiguous range of logical blocks (XCD x: logical
+// x floor(G/8) + min(x, G mod 8) + b / 8), which keeps neighbouring blocks that read the same
+// data on one XCD and its L2.  A bijection on [0, G) for any grid size G.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
+  const int64_t x = b % kXcds, s = b / kXcds, q = G / kXcds, r = G % kXcds;
+  return x * q + (x < r ? x : r) + s;
+}
+
 template <typename T> struct cvec;
 template <> struct cvec<float> { using type = float2; };
 template <> struct cvec<double> { using type = double2; };

@@ -8,6 +8,16 @@
 
 namespace mci {
 
+// Pass 1 of an A x B transform of length L multiplies element k_b of line a by w_L^m,
+// m = a k_b < L.  The factors come from a two-level table: w_L^m = lo[m mod kTwLo] hi[m / kTwLo],
+// lo[j] = w_L^j (entries 0 .. kTwLo - 1) and hi[i] = w_L^{kTwLo i} (entries kTwLo + i), both
+// exact roundings, so a factor is one rounding further from w_L^m than a direct table entry,
+// and the 8 KB low table stays in the L1 cache where a per-element gather from an L-entry
+// table missed it on nearly every element.
+constexpr int kTwLoBits = 10;
+constexpr int64_t kTwLo = (int64_t)1 << kTwLoBits;
+inline int64_t fl_twiddle_entries(int64_t L) { return kTwLo + (L + kTwLo - 1) / kTwLo; }
+
 // a line length of the register-staged line FFT: 32, 48, 64, 96, 128, 192, 256, 384, 512
 bool line_length_ok(int64_t n);
 // L = A B with A, B line lengths (most balanced), or A = 1 and B = L for a line length
@@ -30,7 +40,7 @@ struct LineXform {
   float2* tmp = nullptr;
   int64_t count = 0;
   int A = 1, B = 0, sign = -1;
-  const float2 *twA = nullptr, *twB = nullptr, *twL = nullptr;
+  const float2 *twA = nullptr, *twB = nullptr, *twL = nullptr;   // twL: the two-level table above
   const int64_t* in_offs = nullptr;
   int64_t in_per = 1, in_sig = 0, in_tr = 0;
   const int64_t* out_offs = nullptr;

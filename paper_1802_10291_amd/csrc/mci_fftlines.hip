@@ -53,7 +53,7 @@ struct LinesArgs {
   int64_t u_in, e_in;       // complex strides of a line and of its elements (input)
   int64_t u_out, e_out;     // (output)
   const float2* tw;         // N entries e^{-2 pi i k / N}
-  const float2* twL;        // L entries e^{-2 pi i m / L} (pass 1 of two), or null
+  const float2* twL;        // pass 1 of two: the two-level table of e^{-2 pi i m / L} (mci_fftlines.h), or null
   const float2* pre;        // input position p: p < len_in ? in * pre[p] : 0 (if pre), else in
   int64_t len_in;           // with pre or real input: positions at or beyond it read as zero
   const float2* post;       // output position k multiplied by post[k], or null
@@ -97,6 +97,7 @@ __device__ __forceinline__ void lines_body(const LinesArgs& a, int64_t bx) {
   if constexpr (IN_T && GEN) {
     // the tile's 16 lines belong to one transform: positions u0 + c + n e_in
     const int64_t tr = t0 / a.U, u0 = t0 - tr * a.U;
+#pragma unroll
     for (int e = tid; e < N * FL; e += NT) {
       const int n = e / FL, c = e % FL;
       sml[c * TS + n] = band_bin(a.gen, tr, (int)(u0 + c + n * a.e_in));
@@ -163,7 +164,8 @@ __device__ __forceinline__ void lines_body(const LinesArgs& a, int64_t bx) {
   if (a.twL) {
 #pragma unroll
     for (int c = 0; c < E; ++c) {
-      float2 w = a.twL[u * (l + G * c)];
+      const int m = (int)(u * (l + G * c));   // < L
+      float2 w = cmul(a.twL[m & (int)(kTwLo - 1)], a.twL[kTwLo + (m >> kTwLoBits)]);
       if constexpr (S > 0) w.y = -w.y;
       v[c] = cmul(v[c], w);
     }
@@ -206,7 +208,9 @@ __device__ __forceinline__ void lines_body(const LinesArgs& a, int64_t bx) {
 
 template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
 __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
-  lines_body<N, S, IN_T, OUT_T, GEN>(a, blockIdx.x);
+  // the generating first pass: the blocks of one transform all read that signal's channel
+  // spectra, so they go to one XCD, whose L2 then serves the re-reads
+  lines_body<N, S, IN_T, OUT_T, GEN>(a, GEN && IN_T ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x);
 }
 
 // merged form: one persistent launch over the jobs of an uneven batch

@@ -28,8 +28,10 @@ struct FftSide {
   int fa = 0, fb = 0;
   void* twA = nullptr;
   void* twB = nullptr;
+  // pass 1's twiddles w^m, m < lexec, as a product of two small tables (see mci_fftlines.h)
+  void* twL = nullptr;
   bool two_pass = false;
-  void* chirp = nullptr;      // Bluestein: e^{sign i pi k^2 / len}, len entries
+  void* chirp = nullptr;      // Bluestein: e^{sign i pi k^2 / len} for k < len, zero-padded to lexec entries
   void* bhat = nullptr;       // Bluestein: forward DFT_P of the conjugate chirp, divided by P
 };
 

@@ -323,7 +323,7 @@ static hipError_t direction(const FftSide& f, int sign, cx<T>* buf[2], int& cur,
   if constexpr (std::is_same<T, float>::value) {
     if (f.two_pass)
       return fft_two_pass(buf[cur], buf[cur], buf[1 - cur], count, f.fa, f.fb, sign, (const float2*)f.twA,
-                          (const float2*)f.twB, (const float2*)f.tw, s);
+                          (const float2*)f.twB, (const float2*)f.twL, s);
   }
   if (sign < 0) return run_passes<T, -1>(buf, cur, count, f.lexec, f.radices, tw, s);
   return run_passes<T, +1>(buf, cur, count, f.lexec, f.radices, tw, s);

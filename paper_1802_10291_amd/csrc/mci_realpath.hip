@@ -5,7 +5,7 @@
 //     z[p] = g[2p] + i g[2p+1] (odd N: as N real values), goes through a one- or two-pass
 //     transform of length H (N) (through Bluestein's chirp convolution when that length does
 //     not factor: the chirp is applied as the first pass loads, the filter spectrum as the
-//     second one stores);
+//     second one stores, and the output chirp as the inverse transform's last pass stores);
 //  2. apply (eq. matrixeqn1) and the real part: X_m[r] = E[r'] + e^{-2 pi i r / N} O[r'],
 //     r' = r mod H, with E, O the even/odd-sample DFTs recovered from Z (odd N: X_m = Z);
 //     a(k) = sum_m X_m[k mod N] Tab[m][j][i] for k = n1 + i + jN; S(k) = (a(k) + conj a(-k)) / 2;
@@ -55,7 +55,7 @@ hipError_t run_real_1d(const RealPath& r, const void* g, void* y, int64_t batch,
   LineXform x;
   x.in = (const float2*)g; x.out = Zf; x.tmp = T1; x.count = batch * r.M;
   x.A = f.fa; x.B = f.fb; x.sign = -1;
-  x.twA = (const float2*)f.twA; x.twB = (const float2*)f.twB; x.twL = (const float2*)f.tw;
+  x.twA = (const float2*)f.twA; x.twB = (const float2*)f.twB; x.twL = (const float2*)f.twL;
   const int64_t L_in = r.half ? r.H : r.N;   // complex pairs, or real samples, per row
   x.in_offs = offs; x.in_per = r.M; x.in_sig = r.M * L_in; x.in_tr = L_in;
   x.real_in = !r.half;
@@ -72,19 +72,21 @@ hipError_t run_real_1d(const RealPath& r, const void* g, void* y, int64_t batch,
     LineXform u;
     u.in = Zf; u.out = Zf; u.tmp = T1; u.count = batch * r.M;
     u.A = f.fa; u.B = f.fb; u.sign = +1;
-    u.twA = (const float2*)f.twA; u.twB = (const float2*)f.twB; u.twL = (const float2*)f.tw;
+    u.twA = (const float2*)f.twA; u.twB = (const float2*)f.twB; u.twL = (const float2*)f.twL;
     u.in_sig = u.out_sig = Lz;
+    u.post = (const float2*)f.chirp;   // the output chirp, applied as the last pass stores
     if ((e = fft_lines(u, s)) != hipSuccess) return e;
   }
   // 2-3. one inverse transform of length P per (signal, op), written as the output row; its
   //    first pass computes its input, the gathered spectrum Zc, from the channel spectra as
   //    it loads it (the apply, the real part and the polyphase gather: band_bin)
-  const BandGen bg{Zf, Lz, f.blue ? (const float2*)f.chirp : nullptr, r.wN, r.D, r.M, r.n_ops,
-                   (int)r.N, (int)r.H, (int)r.n1, (int)r.K, (int)r.P, r.half ? 1 : 0};
+  const BandGen bg{Zf, Lz, nullptr, r.wN, r.D, r.M, r.n_ops,
+                   (int)r.N, (int)r.H, (int)r.n1, (int)r.K, (int)r.P, r.half ? 1 : 0,
+                   r.P >= 2 * r.K + 1 ? 1 : 0};
   LineXform o;
   o.in = nullptr; o.out = (float2*)y; o.tmp = T2; o.count = batch * r.n_ops;
   o.A = v.fa; o.B = v.fb; o.sign = +1;
-  o.twA = (const float2*)v.twA; o.twB = (const float2*)v.twB; o.twL = (const float2*)v.tw;
+  o.twA = (const float2*)v.twA; o.twB = (const float2*)v.twB; o.twL = (const float2*)v.twL;
   o.in_sig = r.P;
   o.out_offs = offs; o.out_per = r.n_ops; o.out_sig = r.n_ops * r.P; o.out_tr = r.P;
   o.out_half = r.f16;
