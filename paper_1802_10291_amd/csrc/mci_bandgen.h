@@ -92,12 +92,34 @@ __device__ __forceinline__ float2 band_bin(const BandGen& g, int64_t tr, int b) 
     int r = k;
     while (r < 0) r += N;
     while (r >= N) r -= N;
-    float2 x[MM];
-    chan_x<MM>(g, Zs, r, x);
+    const float2* Dk = Dop + k + K;
+    if (!g.half_rows || g.post) {
+      float2 x[MM];
+      chan_x<MM>(g, Zs, r, x);
+#pragma unroll
+      for (int m = 0; m < MM; ++m)
+        if (m < g.M) acc = cadd(acc, cmul(x[m], Dk[(int64_t)m * (2 * K + 1)]));
+      return acc;
+    }
+    // X_m = E + s w O with E = (z1 + conj z2) / 2, O = (z1 - conj z2) / (2i), s = +-1, is
+    // z1 alpha + conj(z2) beta with alpha = (1 - i s w) / 2, beta = (1 + i s w) / 2, so the bin
+    // is alpha sum_m z1_m D_m + beta sum_m conj(z2_m) D_m
+    const int H = g.H;
+    const int rh = r < H ? r : r - H;
+    const int rr = rh == 0 ? 0 : H - rh;
+    const float sg = r < H ? 0.5f : -0.5f;
+    const float2 w = g.wN[rh];
+    const float2 al = make_float2(0.5f + sg * w.y, -sg * w.x), be = make_float2(0.5f - sg * w.y, sg * w.x);
+    float2 s1 = make_float2(0.f, 0.f), s2 = s1;
 #pragma unroll
     for (int m = 0; m < MM; ++m)
-      if (m < g.M) acc = cadd(acc, cmul(x[m], Dop[(int64_t)m * (2 * K + 1) + k + K]));
-    return acc;
+      if (m < g.M) {
+        const float2 d = Dk[(int64_t)m * (2 * K + 1)];
+        const float2 z1 = Zs[m * g.Lz + rh], z2 = Zs[m * g.Lz + rr];
+        s1 = make_float2(s1.x + z1.x * d.x - z1.y * d.y, s1.y + z1.x * d.y + z1.y * d.x);
+        s2 = make_float2(s2.x + z2.x * d.x + z2.y * d.y, s2.y + z2.x * d.y - z2.y * d.x);   // conj(z2) d
+      }
+    return cadd(cmul(al, s1), cmul(be, s2));
   }
   for (int k = b - ((b + K) / P) * P; k <= K; k += P) {
     int r = k % N;

@@ -20,6 +20,12 @@ namespace mci {
 // x floor(G/8) + min(x, G mod 8) + b / 8), which keeps neighbouring blocks that read the same
 // data on one XCD and its L2.  A bijection on [0, G) for any grid size G.
 constexpr int kXcds = 8;
+
+// Word 3 of a buffer resource for untyped (raw) access on this architecture: buffer loads
+// then take a byte offset in one VGPR and a uniform one in an SGPR, with no 64-bit address
+// arithmetic per access (out-of-range offsets read zero).
+constexpr int kRawBufferWord3 = 0x00020000;
+
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
   const int64_t x = b % kXcds, s = b / kXcds, q = G / kXcds, r = G % kXcds;
   return x * q + (x < r ? x : r) + s;

@@ -75,10 +75,6 @@ struct FusedArgs {
 // Stockham passes then spread over all banks.
 __device__ __forceinline__ int pad(int x) { return x + (x >> 4); }
 
-// Word 3 of a buffer resource for untyped (raw) access on this architecture: buffer loads
-// then take a byte offset in one VGPR and a uniform one in an SGPR, with no 64-bit address
-// arithmetic per access.
-constexpr int kRawBufferWord3 = 0x00020000;
 constexpr int padded(int n) { return n + (n >> 4) + 1; }
 static_assert(NT % 16 == 0, "pad(tid + NT c) = pad(tid) + c (NT + NT / 16) needs NT % 16 == 0");
 
