@@ -59,6 +59,13 @@ struct LineXform {
   const BandGen* gen = nullptr;
 };
 hipError_t fft_lines(const LineXform& x, hipStream_t s);
+// Bluestein's chirp convolution, for two-pass lengths (A > 1): the forward transform of x's
+// input (x.pre applied as it loads), times filt at each natural position, then the inverse
+// transform (x.post applied as it stores) into x.out, in three passes instead of four: the
+// forward's second pass, the product and the inverse's first pass (factors B x A, so that it
+// takes the same lines) run in one kernel.  x.tmp and mid hold count A B complex each; x.out,
+// x.tmp and mid are distinct.  Forward direction (x.sign = -1), FP32 output.
+hipError_t fft_chirp_conv(const LineXform& x, const float2* filt, float2* mid, hipStream_t s);
 
 // count transforms of length A B (contiguous, complex) from in to out with sign `sign`;
 // tmp (count A B complex) holds the pass-1 result; twA, twB, twL: e^{-2 pi i k / n} tables of

@@ -60,6 +60,7 @@ struct LinesArgs {
   int real_in;              // input holds real values: position p reads (in[p], 0)
   int in_half, out_half;    // input / output stored as FP16 (half2 pairs, or halves for real input)
   BandGen gen;              // GEN kernels: input position p of transform t is band_bin(gen, t, p)
+  const float2* mid;        // MID kernels: the filter multiplying the spectrum between the two transforms
 };
 
 // input position p of the transform whose first element is element `base` of the input
@@ -84,7 +85,7 @@ __device__ __forceinline__ void store_out(const LinesArgs& a, int64_t q, float2 
 // e); they then share one transform and U is a multiple of 16.  Otherwise lines are rows
 // (element stride 1).  Positions inside a transform: input u u_in + n e_in, output
 // u u_out + k e_out.
-template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
+template <int N, int S, bool IN_T, bool OUT_T, bool GEN, bool MID>
 __device__ __forceinline__ void lines_body(const LinesArgs& a, int64_t bx) {
   constexpr int E = LinesFFT<N>::E, G = N / E, NT = threads<N>();
   constexpr int TS = N + 1;
@@ -161,12 +162,21 @@ __device__ __forceinline__ void lines_body(const LinesArgs& a, int64_t bx) {
   gfft<N, S, LinesFFT<N>>(sml + g * padded(N), l, v, a.tw);
   const int64_t t = t0 + g;
   const int64_t tr = t / a.U, u = t - tr * a.U;
+  // MID: this is the last pass of a forward transform (factors A x B, line u = k_b, element
+  // k = k_a); the spectrum is multiplied by the filter at its natural position k_b + B k_a and
+  // the inverse transform (factors B x A) takes its first pass on the same line
+  constexpr int ST = MID ? +1 : S;   // direction of the twiddles below
+  if constexpr (MID) {
+#pragma unroll
+    for (int c = 0; c < E; ++c) v[c] = cmul(v[c], a.mid[u + a.U * (int64_t)(l + G * c)]);
+    gfft<N, +1, LinesFFT<N>>(sml + g * padded(N), l, v, a.tw);
+  }
   if (a.twL) {
 #pragma unroll
     for (int c = 0; c < E; ++c) {
       const int m = (int)(u * (l + G * c));   // < L
       float2 w = cmul(a.twL[m & (int)(kTwLo - 1)], a.twL[kTwLo + (m >> kTwLoBits)]);
-      if constexpr (S > 0) w.y = -w.y;
+      if constexpr (ST > 0) w.y = -w.y;
       v[c] = cmul(v[c], w);
     }
   }
@@ -206,15 +216,15 @@ __device__ __forceinline__ void lines_body(const LinesArgs& a, int64_t bx) {
   }
 }
 
-template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
+template <int N, int S, bool IN_T, bool OUT_T, bool GEN, bool MID>
 __global__ __launch_bounds__(threads<N>()) void k_fft_lines(LinesArgs a) {
   // the generating first pass: the blocks of one transform all read that signal's channel
   // spectra, so they go to one XCD, whose L2 then serves the re-reads
-  lines_body<N, S, IN_T, OUT_T, GEN>(a, GEN && IN_T ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x);
+  lines_body<N, S, IN_T, OUT_T, GEN, MID>(a, GEN && IN_T ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x);
 }
 
 // merged form: one persistent launch over the jobs of an uneven batch
-template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
+template <int N, int S, bool IN_T, bool OUT_T, bool GEN, bool MID>
 __global__ __launch_bounds__(threads<N>()) void k_fft_lines_jobs(const LinesArgs* jobs, const JobGrid* grids,
                                                                  const int64_t* first, int n_jobs, int64_t total,
                                                                  JobBases b) {
@@ -223,7 +233,7 @@ __global__ __launch_bounds__(threads<N>()) void k_fft_lines_jobs(const LinesArgs
     a.in = rebase(a.in, b);
     a.out = rebase(a.out, b);
     if constexpr (GEN) a.gen.Z = rebase(a.gen.Z, b);
-    lines_body<N, S, IN_T, OUT_T, GEN>(a, bx);
+    lines_body<N, S, IN_T, OUT_T, GEN, MID>(a, bx);
   });
 }
 
@@ -235,49 +245,52 @@ constexpr size_t lds_bytes() {
   return std::max(tile, std::max(scratch, otile));
 }
 
-template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
+template <int N, int S, bool IN_T, bool OUT_T, bool GEN, bool MID>
 static hipError_t launch_jobs(const MergedLaunch& m, const JobBases& b, hipStream_t s) {
-  return merged_launch<LinesArgs>((const void*)k_fft_lines_jobs<N, S, IN_T, OUT_T, GEN>, threads<N>(), m, b, s);
+  return merged_launch<LinesArgs>((const void*)k_fft_lines_jobs<N, S, IN_T, OUT_T, GEN, MID>, threads<N>(), m, b, s);
 }
-template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
+template <int N, int S, bool IN_T, bool OUT_T, bool GEN, bool MID>
 static int occupancy_jobs(size_t lds) {
-  return occupancy_of((const void*)k_fft_lines_jobs<N, S, IN_T, OUT_T, GEN>, threads<N>(), lds);
+  return occupancy_of((const void*)k_fft_lines_jobs<N, S, IN_T, OUT_T, GEN, MID>, threads<N>(), lds);
 }
 
-template <int N, int S, bool IN_T, bool OUT_T, bool GEN>
+template <int N, int S, bool IN_T, bool OUT_T, bool GEN, bool MID>
 static hipError_t launch(const LinesArgs& a, hipStream_t s, bool prep) {
   const size_t lds = lds_bytes<N, IN_T, OUT_T>();
   if (prep) {
     if (lds <= 64 * 1024) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void*)k_fft_lines<N, S, IN_T, OUT_T, GEN>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_fft_lines<N, S, IN_T, OUT_T, GEN, MID>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_fft_lines_jobs<N, S, IN_T, OUT_T, GEN>,
+    return hipFuncSetAttribute((const void*)k_fft_lines_jobs<N, S, IN_T, OUT_T, GEN, MID>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
   const int64_t blocks = (a.n_lines + FL - 1) / FL;
   if (job_recorder()) {
-    record_job(launch_jobs<N, S, IN_T, OUT_T, GEN>, occupancy_jobs<N, S, IN_T, OUT_T, GEN>, a, blocks, 1, lds);
+    record_job(launch_jobs<N, S, IN_T, OUT_T, GEN, MID>, occupancy_jobs<N, S, IN_T, OUT_T, GEN, MID>, a, blocks, 1, lds);
     return hipSuccess;
   }
   const dim3 grid((unsigned)blocks), block(threads<N>());
-  hipLaunchKernelGGL((k_fft_lines<N, S, IN_T, OUT_T, GEN>), grid, block, lds, s, a);
+  hipLaunchKernelGGL((k_fft_lines<N, S, IN_T, OUT_T, GEN, MID>), grid, block, lds, s, a);
   return hipGetLastError();
 }
 
 // mode 0: rows in, rows out (one pass); 1: interleaved in and out (pass 1); 2: rows in,
-// interleaved out (pass 2).  gen: the input is computed by the band generator (inverse
-// transforms of the real-mode path, modes 0 and 1).
+// interleaved out (pass 2); 3: as 2, then the filter product and the inverse transform's first
+// pass (forward direction only; the chirp convolution's middle).  gen: the input is computed by
+// the band generator (inverse transforms of the real-mode path, modes 0 and 1).
 template <int S>
 static hipError_t dispatch(int N, int mode, bool gen, const LinesArgs& a, hipStream_t s, bool prep) {
 #define MCI_FL(NN)                                                                                  \
   if (N == NN) {                                                                                    \
-    if (gen && S > 0 && mode == 0) return launch<NN, S, false, false, (S > 0)>(a, s, prep);         \
-    if (gen && S > 0 && mode == 1) return launch<NN, S, true, true, (S > 0)>(a, s, prep);           \
+    if (gen && S > 0 && mode == 0) return launch<NN, S, false, false, (S > 0), false>(a, s, prep);  \
+    if (gen && S > 0 && mode == 1) return launch<NN, S, true, true, (S > 0), false>(a, s, prep);    \
     if (gen) return hipErrorInvalidValue;                                                           \
-    if (mode == 0) return launch<NN, S, false, false, false>(a, s, prep);                           \
-    if (mode == 1) return launch<NN, S, true, true, false>(a, s, prep);                             \
-    return launch<NN, S, false, true, false>(a, s, prep);                                           \
+    if (mode == 0) return launch<NN, S, false, false, false, false>(a, s, prep);                    \
+    if (mode == 1) return launch<NN, S, true, true, false, false>(a, s, prep);                      \
+    if (mode == 3) return S < 0 ? launch<NN, S, false, true, false, (S < 0)>(a, s, prep)            \
+                                : hipErrorInvalidValue;                                             \
+    return launch<NN, S, false, true, false, false>(a, s, prep);                                    \
   }
   MCI_FL(32) MCI_FL(48) MCI_FL(64) MCI_FL(96) MCI_FL(128) MCI_FL(192) MCI_FL(256) MCI_FL(384) MCI_FL(512)
 #undef MCI_FL
@@ -334,6 +347,7 @@ hipError_t prepare_two_pass(int A, int B) {
       if ((e = fl::run(B, S, 1, fl::LinesArgs{}, nullptr, true)) != hipSuccess) return e;
       if (S > 0 && (e = fl::run(B, S, 1, fl::LinesArgs{}, nullptr, true, true)) != hipSuccess) return e;
       e = fl::run(A, S, 2, fl::LinesArgs{}, nullptr, true);
+      if (e == hipSuccess && S < 0) e = fl::run(A, S, 3, fl::LinesArgs{}, nullptr, true);
     }
     if (e != hipSuccess) return e;
   }
@@ -364,6 +378,34 @@ hipError_t fft_lines(const LineXform& x, hipStream_t s) {
   fl::LinesArgs p2{x.tmp, x.out, x.count * B, B, dense, so, A, 1, 1, B, x.twA, nullptr, nullptr, 0, x.post, 0, 0,
                    x.out_half, BandGen{}};
   return fl::run(A, x.sign, 2, p2, s, false);
+}
+
+hipError_t fft_chirp_conv(const LineXform& x, const float2* filt, float2* mid, hipStream_t s) {
+  if (x.count <= 0) return hipSuccess;
+  const int A = x.A, B = x.B;
+  if (A == 1 || x.sign > 0 || x.gen || x.out_half) return hipErrorInvalidValue;
+  fl::Side si, so;
+  si.offs = x.in_offs; si.side = 0; si.div = x.real_in ? 1 : 2; si.per = x.in_per; si.sig = x.in_sig; si.tr = x.in_tr;
+  so.offs = x.out_offs; so.side = 1; so.per = x.out_per; so.sig = x.out_sig; so.tr = x.out_tr;
+  const int64_t L = (int64_t)A * B;
+  fl::Side dense;
+  dense.per = 1; dense.sig = L;
+  // forward pass 1: A lines x[a + A b] of length B (x.pre applied as they load), twiddled, to tmp[k_b A + a]
+  fl::LinesArgs p1{x.in, x.tmp, x.count * A, A, si, dense, 1, A, 1, A, x.twB, x.twL, x.pre, x.len_in, nullptr,
+                   x.real_in, x.in_half, 0, BandGen{}};
+  hipError_t e = fl::run(B, -1, 1, p1, s, false);
+  if (e != hipSuccess) return e;
+  // the middle: B contiguous lines tmp[k_b A + a] of length A, transformed (the forward
+  // spectrum at k_b + B k_a), times filt there, inverse-transformed along the same line (the
+  // inverse's first pass, factors B x A), twiddled by w_L^{+k_b k'}, to mid[k' B + k_b]
+  fl::LinesArgs pm{x.tmp, mid, x.count * B, B, dense, dense, A, 1, 1, B, x.twA, x.twL, nullptr, 0, nullptr, 0, 0, 0,
+                   BandGen{}, filt};
+  if ((e = fl::run(A, -1, 3, pm, s, false)) != hipSuccess) return e;
+  // inverse pass 2: A contiguous lines mid[k' B + a'] of length B, to out[k' + A k_a'] (x.post
+  // applied as they store)
+  fl::LinesArgs p2{mid, x.out, x.count * A, A, dense, so, B, 1, 1, A, x.twB, nullptr, nullptr, 0, x.post, 0, 0, 0,
+                   BandGen{}};
+  return fl::run(B, +1, 2, p2, s, false);
 }
 
 hipError_t fft_two_pass(const float2* in, float2* out, float2* tmp, int64_t count, int A, int B, int sign,

@@ -4,8 +4,9 @@
 //  1. channel DFTs (Lemma 3.1): row m of the real samples, read as H = N/2 complex pairs
 //     z[p] = g[2p] + i g[2p+1] (odd N: as N real values), goes through a one- or two-pass
 //     transform of length H (N) (through Bluestein's chirp convolution when that length does
-//     not factor: the chirp is applied as the first pass loads, the filter spectrum as the
-//     second one stores, and the output chirp as the inverse transform's last pass stores);
+//     not factor: the chirp is applied as the first pass loads, the filter spectrum between the
+//     forward transform's last pass and the inverse's first, which share one kernel for two-pass
+//     lengths, and the output chirp as the inverse transform's last pass stores);
 //  2. apply (eq. matrixeqn1) and the real part: X_m[r] = E[r'] + e^{-2 pi i r / N} O[r'],
 //     r' = r mod H, with E, O the even/odd-sample DFTs recovered from Z (odd N: X_m = Z);
 //     a(k) = sum_m X_m[k mod N] Tab[m][j][i] for k = n1 + i + jN; S(k) = (a(k) + conj a(-k)) / 2;
@@ -34,7 +35,9 @@ size_t real_path_workspace(const RealPath& r, int64_t batch) {
   if (batch <= 0) return 0;
   const size_t nz = (size_t)batch * r.M * r.fwd->lexec * sizeof(float2);
   const size_t nc = (size_t)batch * r.n_ops * r.P * sizeof(float2);
-  return 2 * al(nz) + al(nc) + 256;
+  // the third region is the output transform's scratch, and the chirp convolution's middle
+  // result before it
+  return 2 * al(nz) + al(r.fwd->blue ? std::max(nz, nc) : nc) + 256;
 }
 
 hipError_t run_real_1d(const RealPath& r, const void* g, void* y, int64_t batch, void* ws, const int64_t* offs,
@@ -62,20 +65,28 @@ hipError_t run_real_1d(const RealPath& r, const void* g, void* y, int64_t batch,
   x.in_half = r.f16;
   x.len_in = L_in;
   x.out_sig = Lz;
-  if (f.blue) {
+  hipError_t e;
+  if (f.blue && f.fa > 1) {
+    // the chirp convolution in three passes, Zf = chirp * IDFT(DFT(chirp * z) * bhat), its
+    // middle result in T2 (free until the output transform)
     x.pre = (const float2*)f.chirp;
-    x.post = (const float2*)f.bhat;
-  }
-  hipError_t e = fft_lines(x, s);
-  if (e != hipSuccess) return e;
-  if (f.blue) {
-    LineXform u;
-    u.in = Zf; u.out = Zf; u.tmp = T1; u.count = batch * r.M;
-    u.A = f.fa; u.B = f.fb; u.sign = +1;
-    u.twA = (const float2*)f.twA; u.twB = (const float2*)f.twB; u.twL = (const float2*)f.twL;
-    u.in_sig = u.out_sig = Lz;
-    u.post = (const float2*)f.chirp;   // the output chirp, applied as the last pass stores
-    if ((e = fft_lines(u, s)) != hipSuccess) return e;
+    x.post = (const float2*)f.chirp;
+    if ((e = fft_chirp_conv(x, (const float2*)f.bhat, T2, s)) != hipSuccess) return e;
+  } else {
+    if (f.blue) {
+      x.pre = (const float2*)f.chirp;
+      x.post = (const float2*)f.bhat;
+    }
+    if ((e = fft_lines(x, s)) != hipSuccess) return e;
+    if (f.blue) {
+      LineXform u;
+      u.in = Zf; u.out = Zf; u.tmp = T1; u.count = batch * r.M;
+      u.A = f.fa; u.B = f.fb; u.sign = +1;
+      u.twA = (const float2*)f.twA; u.twB = (const float2*)f.twB; u.twL = (const float2*)f.twL;
+      u.in_sig = u.out_sig = Lz;
+      u.post = (const float2*)f.chirp;   // the output chirp, applied as the last pass stores
+      if ((e = fft_lines(u, s)) != hipSuccess) return e;
+    }
   }
   // 2-3. one inverse transform of length P per (signal, op), written as the output row; its
   //    first pass computes its input, the gathered spectrum Zc, from the channel spectra as
