@@ -100,8 +100,12 @@ __device__ __forceinline__ void dft_r(float2* u) {
 #pragma unroll
       for (int s = 1; s < 4; ++s) {
         const int m = q * s;
-        const float wc = cs[m], ws = (float)S * sn[m];
         const float2 x = a[q + 4 * s];
+        if (m == 4) {   // e^{S i pi / 2} = S i: a swap and a sign, no products
+          a[q + 4 * s] = cmul_si<S>(x);
+          continue;
+        }
+        const float wc = cs[m], ws = (float)S * sn[m];
         a[q + 4 * s] = make_float2(x.x * wc - x.y * ws, x.x * ws + x.y * wc);
       }
 #pragma unroll
@@ -359,6 +363,15 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, int64_t sig_index
             for (int m = 0; m < M; ++m) v[m][c] = cmul(v[m][c], ch);
           }
         }
+      }
+      if constexpr (BLUE == 2) {
+        // the split form has H + ceil(H / 2) - 1 <= PF, so H <= (2 PF + 2) / 3: the slots from
+        // CZ on hold no sample, and the first pass may know it
+        constexpr int CZ = ((2 * PF + 2) / 3 + NT - 1) / NT;
+#pragma unroll
+        for (int c = CZ; c < EF; ++c)
+#pragma unroll
+          for (int m = 0; m < M; ++m) v[m][c] = make_float2(0.f, 0.f);
       }
       // the split form's kernel spectra, loaded here so that the loads overlap the transform
       float2 bh[BLUE == 2 ? 2 : 1][EF];

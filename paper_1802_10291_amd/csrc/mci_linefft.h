@@ -38,8 +38,12 @@ __device__ __forceinline__ void dft_r(float2* u) {
 #pragma unroll
       for (int s = 1; s < 4; ++s) {
         const int m = q * s;
-        const float wc = cs[m], ws = (float)S * sn[m];
         const float2 x = a[q + 4 * s];
+        if (m == 4) {   // e^{S i pi / 2} = S i: a swap and a sign, no products
+          a[q + 4 * s] = cmul_si<S>(x);
+          continue;
+        }
+        const float wc = cs[m], ws = (float)S * sn[m];
         a[q + 4 * s] = make_float2(x.x * wc - x.y * ws, x.x * ws + x.y * wc);
       }
 #pragma unroll
