@@ -251,6 +251,7 @@ __device__ __forceinline__ void fft_passes(float2* __restrict__ lds, float2 (&v)
 }
 
 template <int L> struct Radices;
+template <> struct Radices<512> { using type = RList<2, 2, 2, 2, 2, 2, 2, 2, 2>; };   // 2 elements per thread
 template <> struct Radices<1024> { using type = RList<4, 4, 4, 4, 4>; };
 template <> struct Radices<2048> { using type = RList<8, 8, 8, 4>; };
 template <> struct Radices<4096> { using type = RList<16, 16, 16>; };
@@ -757,6 +758,9 @@ static const Variant kVariants[] = {
     MCI_FV(2048, 1, 4096, 4), MCI_FV(1024, 1, 4096, 4), MCI_FV(1024, 0, 4096, 4),
     MCI_FV(2048, 0, 4096, 4), MCI_FV(2048, 1, 2048, 4), MCI_FV(1024, 0, 1024, 4),
     MCI_FV(2048, 0, 2048, 4), MCI_FV(1024, 2, 4096, 4),
+    // 512-point channel transforms (two elements per thread, radix-2 passes): H = 512 with
+    // 8192- and 16384-point outputs, Bluestein for H <= 256 with 4096-point outputs
+    MCI_FV(512, 0, 4096, 4), MCI_FV(512, 0, 2048, 4), MCI_FV(512, 1, 1024, 4),
 };
 #undef MCI_FV
 

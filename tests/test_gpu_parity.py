@@ -234,6 +234,10 @@ FUSED = [
     (1000, 16384, [("deriv", 0), ("deriv", 1), ("deriv", 2)], 100),     # band not containing 0
     (1100, 16384, [("deriv", 0), ("deriv", 1), ("deriv", 2)], None),    # split Bluestein, H = 550
     (1200, 16384, [("deriv", 0)], None),                                # split Bluestein, M = 1, H = 600
+    (1024, 16384, [("deriv", 0), ("deriv", 1), ("deriv", 2), ("deriv", 3)], None),  # 512-point forward, M = 4
+    (1024, 8192, [("deriv", 0), ("deriv", 1)], None),                   # 512-point forward, P = 2048
+    (342, 4096, [("deriv", 0), ("deriv", 1), ("deriv", 2)], None),      # Bluestein at 512 (H = 171), P = 1024
+    (300, 4096, [("deriv", 0), ("deriv", 1)], -20),                     # Bluestein at 512 (H = 150), shifted band
 ]
 
 
