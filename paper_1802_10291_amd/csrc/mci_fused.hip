@@ -83,6 +83,7 @@ __device__ __forceinline__ void dft_r(float2* u) {
   if constexpr (R == 2) dft2<S>(u[0], u[1]);
   else if constexpr (R == 4) dft4<S>(u[0], u[1], u[2], u[3]);
   else if constexpr (R == 8) dft8<S>(u);
+  else if constexpr (R == 12) dft12<S>(u);
   else {
     static_assert(R == 16, "radix");
     // 16 = 4 x 4: DFT4 over each stride-4 group, twiddles e^{S 2 pi i q s / 16}, DFT4 across
@@ -123,12 +124,12 @@ template <int R0, int... Rs> struct RList<R0, Rs...> { static constexpr int firs
 // Base twiddles of a pass, loaded before the exchange that precedes it so that the load
 // overlaps the barrier waits (at most 2 butterflies per thread for the radices used here).
 struct PassTw {
-  float2 w1[2], w4[2];
+  float2 w1[3], w4[3];
 };
 template <int L, int NS, int R>
 __device__ __forceinline__ PassTw load_pass_tw(const float2* __restrict__ tw) {
   constexpr int BPT = (L / NT) / R;
-  static_assert(BPT <= 2, "prefetch holds two butterflies");
+  static_assert(BPT <= 3, "prefetch holds three butterflies");
   PassTw p;
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
@@ -255,6 +256,9 @@ template <> struct Radices<512> { using type = RList<2, 2, 2, 2, 2, 2, 2, 2, 2>;
 template <> struct Radices<1024> { using type = RList<4, 4, 4, 4, 4>; };
 template <> struct Radices<2048> { using type = RList<8, 8, 8, 4>; };
 template <> struct Radices<4096> { using type = RList<16, 16, 16>; };
+// 12 elements per thread; the radix-12 (3 x 4 prime-factor) pass comes last, so every exchange
+// is between power-of-two passes (the LDS padding's address arithmetic relies on that)
+template <> struct Radices<3072> { using type = RList<4, 4, 4, 4, 12>; };
 
 template <int L, int S, int T>
 __device__ __forceinline__ void fft(float2* lds, float2 (&v)[T][L / NT], const float2* tw) {
@@ -761,6 +765,8 @@ static const Variant kVariants[] = {
     // 512-point channel transforms (two elements per thread, radix-2 passes): H = 512 with
     // 8192- and 16384-point outputs, Bluestein for H <= 256 with 4096-point outputs
     MCI_FV(512, 0, 4096, 4), MCI_FV(512, 0, 2048, 4), MCI_FV(512, 1, 1024, 4),
+    // 12288-point outputs (P = 3072 = 4^4 x 12)
+    MCI_FV(512, 0, 3072, 4), MCI_FV(1024, 1, 3072, 4), MCI_FV(2048, 1, 3072, 4),
 };
 #undef MCI_FV
 

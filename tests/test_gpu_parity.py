@@ -238,6 +238,9 @@ FUSED = [
     (1024, 8192, [("deriv", 0), ("deriv", 1)], None),                   # 512-point forward, P = 2048
     (342, 4096, [("deriv", 0), ("deriv", 1), ("deriv", 2)], None),      # Bluestein at 512 (H = 171), P = 1024
     (300, 4096, [("deriv", 0), ("deriv", 1)], -20),                     # Bluestein at 512 (H = 150), shifted band
+    (1024, 12288, [("deriv", 0), ("deriv", 1), ("deriv", 2)], None),    # 3072-point output (radix 12 last)
+    (768, 12288, [("deriv", 0), ("deriv", 1), ("deriv", 2), ("deriv", 3)], None),  # Bluestein 1024, P = 3072
+    (1536, 12288, [("deriv", 0), ("deriv", 1)], -1500),                 # Bluestein 2048, P = 3072, shifted band
 ]
 
 
