@@ -700,7 +700,8 @@ static hipError_t prep_m(const int* lds_ti) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds_ti[0]);
     if (e != hipSuccess) return e;
   }
-  if (lds_ti[1] > 64 * 1024) {
+  if constexpr (Q < 4) return hipSuccess;   // one output transform: no side-by-side form
+  else if (lds_ti[1] > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_mci1d_fused<PF, BLUE, P, Q, M, 2, TS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_ti[1]);
     if (e != hipSuccess) return e;
@@ -724,11 +725,13 @@ static hipError_t prep_t(int M, int store, const int* lds_ti) {
 template <int PF, int BLUE, int P, int Q, int M>
 static hipError_t launch_m(const FusedPlan& fp, const void* g, void* y, int64_t batch, const int64_t* offs,
                            hipStream_t s) {
-  if (fp.store == ST_F16) {
-    if (fp.ti == 2) return launch_mt<PF, BLUE, P, Q, M, 2, __half>(fp, g, y, batch, offs, s);
-    return launch_mt<PF, BLUE, P, Q, M, 1, __half>(fp, g, y, batch, offs, s);
+  if constexpr (Q >= 4) {
+    if (fp.ti == 2) {
+      if (fp.store == ST_F16) return launch_mt<PF, BLUE, P, Q, M, 2, __half>(fp, g, y, batch, offs, s);
+      return launch_mt<PF, BLUE, P, Q, M, 2, float>(fp, g, y, batch, offs, s);
+    }
   }
-  if (fp.ti == 2) return launch_mt<PF, BLUE, P, Q, M, 2, float>(fp, g, y, batch, offs, s);
+  if (fp.store == ST_F16) return launch_mt<PF, BLUE, P, Q, M, 1, __half>(fp, g, y, batch, offs, s);
   return launch_mt<PF, BLUE, P, Q, M, 1, float>(fp, g, y, batch, offs, s);
 }
 
@@ -767,10 +770,12 @@ static const Variant kVariants[] = {
     MCI_FV(512, 0, 4096, 4), MCI_FV(512, 0, 2048, 4), MCI_FV(512, 1, 1024, 4),
     // 12288-point outputs (P = 3072 = 4^4 x 12)
     MCI_FV(512, 0, 3072, 4), MCI_FV(1024, 1, 3072, 4), MCI_FV(2048, 1, 3072, 4),
+    // Bluestein at 512 for H <= 256 (power-of-two H included) with 8192-point outputs, and one
+    // output transform (Q = 2: y[2q] + i y[2q + 1]) for 2048- and 6144-point outputs
+    MCI_FV(512, 1, 2048, 4), MCI_FV(512, 1, 1024, 2), MCI_FV(512, 1, 3072, 2), MCI_FV(1024, 1, 3072, 2),
 };
 #undef MCI_FV
 
-static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void* tab, FusedPlan& fp) {
   fp.kind = 0;
@@ -782,9 +787,11 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   const int64_t K = std::max<int64_t>(std::llabs(n1), std::llabs(n1 + mu - 1));
   const Variant* pick = nullptr;
   for (const Variant& v : kVariants) {
+    // (a power-of-two H also takes Bluestein where no plain form fits: the smallest PF wins,
+    // and the plain form, PF = H, is always smaller than a chirp convolution's)
     const bool fwd_ok = v.blue == 0 ? H == v.PF
-                : v.blue == 1 ? (2 * H - 1 <= v.PF && !is_pow2(H))
-                              : (H + (H + 1) / 2 - 1 <= v.PF && !is_pow2(H));
+                : v.blue == 1 ? 2 * H - 1 <= v.PF
+                              : H + (H + 1) / 2 - 1 <= v.PF;
     if (!fwd_ok || (int64_t)v.P * v.Q != d.n_out) continue;
     if (!pick || v.PF < pick->PF) pick = &v;
   }
@@ -801,7 +808,7 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   for (int t = 0; t < 2; ++t)
     lds_ti[t] = (int64_t)fused_slots(pick->PF, pick->P, t + 1, pick->Q, (int)M, (int)H, (int)K) * (int64_t)sizeof(float2);
   if (lds_ti[0] > max_lds) return MCI_OK;
-  const int n_ti = lds_ti[1] <= max_lds ? 2 : 1;
+  const int n_ti = pick->Q >= 4 && lds_ti[1] <= max_lds ? 2 : 1;
   {
     const int lt[2] = {(int)lds_ti[0], n_ti == 2 ? (int)lds_ti[1] : 0};
     if (pick->prep((int)M, store, lt) != hipSuccess) return MCI_OK;   // no fused kernel then

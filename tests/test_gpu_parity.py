@@ -241,6 +241,10 @@ FUSED = [
     (1024, 12288, [("deriv", 0), ("deriv", 1), ("deriv", 2)], None),    # 3072-point output (radix 12 last)
     (768, 12288, [("deriv", 0), ("deriv", 1), ("deriv", 2), ("deriv", 3)], None),  # Bluestein 1024, P = 3072
     (1536, 12288, [("deriv", 0), ("deriv", 1)], -1500),                 # Bluestein 2048, P = 3072, shifted band
+    (512, 8192, [("deriv", 0), ("deriv", 1), ("deriv", 2), ("deriv", 3)], None),  # power-of-two H = 256 by Bluestein
+    (256, 2048, [("deriv", 0), ("deriv", 1)], None),                    # one output transform (Q = 2), P = 1024
+    (768, 6144, [("deriv", 0), ("deriv", 1)], None),                    # Q = 2, P = 3072, Bluestein 1024
+    (384, 6144, [("deriv", 0), ("hilbert", 0)], None),                  # Q = 2, P = 3072, Hilbert channel
 ]
 
 
