@@ -81,6 +81,7 @@ static_assert(NT % 16 == 0, "pad(tid + NT c) = pad(tid) + c (NT + NT / 16) needs
 template <int R, int S>
 __device__ __forceinline__ void dft_r(float2* u) {
   if constexpr (R == 2) dft2<S>(u[0], u[1]);
+  else if constexpr (R == 3) dft3<S>(u[0], u[1], u[2]);
   else if constexpr (R == 4) dft4<S>(u[0], u[1], u[2], u[3]);
   else if constexpr (R == 8) dft8<S>(u);
   else if constexpr (R == 12) dft12<S>(u);
@@ -174,10 +175,8 @@ __device__ __forceinline__ void fft_passes(float2* __restrict__ lds, float2 (&v)
       }
       float2 wl[4];
       wl[1] = w1;
-      if constexpr (R >= 4) {
-        wl[2] = cmul(w1, w1);
-        wl[3] = cmul(wl[2], w1);
-      }
+      if constexpr (R >= 3) wl[2] = cmul(w1, w1);
+      if constexpr (R >= 4) wl[3] = cmul(wl[2], w1);
 #pragma unroll
       for (int r = 1; r < (R < 4 ? R : 4); ++r)
 #pragma unroll
@@ -259,6 +258,8 @@ template <> struct Radices<4096> { using type = RList<16, 16, 16>; };
 // 12 elements per thread; the radix-12 (3 x 4 prime-factor) pass comes last, so every exchange
 // is between power-of-two passes (the LDS padding's address arithmetic relies on that)
 template <> struct Radices<3072> { using type = RList<4, 4, 4, 4, 12>; };
+// 6 elements per thread: nine radix-2 passes, then radix 3
+template <> struct Radices<1536> { using type = RList<2, 2, 2, 2, 2, 2, 2, 2, 2, 3>; };
 
 template <int L, int S, int T>
 __device__ __forceinline__ void fft(float2* lds, float2 (&v)[T][L / NT], const float2* tw) {
@@ -773,6 +774,8 @@ static const Variant kVariants[] = {
     // Bluestein at 512 for H <= 256 (power-of-two H included) with 8192-point outputs, and one
     // output transform (Q = 2: y[2q] + i y[2q + 1]) for 2048- and 6144-point outputs
     MCI_FV(512, 1, 2048, 4), MCI_FV(512, 1, 1024, 2), MCI_FV(512, 1, 3072, 2), MCI_FV(1024, 1, 3072, 2),
+    // 1024- and 3072-point outputs as one transform of 512 or 1536 points
+    MCI_FV(512, 1, 512, 2), MCI_FV(512, 1, 1536, 2),
 };
 #undef MCI_FV
 

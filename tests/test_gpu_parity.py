@@ -245,6 +245,9 @@ FUSED = [
     (256, 2048, [("deriv", 0), ("deriv", 1)], None),                    # one output transform (Q = 2), P = 1024
     (768, 6144, [("deriv", 0), ("deriv", 1)], None),                    # Q = 2, P = 3072, Bluestein 1024
     (384, 6144, [("deriv", 0), ("hilbert", 0)], None),                  # Q = 2, P = 3072, Hilbert channel
+    (86, 1024, [("deriv", 0), ("deriv", 1), ("deriv", 2)], None),       # Q = 2, P = 512 (H = 43)
+    (192, 3072, [("deriv", 0), ("deriv", 1), ("deriv", 2), ("deriv", 3)], None),  # Q = 2, P = 1536 (radix 3 last)
+    (384, 3072, [("deriv", 0), ("deriv", 1)], -300),                    # Q = 2, P = 1536, shifted band
 ]
 
 
