@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <new>
 #include <string>
 #include <vector>
@@ -97,53 +98,66 @@ __global__ __launch_bounds__(NT) void k_weights(EvalArgs a) {
   for (int k = 0; k < a.w; ++k) ((T*)a.wt)[k * a.n_t + j] = es_weight<T>((T)(x0 + k * step), (T)a.beta);
 }
 
-// Shared points, rows that fit the LDS: one workgroup per output row (signal b, operator op)
-// copies the row's grid into LDS with coalesced loads, then every thread evaluates points
-// j = tid, tid + NG, ... from the table.
+// Shared points, rows that fit the LDS: one workgroup per RR output rows (signal b, operator op)
+// copies the rows' grids into LDS with coalesced loads, then every thread evaluates points
+// j = tid, tid + NG, ... from the table.  The table (start and W weights per point, shared by
+// every row) is what the gather reads most; taking RR = 2 rows per workgroup reads it once for
+// both (the two 64 KB FP32 rows of the 16384-point grids fit the LDS together).
 constexpr int NG = 512;
 
-template <typename T, bool REAL, int W>
-__global__ __launch_bounds__(NG) void k_gather_lds(EvalArgs a) {
+template <int RR> constexpr int gather_threads() { return RR * NG; }   // one LDS-resident workgroup per CU at RR = 2
+
+template <typename T, bool REAL, int W, int RR>
+__global__ __launch_bounds__(gather_threads<RR>()) void k_gather_lds(EvalArgs a) {
+  constexpr int NTG = gather_threads<RR>();
   extern __shared__ __align__(16) unsigned char lds_raw[];
   using V = typename std::conditional<REAL, T, typename std::conditional<sizeof(T) == 4, float2, double2>::type>::type;
-  V* row = (V*)lds_raw;
-  const int64_t r = blockIdx.x;
+  V* rows = (V*)lds_raw;
   const int64_t L = a.L;
+  const int64_t r0 = (int64_t)blockIdx.x * RR;
+  const int64_t n_rows = a.batch * a.n_ops;
+  const int nr = (int)(n_rows - r0 < RR ? n_rows - r0 : RR);
   {
     // 16-byte copies: a row is L sizeof(V) bytes, a multiple of 16 (L is a power of two >= 32)
-    // the row is read once (non-temporal), leaving L2 to the shared weight table
+    // the rows are read once (non-temporal), leaving L2 to the shared weight table
     typedef unsigned u4_nt __attribute__((ext_vector_type(4)));
-    const u4_nt* src = (const u4_nt*)((const V*)a.grid + r * L);
-    u4_nt* dst = (u4_nt*)row;
-    const int64_t n16 = L * (int64_t)sizeof(V) / 16;
-    for (int64_t q = threadIdx.x; q < n16; q += NG) dst[q] = __builtin_nontemporal_load(src + q);
+    const u4_nt* src = (const u4_nt*)((const V*)a.grid + r0 * L);
+    u4_nt* dst = (u4_nt*)rows;
+    const int64_t n16 = nr * L * (int64_t)sizeof(V) / 16;
+    for (int64_t q = threadIdx.x; q < n16; q += NTG) dst[q] = __builtin_nontemporal_load(src + q);
   }
   __syncthreads();
   const T* wt = (const T*)a.wt;
   const int mask = (int)(L - 1);
   // the table loads of a point (start and W weights) are independent: with W fixed at
   // compile time they issue back to back and share one wait
-  for (int64_t j = threadIdx.x; j < a.n_t; j += NG) {
+  for (int64_t j = threadIdx.x; j < a.n_t; j += NTG) {
     const int s0 = a.start[j];
     T c[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) c[k] = wt[k * a.n_t + j];
-    if constexpr (REAL) {
-      T acc = T(0);
 #pragma unroll
-      for (int k = 0; k < W; ++k) acc += c[k] * row[(s0 + k) & mask];
-      __builtin_nontemporal_store(acc, (T*)a.y + r * a.n_t + j);
-    } else {
-      T re = T(0), im = T(0);
+    for (int rr = 0; rr < RR; ++rr) {
+      if (rr >= nr) break;
+      const V* row = rows + rr * L;
+      const int64_t r = r0 + rr;
+      if constexpr (REAL) {
+        T acc = T(0);
 #pragma unroll
-      for (int k = 0; k < W; ++k) {
-        const V g = row[(s0 + k) & mask];
-        re += c[k] * g.x;
-        im += c[k] * g.y;
+        for (int k = 0; k < W; ++k) acc += c[k] * row[(s0 + k) & mask];
+        __builtin_nontemporal_store(acc, (T*)a.y + r * a.n_t + j);
+      } else {
+        T re = T(0), im = T(0);
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          const V g = row[(s0 + k) & mask];
+          re += c[k] * g.x;
+          im += c[k] * g.y;
+        }
+        T* y = (T*)a.y + 2 * (r * a.n_t + j);
+        __builtin_nontemporal_store(re, y);
+        __builtin_nontemporal_store(im, y + 1);
       }
-      T* y = (T*)a.y + 2 * (r * a.n_t + j);
-      __builtin_nontemporal_store(re, y);
-      __builtin_nontemporal_store(im, y + 1);
     }
   }
 }
@@ -194,6 +208,30 @@ __global__ __launch_bounds__(NT) void k_gather(EvalArgs a) {
   }
 }
 
+// dynamic LDS of the two-row gather (its limit is raised at plan time)
+constexpr size_t kGatherLds2 = 128 * 1024;
+
+template <typename T, bool REAL, int W>
+static hipError_t prep_gather_w() {
+  return hipFuncSetAttribute((const void*)k_gather_lds<T, REAL, W, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kGatherLds2);
+}
+template <typename T, bool REAL>
+static hipError_t prep_gather_t(int w) {
+  switch (w) {
+#define MCI_OG_W(W) \
+  case W: return prep_gather_w<T, REAL, W>();
+    MCI_OG_W(2) MCI_OG_W(3) MCI_OG_W(4) MCI_OG_W(5) MCI_OG_W(6) MCI_OG_W(7) MCI_OG_W(8) MCI_OG_W(9)
+    MCI_OG_W(10) MCI_OG_W(11) MCI_OG_W(12) MCI_OG_W(13) MCI_OG_W(14) MCI_OG_W(15) MCI_OG_W(16)
+#undef MCI_OG_W
+    default: return hipErrorInvalidValue;
+  }
+}
+static hipError_t prep_gather(int prec, bool real, int w) {
+  if (prec == MCI_F64) return real ? prep_gather_t<double, true>(w) : prep_gather_t<double, false>(w);
+  return real ? prep_gather_t<float, true>(w) : prep_gather_t<float, false>(w);
+}
+
 template <typename T, bool REAL, int W>
 static hipError_t launch_eval_w(const EvalArgs& a, bool shared, hipStream_t s) {
   const int64_t gx = (a.n_t + NT - 1) / NT;
@@ -205,8 +243,13 @@ static hipError_t launch_eval_w(const EvalArgs& a, bool shared, hipStream_t s) {
   hipLaunchKernelGGL(k_weights<T>, dim3((unsigned)gx), dim3(NT), 0, s, a);
   const size_t row_bytes = (size_t)a.L * sizeof(T) * (REAL ? 1 : 2);
   const int64_t rows = a.batch * a.n_ops;
-  if (row_bytes <= 64 * 1024 && rows <= 0x7fffffff)
-    hipLaunchKernelGGL((k_gather_lds<T, REAL, W>), dim3((unsigned)rows), dim3(NG), row_bytes, s, a);
+  // (MCI_GATHER_ONE_ROW=1 keeps one row per workgroup, the form measured against)
+  static const bool one_row = std::getenv("MCI_GATHER_ONE_ROW") && std::getenv("MCI_GATHER_ONE_ROW")[0] == '1';
+  if (!one_row && 2 * row_bytes <= kGatherLds2 && rows >= 2 && rows <= 0x7fffffff)
+    hipLaunchKernelGGL((k_gather_lds<T, REAL, W, 2>), dim3((unsigned)((rows + 1) / 2)), dim3(gather_threads<2>()),
+                       2 * row_bytes, s, a);
+  else if (row_bytes <= 64 * 1024 && rows <= 0x7fffffff)
+    hipLaunchKernelGGL((k_gather_lds<T, REAL, W, 1>), dim3((unsigned)rows), dim3(gather_threads<1>()), row_bytes, s, a);
   else
     hipLaunchKernelGGL((k_gather<T, REAL, true, W>), g2, dim3(NT), 0, s, a);
   return hipGetLastError();
@@ -316,6 +359,11 @@ mci_status mci_offgrid_plan(const mci_plan_desc* desc, int32_t width, int device
   p->device = device;
   p->prec = desc->precision;
   p->real_io = desc->real_io ? 1 : 0;
+  if (prep_gather(p->prec, p->real_io != 0, w) != hipSuccess) {
+    (void)mci_plan_destroy(gp);
+    delete p;
+    return fail(MCI_E_DEVICE, "gather LDS attribute");
+  }
   p->n_ops = desc->n_ops;
   p->L = L;
   p->w = w;
