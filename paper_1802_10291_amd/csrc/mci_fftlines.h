@@ -20,7 +20,7 @@ inline int64_t fl_twiddle_entries(int64_t L) { return kTwLo + (L + kTwLo - 1) / 
 
 // a line length of the register-staged line FFT: 32, 48, 64, 96, 128, 192, 256, 384, 512
 bool line_length_ok(int64_t n);
-// L = A B with A, B line lengths (most balanced), or A = 1 and B = L for a line length
+// L = A B with A, B line lengths (most balanced, the larger A among equals), or A = 1 and B = L for a line length
 bool two_pass_factors(int64_t L, int& A, int& B);
 // smallest length >= n that two_pass_factors accepts, or -1
 int64_t next_two_pass_length(int64_t n);

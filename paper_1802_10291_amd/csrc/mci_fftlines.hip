@@ -315,10 +315,14 @@ bool two_pass_factors(int64_t L, int& A, int& B) {
   }
   A = B = 0;
   double best = 1e30;
+  // between equally balanced factorisations the longer second pass (shorter first-pass lines)
+  // wins: the first pass carries the twiddles and, in the real-mode path, the band generation,
+  // and its smaller workgroups hide their latency better (an output transform of 131072 points
+  // as 512 x 256 instead of 256 x 512: 0.204 -> 0.190 ms for its class, 65536 samples and M = 3)
   for (int a : {32, 48, 64, 96, 128, 192, 256, 384, 512}) {
     if (L % a || !line_length_ok(L / a)) continue;
     const double bal = std::fabs(std::log((double)a) - std::log((double)(L / a)));
-    if (bal < best) {
+    if (bal < best + 1e-9) {
       best = bal;
       A = a;
       B = (int)(L / a);
