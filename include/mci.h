@@ -421,7 +421,10 @@ mci_status mci_refiner_load_state(mci_refiner_t r, const void* host, size_t len)
 mci_status mci_refiner_workspace_size(int64_t batch, int h, int w, size_t* bytes);
 /* y = u + CNN(u).  With ratio != NULL, ratio[b] = ||y_b - u_b|| / ||u_b|| (device, [batch]);
  * with apply_fallback, images whose ratio exceeds tau (or is NaN) are replaced by u and
- * used[b] (device int) records 1 for refined, 0 for fallback. */
+ * used[b] (device int) records 1 for refined, 0 for fallback.  Layers 2 and 3 run as one
+ * pass here (the layer-2 activations stay on chip), with results bit-identical to the
+ * layer-by-layer forward that training runs; MCI_REFINER_LAYERED=1 in the environment selects
+ * that layer-by-layer form instead. */
 mci_status mci_refiner_forward(mci_refiner_t r, const float* u, float* y, int64_t batch, int h, int w,
                                int apply_fallback, float* ratio, int* used, void* workspace, size_t ws_bytes,
                                hipStream_t stream);

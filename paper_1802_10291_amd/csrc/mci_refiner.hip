@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <random>
 #include <string>
@@ -267,6 +268,153 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
         *(bf16x8*)(out + o) = v;
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- two hidden layers in one pass
+// Inference form of layers 2 and 3 (conv 32 -> 32, ReLU, twice) on one 16 x 16 tile: layer 2
+// runs on the 18 x 18 region that layer 3's halo needs (324 pixels, flattened into 21 MFMA
+// row blocks of 16), its BF16 result stays in LDS (zero outside the image: layer 3's padding),
+// and only layer 3's output goes to memory.  Each output is accumulated in the same order as
+// by k_conv, and the intermediate is rounded to BF16 as k_conv stores it.
+constexpr int HT2 = T + 4;               // input tile side: the two layers' two-pixel halo
+constexpr int NP2 = HT * HT;             // layer-2 pixels
+constexpr int MB2 = (NP2 + 15) / 16;     // their 16-pixel row blocks
+constexpr int MW2 = (MB2 + 3) / 4;       // row blocks per wave (block m goes to wave m % 4)
+
+struct Conv23Args {
+  const bf16* in;                        // layer-1 activations [B][H][W][32]
+  const bf16* w2;                        // [32][9][32]
+  const float* b2;
+  const bf16* w3;
+  const float* b3;
+  bf16* out;                             // layer-3 activations [B][H][W][32]
+  int H, W;
+};
+
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_conv23(Conv23Args a) {
+  // the input tile [20 x 20][32]; layer 2's result [18 x 18][32] and the output staging reuse
+  // it once every wave is past the MFMAs that read it
+  __shared__ __attribute__((aligned(16))) bf16 tl[HT2 * HT2 * C];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tx0 = blockIdx.x * T, ty0 = blockIdx.y * T, b = blockIdx.z;
+  const int H = a.H, W = a.W;
+  const int px = lane & 15, kb = lane >> 4;
+  constexpr int NPRE = 4;   // weight taps loaded ahead, as in k_conv
+  bf16x8 bw[9][2];
+#pragma unroll
+  for (int tap = 0; tap < NPRE; ++tap)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) bw[tap][n] = *(const bf16x8*)(a.w2 + ((16 * n + px) * 9 + tap) * C + 8 * kb);
+  {
+    constexpr int CH = HT2 * HT2 * 4, IT = (CH + NT - 1) / NT;
+    const bf16* in = a.in + (size_t)b * H * W * C;
+    uint4 v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {            // 16-byte chunks: 4 per pixel
+      const int e = tid + NT * it;
+      const int pix = e >> 2, part = e & 3;
+      const int y = ty0 - 2 + pix / HT2, x = tx0 - 2 + pix % HT2;
+      v[it] = make_uint4(0, 0, 0, 0);
+      if (e < CH && y >= 0 && y < H && x >= 0 && x < W) v[it] = *(const uint4*)(in + ((size_t)y * W + x) * C + part * 8);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + NT * it;
+      if (e < CH) *(uint4*)(tl + (e >> 2) * C + (e & 3) * 8) = v[it];
+    }
+  }
+  __syncthreads();
+  // ---- layer 2 on the 18 x 18 region (region pixel p at (p / 18, p % 18), tile pixel (p / 18 - 1, p % 18 - 1))
+  f4 acc[MW2][2];
+  int abase[MW2];
+#pragma unroll
+  for (int j = 0; j < MW2; ++j) {
+    const int p = min(16 * (wave + 4 * j) + px, NP2 - 1);   // rows past the region compute a copy, unused
+    abase[j] = ((p / HT) * HT2 + p % HT) * C + 8 * kb;
+#pragma unroll
+    for (int n = 0; n < 2; ++n) acc[j][n] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    if (tap + NPRE < 9)
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+        bw[tap + NPRE][n] = *(const bf16x8*)(a.w2 + ((16 * n + px) * 9 + tap + NPRE) * C + 8 * kb);
+    const int off = ((tap / 3) * HT2 + tap % 3) * C;
+#pragma unroll
+    for (int j = 0; j < MW2; ++j) {
+      if (wave + 4 * j < MB2) {   // uniform per wave
+        const bf16x8 av = *(const bf16x8*)(tl + abase[j] + off);
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[j][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[tap][n], acc[j][n], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int tap = 0; tap < NPRE; ++tap)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) bw[tap][n] = *(const bf16x8*)(a.w3 + ((16 * n + px) * 9 + tap) * C + 8 * kb);
+  __syncthreads();   // every wave is done reading the input tile
+  // bias, ReLU, zero outside the image; D[pixel 4 kb + i of the block][channel px + 16 n]
+#pragma unroll
+  for (int j = 0; j < MW2; ++j) {
+    const int m = wave + 4 * j;
+    if (m >= MB2) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = 16 * m + 4 * kb + i;
+      if (p >= NP2) continue;
+      const int y = ty0 - 1 + p / HT, x = tx0 - 1 + p % HT;
+      const bool inside = y >= 0 && y < H && x >= 0 && x < W;
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+        tl[p * C + 16 * n + px] = tobf(inside ? fmaxf(acc[j][n][i] + a.b2[16 * n + px], 0.f) : 0.f);
+    }
+  }
+  __syncthreads();
+  // ---- layer 3: tile rows 4 wave .. 4 wave + 3, as k_conv's 32-channel path
+  f4 acc3[4][2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) acc3[m][n] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    if (tap + NPRE < 9)
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+        bw[tap + NPRE][n] = *(const bf16x8*)(a.w3 + ((16 * n + px) * 9 + tap + NPRE) * C + 8 * kb);
+    const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int row = 4 * wave + m;
+      const bf16x8 av = *(const bf16x8*)(tl + ((row + dy) * HT + (px + dx)) * C + 8 * kb);
+#pragma unroll
+      for (int n = 0; n < 2; ++n) acc3[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[tap][n], acc3[m][n], 0, 0, 0);
+    }
+  }
+  // ---- epilogue: two passes of 16 channels through the staging area, 16-byte stores
+  float* tout = (float*)tl;
+  bf16* out = a.out + (size_t)b * H * W * C;
+#pragma unroll
+  for (int n = 0; n < 2; ++n) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        tout[((4 * wave + m) * T + 4 * kb + i) * 16 + px] = fmaxf(acc3[m][n][i] + a.b3[16 * n + px], 0.f);
+    __syncthreads();
+    for (int e = tid; e < T * T * 2; e += NT) {          // 8 channels per chunk
+      const int pix = e >> 1, part = e & 1;
+      const int y = ty0 + pix / T, x = tx0 + pix % T;
+      if (y >= H || x >= W) continue;
+      bf16x8 v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = tobf(tout[pix * 16 + 8 * part + j]);
+      *(bf16x8*)(out + ((size_t)y * W + x) * C + 16 * n + 8 * part) = v;
     }
   }
 }
@@ -536,18 +684,25 @@ static hipError_t conv(int inm, int cout, int epi, const ConvArgs& a, int64_t B,
   return hipGetLastError();
 }
 
-// forward through the four layers; out = u + CNN(u)
+// forward through the four layers; out = u + CNN(u).  fused23: layers 2 and 3 in one pass
+// (inference: the layer-2 activations, which training reads back, are not stored)
 static hipError_t ref_forward(mci_refiner_s* r, const float* u, float* out, int64_t B, int H, int W, const RefWs& ws,
-                              hipStream_t s, float* rpart = nullptr) {
+                              hipStream_t s, float* rpart = nullptr, bool fused23 = false) {
   hipError_t e;
   ConvArgs a{};
   a.H = H; a.W = W;
   a.in = u; a.w = r->w + OF1; a.bias = r->p + B1; a.out = ws.a1;
   if ((e = conv(IN3, 32, EPI_RELU, a, B, s)) != hipSuccess) return e;
-  a.in = ws.a1; a.w = r->w + OF2; a.bias = r->p + B2; a.out = ws.a2;
-  if ((e = conv(IN32, 32, EPI_RELU, a, B, s)) != hipSuccess) return e;
-  a.in = ws.a2; a.w = r->w + OF3; a.bias = r->p + B3; a.out = ws.a3;
-  if ((e = conv(IN32, 32, EPI_RELU, a, B, s)) != hipSuccess) return e;
+  if (fused23) {
+    const Conv23Args c{ws.a1, r->w + OF2, r->p + B2, r->w + OF3, r->p + B3, ws.a3, H, W};
+    hipLaunchKernelGGL(k_conv23, dim3((W + T - 1) / T, (H + T - 1) / T, (unsigned)B), dim3(NT), 0, s, c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else {
+    a.in = ws.a1; a.w = r->w + OF2; a.bias = r->p + B2; a.out = ws.a2;
+    if ((e = conv(IN32, 32, EPI_RELU, a, B, s)) != hipSuccess) return e;
+    a.in = ws.a2; a.w = r->w + OF3; a.bias = r->p + B3; a.out = ws.a3;
+    if ((e = conv(IN32, 32, EPI_RELU, a, B, s)) != hipSuccess) return e;
+  }
   a.in = ws.a3; a.w = r->w + OF4; a.bias = r->p + B4; a.base = u; a.out = out; a.rpart = rpart;
   return conv(IN32, 16, EPI_RESID, a, B, s);
 }
@@ -761,7 +916,7 @@ mci_status mci_refiner_forward(mci_refiner_t r, const float* u, float* y, int64_
   RHIP(hipSetDevice(r->device));
   // the weight-gradient partials buffer (unused by a forward call) takes the ratio's
   // per-tile sums
-  RHIP(ref_forward(r, u, y, batch, h, w, ws, stream, ratio ? ws.part : nullptr));
+  RHIP(ref_forward(r, u, y, batch, h, w, ws, stream, ratio ? ws.part : nullptr, !std::getenv("MCI_REFINER_LAYERED")));
   if (ratio) {
     const int64_t per = 3 * (int64_t)h * w;
     const int tiles = ((h + T - 1) / T) * ((w + T - 1) / T);

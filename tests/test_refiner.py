@@ -310,10 +310,10 @@ def test_refiner_training_beats_plain_mci(torch_cuda):
 @pytest.mark.gpu
 @pytest.mark.parametrize("H,W", [(64, 48), (37, 50)])
 def test_forward_output_matches_training_loss(torch_cuda, H, W):
-    """The inference forward (with the ratio's per-tile sums in its last epilogue) and the
-    forward inside a training step run the same layer kernels, so the training loss equals
-    the squared error of the inference output (up to the order of the loss reduction), on
-    tiled and ragged image sizes."""
+    """The inference forward (with the ratio's per-tile sums in its last epilogue, and layers
+    2 and 3 in one pass) and the forward inside a training step (layer by layer) compute the
+    same values, so the training loss equals the squared error of the inference output (up
+    to the order of the loss reduction), on tiled and ragged image sizes."""
     from paper_1802_10291_amd import Refiner
     torch = torch_cuda
     rng = np.random.default_rng(H * W)
@@ -325,6 +325,30 @@ def test_forward_output_matches_training_loss(torch_cuda, H, W):
     loss = float(r.backward(u, hr))
     want = float(((y.double() - hr.double()) ** 2).mean())
     assert loss == pytest.approx(want, rel=1e-5)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("B,H,W", [(2, 32, 48), (3, 37, 50), (1, 5, 7), (2, 16, 16), (2, 512, 512)])
+def test_two_layer_pass_equals_layered_forward(torch_cuda, monkeypatch, B, H, W):
+    """The inference pass that runs layers 2 and 3 in one kernel (layer 2 on the 18 x 18
+    region of each tile, its BF16 result kept on chip) accumulates every output in the same
+    order as the layer-by-layer kernels and rounds the intermediate the same way: the outputs
+    and ratios are bit-identical, on ragged sizes, an image smaller than one tile and the
+    benchmark's 512 x 512."""
+    from paper_1802_10291_amd import Refiner
+    torch = torch_cuda
+    rng = np.random.default_rng(B * H * W)
+    r = Refiner(seed=4)
+    r.set_params(random_params(23).astype(np.float32))
+    u = torch.from_numpy(rng.uniform(size=(B, 3, H, W)).astype(np.float32)).cuda()
+    monkeypatch.delenv("MCI_REFINER_LAYERED", raising=False)
+    y1, ratio1, _ = r.forward(u)
+    y1 = y1.clone()
+    monkeypatch.setenv("MCI_REFINER_LAYERED", "1")
+    y2, ratio2, _ = r.forward(u)
+    assert torch.equal(y1, y2)
+    assert torch.equal(ratio1, ratio2)
+    assert (y1 - u).abs().max().item() > 0      # the network changed the image
 
 
 def test_training_images_recipe_on_cpu():
