@@ -161,6 +161,21 @@ mci_status mci_workspace_size(mci_plan_t plan, int64_t batch, size_t* bytes);
 mci_status mci_reconstruct_1d(mci_plan_t plan, const void* g, void* y, int64_t batch, void* workspace,
                               size_t ws_bytes, hipStream_t stream);
 
+/* mci_reconstruct_1d_strided -- mci_reconstruct_1d on signals spaced ld_g elements apart in g
+ * and ld_y elements apart in y (signal b's samples start at g + b ld_g, its outputs at
+ * y + b ld_y, each laid out as in mci_reconstruct_1d; elements of the storage type, a complex
+ * value counting two).  ld_g >= M N (x2 for complex), ld_y >= n_ops n_out (x2 for complex),
+ * both multiples of 4 (vector access); the output extents must not overlap.  The kernels and
+ * results are those of mci_reconstruct_1d, the signals found through a table of offsets that
+ * the call writes into the workspace (so it still allocates nothing and is graph-capturable):
+ * workspace / ws_bytes of at least mci_workspace_size_strided(plan, batch), 16-byte aligned.
+ * Errors: MCI_E_INVALID_ARG (strides, alignment, workspace), MCI_E_DEVICE. */
+mci_status mci_reconstruct_1d_strided(mci_plan_t plan, const void* g, int64_t ld_g, void* y, int64_t ld_y,
+                                      int64_t batch, void* workspace, size_t ws_bytes, hipStream_t stream);
+/* mci_workspace_size_strided -- device bytes mci_reconstruct_1d_strided needs for `batch`
+ * signals (1-D plans; 0 for batch = 0). */
+mci_status mci_workspace_size_strided(mci_plan_t plan, int64_t batch, size_t* bytes);
+
 /* ----------------------------------------------------------------------------------- */
 /* 2-D separable upsampling (Section 5.2): every row, then every column of the result,  */
 /* is reconstructed by MCI from two channels -- the line and its three-point centred     */

@@ -20,9 +20,25 @@ import numpy as np
 from . import _lib
 from ._lib import (  # noqa: F401  (the C-ABI names, re-exported)
     MCIError, mci_plan, mci_plan_destroy, mci_plan_info, mci_workspace_size, mci_reconstruct_1d, mci_plan_2d,
+    mci_reconstruct_1d_strided, mci_workspace_size_strided,
     mci_upsample_2d, mci_plan_variants, mci_plan_set_variant, mci_plan_autotune, mci_batch_create,
     mci_batch_destroy, mci_batch_sizes, mci_reconstruct_batch, VARIANT_NAMES,
 )
+
+def _batch_stride(t):
+    """Elements between consecutive items of t's first dimension when every item is
+    contiguous (None otherwise)."""
+    if t.dim() == 0:
+        return None
+    inner = 1
+    for d in t.shape[1:]:
+        inner *= d
+    if t.is_contiguous():
+        return inner
+    if t.shape[0] == 0 or not t[0].is_contiguous():
+        return None
+    return t.stride(0) if t.shape[0] > 1 else inner
+
 
 _KINDS = {"deriv": _lib.MCI_MULT_DERIV, "hilbert": _lib.MCI_MULT_HILBERT, "table": _lib.MCI_MULT_TABLE}
 _OPS = {"identity": _lib.MCI_OUT_IDENTITY, "hilbert": _lib.MCI_OUT_HILBERT, "deriv": _lib.MCI_OUT_DERIV}
@@ -162,22 +178,31 @@ class Plan1D(_Variants):
 
     def reconstruct(self, g, out=None):
         """g: cuda tensor [batch, M, N] (real) or [batch, M, N, 2] (complex, re/im).
-        Returns [batch, n_ops, n_out] (or [..., 2])."""
+        Returns [batch, n_ops, n_out] (or [..., 2]), or fills `out`.  Each signal of g and out
+        must be contiguous; the batch dimension may be strided (signals spaced a multiple of 4
+        elements apart, e.g. a slice of longer rows), which runs mci_reconstruct_1d_strided."""
         torch = _torch()
         if not g.is_cuda:
             raise ValueError("g must be a device tensor")
         tail = (self.M, self.N) if self.real else (self.M, self.N, 2)
-        if tuple(g.shape[1:]) != tail or g.dtype != self.io_dtype() or not g.is_contiguous():
-            raise ValueError(f"g must be contiguous {self.io_dtype()} [batch, {', '.join(map(str, tail))}]")
+        if tuple(g.shape[1:]) != tail or g.dtype != self.io_dtype() or _batch_stride(g) is None:
+            raise ValueError(f"g must be {self.io_dtype()} [batch, {', '.join(map(str, tail))}] "
+                             "with contiguous signals")
         batch = g.shape[0]
         shape = (batch, self.n_ops, self.n_out) if self.real else (batch, self.n_ops, self.n_out, 2)
         if out is None:
             out = torch.empty(shape, dtype=self.io_dtype(), device=g.device)
-        elif tuple(out.shape) != shape or out.dtype != self.io_dtype() or not out.is_contiguous():
+        elif tuple(out.shape) != shape or out.dtype != self.io_dtype() or _batch_stride(out) is None:
             raise ValueError("bad out tensor")
-        ws, need = self.workspace(batch)
-        mci_reconstruct_1d(self.handle, g.data_ptr(), out.data_ptr(), batch, ws.data_ptr() if ws is not None else 0,
-                           need, _stream_handle(g.device))
+        if g.is_contiguous() and out.is_contiguous():
+            ws, need = self.workspace(batch)
+            mci_reconstruct_1d(self.handle, g.data_ptr(), out.data_ptr(), batch,
+                               ws.data_ptr() if ws is not None else 0, need, _stream_handle(g.device))
+            return out
+        need = mci_workspace_size_strided(self.handle, batch)
+        ws = self._ws.get(need) if need else None
+        mci_reconstruct_1d_strided(self.handle, g.data_ptr(), _batch_stride(g), out.data_ptr(), _batch_stride(out),
+                                   batch, ws.data_ptr() if ws is not None else 0, need, _stream_handle(g.device))
         return out
 
     def close(self):

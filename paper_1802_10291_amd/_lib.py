@@ -69,6 +69,7 @@ class mci_batch_item(ctypes.Structure):
 
 # every symbol the header declares
 EXPORTS = ["mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_plan_kernel_name", "mci_workspace_size", "mci_reconstruct_1d",
+           "mci_reconstruct_1d_strided", "mci_workspace_size_strided",
            "mci_plan_2d", "mci_upsample_2d", "mci_status_string", "mci_last_error", "mci_plan_variants",
            "mci_plan_set_variant", "mci_plan_autotune", "mci_batch_create", "mci_batch_destroy", "mci_batch_sizes",
            "mci_reconstruct_batch", "mci_offgrid_plan", "mci_offgrid_destroy", "mci_offgrid_info",
@@ -106,6 +107,8 @@ def load(path: str = LIB_PATH):
     lib.mci_plan_kernel_name.restype = i32
     lib.mci_workspace_size.argtypes = [vp, i64, P(sz)]
     lib.mci_reconstruct_1d.argtypes = [vp, vp, vp, i64, vp, sz, vp]
+    lib.mci_reconstruct_1d_strided.argtypes = [vp, vp, i64, vp, i64, i64, vp, sz, vp]
+    lib.mci_workspace_size_strided.argtypes = [vp, i64, P(sz)]
     lib.mci_plan_2d.argtypes = [P(mci_plan2d_desc), i32, P(vp)]
     lib.mci_upsample_2d.argtypes = [vp, vp, vp, i64, vp, sz, vp]
     lib.mci_status_string.argtypes = [i32]
@@ -134,6 +137,7 @@ def load(path: str = LIB_PATH):
                  "mci_plan_omega", "mci_averaged_error_noalloc"):
         getattr(lib, name).restype = i32
     for name in ("mci_plan", "mci_plan_destroy", "mci_plan_info", "mci_workspace_size", "mci_reconstruct_1d",
+                 "mci_reconstruct_1d_strided", "mci_workspace_size_strided",
                  "mci_plan_2d", "mci_upsample_2d", "mci_plan_variants", "mci_plan_set_variant", "mci_plan_autotune",
                  "mci_batch_create", "mci_batch_destroy", "mci_batch_sizes", "mci_reconstruct_batch"):
         getattr(lib, name).restype = i32
@@ -179,6 +183,18 @@ def mci_workspace_size(plan: int, batch: int) -> int:
 def mci_reconstruct_1d(plan: int, g_ptr: int, y_ptr: int, batch: int, ws_ptr: int, ws_bytes: int,
                        stream: int) -> None:
     check(load().mci_reconstruct_1d(plan, g_ptr, y_ptr, batch, ws_ptr, ws_bytes, stream), "mci_reconstruct_1d")
+
+
+def mci_workspace_size_strided(plan: int, batch: int) -> int:
+    n = ctypes.c_size_t()
+    check(load().mci_workspace_size_strided(plan, batch, ctypes.byref(n)), "mci_workspace_size_strided")
+    return n.value
+
+
+def mci_reconstruct_1d_strided(plan: int, g_ptr: int, ld_g: int, y_ptr: int, ld_y: int, batch: int, ws_ptr: int,
+                               ws_bytes: int, stream: int) -> None:
+    check(load().mci_reconstruct_1d_strided(plan, g_ptr, ld_g, y_ptr, ld_y, batch, ws_ptr, ws_bytes, stream),
+          "mci_reconstruct_1d_strided")
 
 
 def mci_plan_2d(desc: mci_plan2d_desc, device: int = 0) -> int:

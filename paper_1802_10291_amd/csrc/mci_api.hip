@@ -661,6 +661,52 @@ mci_status mci_reconstruct_1d(mci_plan_t p, const void* g, void* y, int64_t batc
   return plan_run(p, g, y, batch, workspace, nullptr, stream);
 }
 
+// offsets table of a strided call: signal b's samples at b ld_g, its outputs at b ld_y
+__global__ void k_strided_offsets(int64_t* __restrict__ offs, int64_t batch, int64_t ld_g, int64_t ld_y) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch) {
+    offs[2 * b] = b * ld_g;
+    offs[2 * b + 1] = b * ld_y;
+  }
+}
+
+// the run's scratch first (256-byte aligned), then the offsets table
+static size_t ws_1d_strided(const mci_plan_s* p, int64_t batch) {
+  return ((ws_1d(p, batch) + 255) & ~(size_t)255) + (size_t)batch * 2 * sizeof(int64_t) + 256;
+}
+
+mci_status mci_workspace_size_strided(mci_plan_t p, int64_t batch, size_t* bytes) {
+  if (!p || !bytes || batch < 0 || p->dims != 1) return fail(MCI_E_INVALID_ARG, "bad argument");
+  *bytes = batch ? ws_1d_strided(p, batch) : 0;
+  return MCI_OK;
+}
+
+mci_status mci_reconstruct_1d_strided(mci_plan_t p, const void* g, int64_t ld_g, void* y, int64_t ld_y, int64_t batch,
+                                      void* workspace, size_t ws_bytes, hipStream_t stream) {
+  if (!p || p->dims != 1) return fail(MCI_E_INVALID_ARG, "not a 1-D plan");
+  if (batch < 0) return fail(MCI_E_INVALID_ARG, "batch < 0");
+  if (batch == 0) return MCI_OK;
+  if (!g || !y || !workspace) return fail(MCI_E_INVALID_ARG, "NULL data pointer or workspace");
+  if (!aligned16(g) || !aligned16(y) || !aligned16(workspace))
+    return fail(MCI_E_INVALID_ARG, "data pointers and workspace must be 16-byte aligned");
+  const int64_t c = p->d.real_io ? 1 : 2;
+  const int64_t in_elems = p->mu * c, out_elems = p->d.n_out * p->d.n_ops * c;
+  if (ld_g < in_elems || ld_y < out_elems)
+    return fail(MCI_E_INVALID_ARG, "stride smaller than one signal: ld_g >= " + std::to_string(in_elems) +
+                                       ", ld_y >= " + std::to_string(out_elems) + " elements");
+  if (ld_g % 4 || ld_y % 4) return fail(MCI_E_INVALID_ARG, "strides must be multiples of 4 elements");
+  if (batch > ((int64_t)1 << 40) / std::max(ld_g, ld_y)) return fail(MCI_E_INVALID_ARG, "batch too large");
+  const size_t need = ws_1d_strided(p, batch);
+  if (ws_bytes < need) return fail(MCI_E_INVALID_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
+  HIP_TRY(hipSetDevice(p->device));
+  char* base = (char*)workspace;   // 16-byte aligned (checked); the paths align their own scratch
+  int64_t* offs = (int64_t*)(base + ((ws_1d(p, batch) + 255) & ~(size_t)255));
+  hipLaunchKernelGGL(k_strided_offsets, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, stream, offs, batch,
+                     ld_g, ld_y);
+  HIP_TRY(hipGetLastError());
+  return plan_run(p, g, y, batch, base, offs, stream);
+}
+
 mci_status mci_plan_2d(const mci_plan2d_desc* desc, int device, mci_plan_t* out) {
   if (!out) return fail(MCI_E_INVALID_ARG, "out is NULL");
   *out = nullptr;

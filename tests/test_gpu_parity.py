@@ -140,6 +140,46 @@ def test_parity_random_table_multipliers(torch_cuda):
             assert_parity(y, want, TOL[precision])
 
 
+@pytest.mark.parametrize("N,n_out,M,real", [(1366, 16384, 3, True), (1024, 4096, 2, True), (100, 700, 3, True),
+                                           (24, 96, 2, False)])
+def test_strided_batch_matches_dense(torch_cuda, N, n_out, M, real):
+    """mci_reconstruct_1d_strided on signals inside longer rows (a view of g and of y with a
+    batch stride) gives the dense call's outputs bit for bit, on the single-pass, real-mode
+    and multi-pass paths and for complex samples, and leaves the gaps between output rows
+    untouched; strides that are not multiples of 4 or shorter than a signal are rejected."""
+    from paper_1802_10291_amd import MCIError, Plan1D
+    torch = torch_cuda
+    chans = [("deriv", m) for m in range(M)]
+    plan = Plan1D(N=N, n_out=n_out, channels=chans, real=real)
+    c = 1 if real else 2
+    n_in, n_o = M * N * c, n_out * c
+    B = 5
+    rng = np.random.default_rng(N + M)
+    g = torch.from_numpy(rng.standard_normal((B, n_in)).astype(np.float32)).cuda()
+    ld_g = n_in + 4 + (-n_in) % 4
+    ld_y = n_o + 8 + (-n_o) % 4
+    big_g = torch.zeros((B, ld_g), device="cuda")
+    big_g[:, :n_in] = g
+    big_y = torch.full((B, ld_y), float("nan"), device="cuda")
+    tail = (M, N) if real else (M, N, 2)
+    gv = big_g[:, :n_in].unflatten(1, tail)
+    yv = big_y[:, :n_o].unflatten(1, (1, n_out) if real else (1, n_out, 2))
+    assert not gv.is_contiguous() and not yv.is_contiguous()
+    plan.reconstruct(gv, out=yv)
+    dense = plan.reconstruct(g.unflatten(1, tail).contiguous())
+    assert torch.equal(yv, dense)
+    assert torch.isnan(big_y[:, n_o:]).all()
+    with pytest.raises(MCIError):
+        plan.reconstruct(big_g[:, : n_in].unflatten(1, tail), out=big_y[:, 2: n_o + 2].unflatten(
+            1, (1, n_out) if real else (1, n_out, 2)))      # misaligned output start
+    from paper_1802_10291_amd import _lib as L
+    ws = torch.empty(L.mci_workspace_size_strided(plan.handle, B) + 64, dtype=torch.uint8, device="cuda")
+    for bad_g, bad_y in ((ld_g + 2, ld_y), (ld_g, n_o - 4)):
+        with pytest.raises(MCIError):
+            L.mci_reconstruct_1d_strided(plan.handle, big_g.data_ptr(), bad_g, big_y.data_ptr(), bad_y, B,
+                                         ws.data_ptr(), ws.numel(), 0)
+
+
 def test_parity_f16_storage(torch_cuda):
     y, want, _ = run_case(torch_cuda, 64, 256, [("deriv", 0), ("deriv", 1)], storage="f16", batch=4, seed=3)
     assert_parity(y, want, TOL["f16"])

@@ -100,8 +100,10 @@ def test_null_arguments_rejected():
     assert lib.mci_plan(None, 0, None) == 1
     assert lib.mci_plan_destroy(None) == 0
     assert lib.mci_reconstruct_1d(None, None, None, 1, None, 0, None) == 1
+    assert lib.mci_reconstruct_1d_strided(None, None, 0, None, 0, 1, None, 0, None) == 1
     n = ctypes.c_size_t()
     assert lib.mci_workspace_size(None, 1, ctypes.byref(n)) == 1
+    assert lib.mci_workspace_size_strided(None, 1, ctypes.byref(n)) == 1
 
 
 def test_batch_and_tuner_structs_match_c_layout():
