@@ -18,7 +18,7 @@ own time, output px/s, roofline, oracle baseline, errors and PSNR (--no-2d skips
 
   python bench.py [--steps K] [--warmup W] [--workload batched1d|sisr2|sisr4|sisr3|refiner|uneven|offgrid|errsel]
                   [--no-cpu]
-                  [--storage f32|f16] [--lanes 8]
+                  [--storage f32|f16] [--lanes 16]
 """
 import argparse
 import json
@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--workload", default="batched1d",
                     choices=["batched1d", "sisr2", "sisr4", "sisr3", "refiner", "uneven", "offgrid", "errsel"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16"], help="uneven: storage of the packed buffers")
-    ap.add_argument("--lanes", type=int, default=8, help="uneven: concurrent lanes of the batch")
+    ap.add_argument("--lanes", type=int, default=16, help="uneven: concurrent lanes of the batch")
     ap.add_argument("--pairs", type=int, default=20000, help="refiner: training pairs")
     ap.add_argument("--epochs", type=int, default=3, help="refiner: training epochs")
     ap.add_argument("--batch", type=int, default=0, help="override the batch size (0 = workload default)")

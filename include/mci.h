@@ -273,7 +273,7 @@ typedef struct mci_batch_s* mci_batch_t;
 
 /* mci_batch_create -- group the items by plan (one size class per distinct plan), upload
  * one device table of (in_off, out_off) per class, and spread the classes over `lanes`
- * streams (1..8; 0 => 8) by estimated bytes, largest first.  All plans must live on one
+ * streams (1..16; 0 => 16) by estimated bytes, largest first.  All plans must live on one
  * device, share one element type (FP32, FP16 or FP64 storage) and outlive the batch.
  * Offsets are >= 0 and multiples of 4 elements (vector access); output extents must not
  * overlap.  Each instance's layout inside its extent is the single-instance layout of

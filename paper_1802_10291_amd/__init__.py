@@ -382,7 +382,7 @@ class Batch:
     rounded up to ``align`` elements, in the order given (or pass explicit offsets).
     """
 
-    def __init__(self, instances: Sequence, lanes: int = 8, align: int = 64, offsets=None):
+    def __init__(self, instances: Sequence, lanes: int = 16, align: int = 64, offsets=None):
         self.plans = list(instances)
         if offsets is None:
             ins, outs, i, o = [], [], 0, 0

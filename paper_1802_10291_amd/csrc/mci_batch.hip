@@ -308,8 +308,8 @@ mci_status mci_batch_create(const mci_batch_item* items, int64_t n_items, int la
   if (!out) return fail(MCI_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (n_items < 0 || (n_items > 0 && !items)) return fail(MCI_E_INVALID_ARG, "bad item list");
-  if (lanes < 0 || lanes > 8) return fail(MCI_E_INVALID_ARG, "lanes must be in 0..8");
-  if (lanes == 0) lanes = 8;
+  if (lanes < 0 || lanes > 16) return fail(MCI_E_INVALID_ARG, "lanes must be in 0..16");
+  if (lanes == 0) lanes = 16;
   mci_batch_s* b = new (std::nothrow) mci_batch_s();
   if (!b) return fail(MCI_E_OUT_OF_MEMORY, "batch");
   std::map<mci_plan_s*, size_t> index;

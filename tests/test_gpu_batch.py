@@ -223,7 +223,7 @@ MIX = [("1d", (1366, 3, 16384)), ("1d", (1000, 3, 16384)), ("1d", (86, 3, 1024))
        ("1d", (128, 2, 1024)), ("2d", (64, 2)), ("2d", (48, 2)), ("2d", (40, 2))]   # 40: no line pass, multi-pass 2-D
 
 
-def _mixed_batch(torch, storage="native", lanes=8, seed=0, per_class=3):
+def _mixed_batch(torch, storage="native", lanes=16, seed=0, per_class=3):
     from paper_1802_10291_amd import Batch, Plan1D, Plan2D
     np_dt = np.float16 if storage == "f16" else np.float32
     f16 = storage == "f16"
@@ -257,9 +257,9 @@ def _unpack(batch, plans, order, out_host):
     return res
 
 
-@pytest.mark.parametrize("storage,lanes,merged", [("native", 8, False), ("native", 4, False), ("native", 1, False),
-                                                  ("f16", 8, False), ("native", 8, True), ("native", 1, True),
-                                                  ("f16", 8, True)])
+@pytest.mark.parametrize("storage,lanes,merged", [("native", 16, False), ("native", 4, False), ("native", 1, False),
+                                                  ("f16", 16, False), ("native", 16, True), ("native", 1, True),
+                                                  ("f16", 16, True)])
 def test_uneven_batch_matches_single_calls_and_oracle(torch_cuda, monkeypatch, storage, lanes, merged):
     """Each class's own launches on the lanes, or (merged) persistent launches over job tables
     for the classes whose kernels record as jobs: both bit-identical to single-plan calls."""
@@ -299,13 +299,13 @@ def test_uneven_batch_matches_single_calls_and_oracle(torch_cuda, monkeypatch, s
 
 @pytest.mark.parametrize("merged", [False, True])
 def test_uneven_batch_graph_capture_replays(torch_cuda, monkeypatch, merged):
-    """The whole mixed batch (eight lanes forked from and joined into the capture stream) is
+    """The whole mixed batch (16 lanes forked from and joined into the capture stream) is
     captured as one graph; each replay, with eager work and new input values in between,
     reproduces the eager result for the current input."""
     torch = torch_cuda
     if merged:
         monkeypatch.setenv("MCI_BATCH_MERGED", "1")
-    batch, plans, data, order, packed = _mixed_batch(torch, "native", 8)
+    batch, plans, data, order, packed = _mixed_batch(torch, "native", 16)
     monkeypatch.delenv("MCI_BATCH_MERGED", raising=False)
     dev_in = torch.from_numpy(packed).cuda()
     out = torch.zeros(batch.out_elems, dtype=torch.float32, device="cuda")
