@@ -14,13 +14,16 @@ dominant kernel (timed with HIP events on its stream) and the FP64 CPU oracle on
 bounded sample of the same workload, plus the relative error of that sample.  The
 default line also carries the metric's 2-D part under "sisr2" and "sisr4": 256
 grayscale images upsampled x2 (256^2 -> 512^2) and x4 (128^2 -> 512^2), each with its
-own time, output px/s, roofline, oracle baseline, errors and PSNR (--no-2d skips them).
+own time, output px/s, roofline, oracle baseline, errors and PSNR (--no-2d skips them),
+and, outside the metric, the uneven batch under "uneven" (4096 mixed 1-D and 2-D instances
+in one graph launch, with its oracle check; --no-uneven skips it).
 
   python bench.py [--steps K] [--warmup W] [--workload batched1d|sisr2|sisr4|sisr3|refiner|uneven|offgrid|errsel]
                   [--no-cpu]
                   [--storage f32|f16] [--lanes 16]
 """
 import argparse
+import copy
 import json
 import os
 import sys
@@ -68,6 +71,8 @@ def parse():
                     help="write profiles/mci1d_batched_fp32_traffic.json from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--no-2d", action="store_true",
                     help="batched1d: skip the 2-D x2 and x4 workloads that the default line also carries")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="batched1d: skip the uneven-batch workload that the default line also carries")
     ap.add_argument("--cpu-sample", type=int, default=0, help="signals/images in the CPU sample (0 = default)")
     return ap.parse_args()
 
@@ -759,7 +764,6 @@ def main():
         if not args.no_2d:
             # the metric's 2-D part: x2 and x4 on 256 images each, same steps and warm-up, each
             # with its own roofline, oracle baseline, errors and PSNR
-            import copy
             sub = copy.copy(args)
             sub.batch = 0
             sub.cpu_sample = 0
@@ -771,6 +775,22 @@ def main():
                             "data"):
                     r2.pop(key, None)
                 res[f"sisr{s}"] = r2
+        if not args.no_uneven:
+            # not part of the metric: the uneven batch, measured in the same run; a failure
+            # here is recorded in the line instead of losing the line
+            sub = copy.copy(args)
+            sub.batch = 0
+            sub.cpu_sample = 0
+            log("uneven-batch workload")
+            try:
+                ru = bench_uneven(sub, torch)
+                _extrapolate_cpu(ru)
+                for key in ("metric", "n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline",
+                            "data", "classes"):
+                    ru.pop(key, None)   # the per-class table stays in the standalone run's line
+                res["uneven"] = ru
+            except Exception as e:  # noqa: BLE001
+                res["uneven"] = {"error": f"{type(e).__name__}: {e}"}
     elif args.workload == "refiner":
         res = bench_refiner(args, torch)
     elif args.workload == "uneven":
