@@ -16,7 +16,8 @@ default line also carries the metric's 2-D part under "sisr2" and "sisr4": 256
 grayscale images upsampled x2 (256^2 -> 512^2) and x4 (128^2 -> 512^2), each with its
 own time, output px/s, roofline, oracle baseline, errors and PSNR (--no-2d skips them),
 and, outside the metric, the uneven batch under "uneven" (4096 mixed 1-D and 2-D instances
-in one graph launch, with its oracle check; --no-uneven skips it).
+in one graph launch, with its oracle check; --no-uneven skips it) and the refiner's forward
+throughput under "refiner_forward" (initial weights; --no-refiner skips it).
 
   python bench.py [--steps K] [--warmup W] [--workload batched1d|sisr2|sisr4|sisr3|refiner|uneven|offgrid|errsel]
                   [--no-cpu]
@@ -73,6 +74,8 @@ def parse():
                     help="batched1d: skip the 2-D x2 and x4 workloads that the default line also carries")
     ap.add_argument("--no-uneven", action="store_true",
                     help="batched1d: skip the uneven-batch workload that the default line also carries")
+    ap.add_argument("--no-refiner", action="store_true",
+                    help="batched1d: skip the refiner forward throughput that the default line also carries")
     ap.add_argument("--cpu-sample", type=int, default=0, help="signals/images in the CPU sample (0 = default)")
     return ap.parse_args()
 
@@ -694,19 +697,24 @@ def bench_uneven(args, torch):
     return result
 
 
-def bench_refiner(args, torch):
+def bench_refiner(args, torch, train=True):
     """Refiner workload: train on method-generated pairs, then time MCI alone and MCI + CNN on
-    RGB 512 x 512 images upsampled x2 from 256 x 256, and report the PSNR gain."""
+    RGB 512 x 512 images upsampled x2 from 256 x 256, and report the PSNR gain.  train=False:
+    the throughput only, on the initial weights (the kernels and their work do not depend on
+    the weights' values), without training, PSNR or fallback."""
     from paper_1802_10291_amd import Plan2D, Refiner, upsample_rgb
     from paper_1802_10291_amd import refiner_train as RT
 
     r = Refiner(seed=0)
-    t_train = time.perf_counter()
-    hist, tau = RT.train(r, n_pairs=args.pairs, batch=16, size=512, lr=1e-3, epochs=args.epochs, log=log)
-    t_train = time.perf_counter() - t_train
+    hist, tau, t_train = [], None, 0.0
+    p_mci = p_ref = frac = None
     n_eval = 512
-    p_mci, p_ref, frac = RT.evaluate(r, n_images=n_eval, size=512)
-    log(f"held-out PSNR over {n_eval} images: MCI {p_mci:.3f} dB, MCI + CNN {p_ref:.3f} dB, refined {frac:.2f}")
+    if train:
+        t_train = time.perf_counter()
+        hist, tau = RT.train(r, n_pairs=args.pairs, batch=16, size=512, lr=1e-3, epochs=args.epochs, log=log)
+        t_train = time.perf_counter() - t_train
+        p_mci, p_ref, frac = RT.evaluate(r, n_images=n_eval, size=512)
+        log(f"held-out PSNR over {n_eval} images: MCI {p_mci:.3f} dB, MCI + CNN {p_ref:.3f} dB, refined {frac:.2f}")
     B = args.batch or 64
     hr_dev = RT.gpu_rgb_images([7_000_000 + i for i in range(min(B, 16))], 512)
     hr_dev = hr_dev.repeat((B + hr_dev.shape[0] - 1) // hr_dev.shape[0], 1, 1, 1)[:B].contiguous()
@@ -720,7 +728,7 @@ def bench_refiner(args, torch):
 
     def step():
         upsample_rgb(plan, lr_img, out=u)
-        r.forward(u, fallback=True, out=y)
+        r.forward(u, fallback=train, out=y)
 
     wall, per = time_steps(torch, step, args.steps, args.warmup, stream)
     ms = float(np.mean(per))
@@ -731,16 +739,17 @@ def bench_refiner(args, torch):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16", "data": "synthetic",
         "config": {"workload": f"MCI x2 (256^2 -> 512^2, RGB) + residual CNN refiner (4 conv3x3, 32 ch, BF16 MFMA), "
-                               f"trained on {args.pairs} method-generated 512^2 RGB pairs x {args.epochs} epochs, "
-                               f"PSNR on {n_eval} held-out 512^2 images",
+                               + (f"trained on {args.pairs} method-generated 512^2 RGB pairs x {args.epochs} epochs, "
+                                  f"PSNR on {n_eval} held-out 512^2 images" if train else
+                                  "initial weights, throughput only (--workload refiner trains and scores it)"),
                    "batch": B},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": achieved / 2500.0, "traffic": None, "kernel": "refiner forward (4 conv layers)"},
         "images_per_s": {"mci": B / (ms_mci * 1e-3), "mci_plus_cnn": B / (ms * 1e-3)},
         "psnr_db": {"mci": p_mci, "mci_plus_cnn": p_ref, "gain": p_ref - p_mci, "images": n_eval,
-                    "refined_fraction": frac},
+                    "refined_fraction": frac} if train else None,
         "training": {"pairs": args.pairs, "size": 512, "epochs": args.epochs, "steps": args.epochs * (args.pairs // 16),
-                     "seconds": t_train},
+                     "seconds": t_train} if train else None,
         "fallback_tau": tau, "train_loss": hist[-1][1] if hist else None, "wall_s": wall,
     }
 
@@ -791,6 +800,20 @@ def main():
                 res["uneven"] = ru
             except Exception as e:  # noqa: BLE001
                 res["uneven"] = {"error": f"{type(e).__name__}: {e}"}
+        if not args.no_refiner:
+            # not part of the metric: the refiner's forward throughput at batch 64 (MCI x2 + CNN on
+            # 512^2 RGB images); training and PSNR are --workload refiner's
+            sub = copy.copy(args)
+            sub.batch = 0
+            log("refiner forward (throughput only)")
+            try:
+                rr = bench_refiner(sub, torch, train=False)
+                for key in ("metric", "n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline",
+                            "data", "psnr_db", "training", "fallback_tau", "train_loss"):
+                    rr.pop(key, None)
+                res["refiner_forward"] = rr
+            except Exception as e:  # noqa: BLE001
+                res["refiner_forward"] = {"error": f"{type(e).__name__}: {e}"}
     elif args.workload == "refiner":
         res = bench_refiner(args, torch)
     elif args.workload == "uneven":
