@@ -83,18 +83,26 @@ __device__ __forceinline__ void line_pass_body(const LinePassArgs& a, int64_t bx
   // when W is a multiple of 4)
   if constexpr (COLS) {
     // row n of image img, columns col0 .. col0 + 31: 32 contiguous values per row
+    // (FP16 inputs likewise as four halves in 8 bytes)
     bool vec = false;
     if constexpr (std::is_same<TI, float>::value) vec = ((xoff | a.W) & 3) == 0 && ((uintptr_t)x & 15) == 0;
+    else vec = ((xoff | a.W) & 3) == 0 && ((uintptr_t)x & 7) == 0;
     if (vec) {
       for (int e4 = tid; e4 < N * LINES / 4; e4 += NT) {
         const int n = e4 / (LINES / 4), c = 4 * (e4 % (LINES / 4));
         const int64_t col = col0 + c;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (col < a.W) {
-          // read once (non-temporal), or kept for the rows pass, which reads the sample rows again
-          const f4_nt* src = (const f4_nt*)((const float*)x + xoff + n * (int64_t)a.W + col);
-          const f4_nt t = ZR ? *src : __builtin_nontemporal_load(src);
-          v = make_float4(t.x, t.y, t.z, t.w);
+          if constexpr (std::is_same<TI, float>::value) {
+            // read once (non-temporal), or kept for the rows pass, which reads the sample rows again
+            const f4_nt* src = (const f4_nt*)((const float*)x + xoff + n * (int64_t)a.W + col);
+            const f4_nt t = ZR ? *src : __builtin_nontemporal_load(src);
+            v = make_float4(t.x, t.y, t.z, t.w);
+          } else {
+            const uint2 raw = *(const uint2*)((const TI*)x + xoff + n * (int64_t)a.W + col);
+            const float2 lo = __half22float2(*(const __half2*)&raw.x), hi = __half22float2(*(const __half2*)&raw.y);
+            v = make_float4(lo.x, lo.y, hi.x, hi.y);
+          }
         }
         tile[c * TS + n] = v.x;
         tile[(c + 1) * TS + n] = v.y;
@@ -213,6 +221,15 @@ __device__ __forceinline__ void line_pass_body(const LinePassArgs& a, int64_t bx
         } else if constexpr (std::is_same<TO, float>::value && SC == 2) {
           const f2_nt t = {o[0], o[1]};
           __builtin_nontemporal_store(t, (f2_nt*)(yl + 2 * q));
+        } else if constexpr (std::is_same<TO, __half>::value && SC == 4) {
+          // FP16 rows: the s outputs of a position as one 8-byte (s = 4) or 4-byte (s = 2) store
+          const __half2 h0 = __floats2half2_rn(o[0], o[1]), h1 = __floats2half2_rn(o[2], o[3]);
+          uint2 raw;
+          __builtin_memcpy(&raw.x, &h0, 4);
+          __builtin_memcpy(&raw.y, &h1, 4);
+          *(uint2*)(yl + 4 * q) = raw;
+        } else if constexpr (std::is_same<TO, __half>::value && SC == 2) {
+          *(__half2*)(yl + 2 * q) = __floats2half2_rn(o[0], o[1]);
         } else {
 #pragma unroll
           for (int r = 0; r < SC; ++r) st_as<float>(yl, (int64_t)SC * q + r, o[r]);

@@ -375,6 +375,21 @@ def test_2d_sample_rows_passed_through(torch_cuda, monkeypatch, h, w, s, M):
     assert np.abs(a[:, ::s, ::s] - lr).max() <= 1e-5
 
 
+@pytest.mark.parametrize("h,w,s", [(256, 256, 2), (128, 128, 4), (64, 96, 3), (48, 32, 2), (96, 64, 4)])
+def test_2d_f16_storage(torch_cuda, h, w, s):
+    """FP16 images in and out (FP32 arithmetic): the columns pass reads four halves per load
+    and the rows pass writes a position's s outputs in one store (s = 2, 4); against the
+    oracle on the FP16-rounded input, within FP16's output rounding."""
+    from paper_1802_10291_amd import Plan2D
+    lr = SI.random_field_images(51 + s, 3, h, w).astype(np.float16)
+    plan = Plan2D(h, w, s, storage="f16")
+    assert plan.info.path == 1
+    hr = plan.upsample(torch_cuda.from_numpy(lr).cuda())
+    assert hr.dtype == torch_cuda.float16
+    hr = hr.cpu().numpy().astype(np.float64)
+    check_rows(hr, O.upsample_2d(lr.astype(np.float64), s), TOL["f16"])
+
+
 def test_2d_three_channels_fp64_exact(torch_cuda):
     from paper_1802_10291_amd import Plan2D
     lr = SI.random_field_images(22, 2, 30, 36).astype(np.float64)
