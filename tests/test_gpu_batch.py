@@ -69,6 +69,23 @@ def test_fused_f16_storage_parity(torch_cuda, N, n_out, M):
         assert rel(y[b], want[b]) <= 1e-3
 
 
+def test_strided_batch_f16_storage(torch_cuda):
+    """The strided call (mci_reconstruct_1d_strided) with FP16 samples and outputs on the
+    single-pass kernel: bit-identical to the dense call, the gaps between rows untouched."""
+    from paper_1802_10291_amd import Plan1D
+    torch = torch_cuda
+    N, n_out, M, B = 1366, 16384, 3, 4
+    g = torch.from_numpy(S.smooth_noisy_batch(0, B, M, N, 2 * N, dtype=np.float16, deriv_scale=N)).cuda()
+    plan = Plan1D(N=N, n_out=n_out, channels=[("table", t) for t in scaled_deriv_tables(M, N)], storage="f16")
+    big = torch.zeros((B, M * N + 6), dtype=torch.float16, device="cuda")
+    big[:, : M * N] = g.reshape(B, -1)
+    out = torch.zeros((B, n_out + 8), dtype=torch.float16, device="cuda")
+    yv = out[:, :n_out].unflatten(1, (1, n_out))
+    plan.reconstruct(big[:, : M * N].unflatten(1, (M, N)), out=yv)
+    assert torch.equal(yv, plan.reconstruct(g))
+    assert (out[:, n_out:] == 0).all()
+
+
 # ------------------------------------------------------------------ variants
 def test_every_1d_variant_matches_oracle(torch_cuda):
     from paper_1802_10291_amd import Plan1D
