@@ -36,6 +36,7 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstdlib>
+#include <cstring>
 #include <complex>
 #include <vector>
 
@@ -312,6 +313,16 @@ __device__ __forceinline__ float2 ld_pair(const __half* r, int p) {
   __builtin_memcpy(&h, &u, sizeof h);
   return __half22float2(h);
 }
+// odd N: sample p as a complex value with zero imaginary part
+__device__ __forceinline__ float2 ld_real(const float* r, int p) {
+  return make_float2(__builtin_nontemporal_load(r + p), 0.f);
+}
+__device__ __forceinline__ float2 ld_real(const __half* r, int p) {
+  const unsigned short u = __builtin_nontemporal_load((const unsigned short*)r + p);
+  __half h;
+  __builtin_memcpy(&h, &u, sizeof h);
+  return make_float2(__half2float(h), 0.f);
+}
 __device__ __forceinline__ void st_pair(float* y, int q, float2 v) { ((float2*)y)[q] = v; }
 __device__ __forceinline__ void st_pair(__half* y, int q, float2 v) { ((__half2*)y)[q] = __float22half2_rn(v); }
 __device__ __forceinline__ void st_quad(float* y, int q, float2 lo, float2 hi) {
@@ -327,8 +338,12 @@ __device__ __forceinline__ void st_quad(__half* y, int q, float2 lo, float2 hi) 
 
 // TI: how many of the Q/2 output transforms run side by side (1 or Q/2).  TS: storage type
 // of the samples and outputs (float or __half); all arithmetic is FP32.
-template <int PF, int BLUE, int P, int Q, int M, int TI, typename TS>
+// BLUE_ 3 and 4: the forms 1 and 2 for odd N, whose channel DFT is the length-N transform of
+// the real samples themselves (H = N, X = Z): no even/odd recovery
+template <int PF, int BLUE_, int P, int Q, int M, int TI, typename TS>
 __device__ __forceinline__ void fused_body(const FusedArgs& a, int64_t sig_index) {
+  constexpr bool ODD = BLUE_ >= 3;
+  constexpr int BLUE = ODD ? BLUE_ - 2 : BLUE_;
   extern __shared__ float2 sm[];
   constexpr int EF = PF / NT, EI = P / NT;
   const int tid = threadIdx.x;
@@ -355,7 +370,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, int64_t sig_index
         for (int c = 0; c < EF; ++c) {
           const int p = tid + NT * c;
           float2 z = make_float2(0.f, 0.f);
-          if (p < H) z = ld_pair(zin, p);
+          if (p < H) z = ODD ? ld_real(zin, p) : ld_pair(zin, p);
           v[m][c] = z;
         }
       }
@@ -477,20 +492,29 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, int64_t sig_index
       // i' has r' = (N - r) mod N, so its value is the conjugate (the channels are real).
       int r = a.n1r + i;                        // (n1 + i) mod N, 0 <= i < N
       if (r >= N) r -= N;
-      const bool lo = r <= H;
-      const int k = lo ? r : N - r;
-      const int k1 = k == H ? 0 : k, k2 = k == 0 ? 0 : H - k;
-      const float2 wn = a.wN[k];
       // d = 2 X_m (the halves of E and O are folded into the final scale of S)
       float2 d[M];
+      if constexpr (ODD) {
+        // odd N: the spectrum holds every residue
 #pragma unroll
-      for (int m = 0; m < M; ++m) {
-        const float2 z1 = Zc[m * XH + k1];
-        const float2 z2 = conjf2(Zc[m * XH + k2]);
-        const float2 e = make_float2(z1.x + z2.x, z1.y + z2.y);
-        const float2 o = make_float2(z1.y - z2.y, z2.x - z1.x);   // (z1 - z2) / i
-        const float2 x = cadd(e, cmul(wn, o));
-        d[m] = lo ? x : conjf2(x);
+        for (int m = 0; m < M; ++m) {
+          const float2 x = Zc[m * XH + r];
+          d[m] = make_float2(2.f * x.x, 2.f * x.y);
+        }
+      } else {
+        const bool lo = r <= H;
+        const int k = lo ? r : N - r;
+        const int k1 = k == H ? 0 : k, k2 = k == 0 ? 0 : H - k;
+        const float2 wn = a.wN[k];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          const float2 z1 = Zc[m * XH + k1];
+          const float2 z2 = conjf2(Zc[m * XH + k2]);
+          const float2 e = make_float2(z1.x + z2.x, z1.y + z2.y);
+          const float2 o = make_float2(z1.y - z2.y, z2.x - z1.x);   // (z1 - z2) / i
+          const float2 x = cadd(e, cmul(wn, o));
+          d[m] = lo ? x : conjf2(x);
+        }
       }
       // table entries Tab[m][j][.] at residues i and i': one byte offset per residue, the
       // row offsets (m M + j) N are uniform
@@ -753,7 +777,8 @@ using PrepFn = hipError_t (*)(int, int, const int*);
 
 struct Variant {
   int PF;
-  int blue;   // 0: power-of-two H = PF; 1: Bluestein, PF >= 2H - 1; 2: split Bluestein, PF >= H + ceil(H/2) - 1
+  int blue;   // 0: power-of-two H = PF; 1: Bluestein, PF >= 2H - 1; 2: split Bluestein, PF >= H + ceil(H/2) - 1;
+              // 3, 4: forms 1 and 2 for odd N (H = N, the real samples as a length-N complex sequence)
   int P, Q;
   LaunchFn fn;
   PrepFn prep;
@@ -776,6 +801,9 @@ static const Variant kVariants[] = {
     MCI_FV(512, 1, 2048, 4), MCI_FV(512, 1, 1024, 2), MCI_FV(512, 1, 3072, 2), MCI_FV(1024, 1, 3072, 2),
     // 1024- and 3072-point outputs as one transform of 512 or 1536 points
     MCI_FV(512, 1, 512, 2), MCI_FV(512, 1, 1536, 2),
+    // odd N: Bluestein at 512 for N <= 256 with 2048-point outputs, split Bluestein at 1024 for
+    // 512 < N <= 683 with 8192- and 16384-point outputs
+    MCI_FV(512, 3, 1024, 2), MCI_FV(512, 3, 2048, 4), MCI_FV(1024, 4, 2048, 4), MCI_FV(1024, 4, 4096, 4),
 };
 #undef MCI_FV
 
@@ -785,16 +813,21 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   if (prec != MCI_F32 || (store != ST_F32 && store != ST_F16) || !d.real_io || d.n_ops != 1 || d.M > MCI_MAX_CHANNELS) return MCI_OK;
   if (std::getenv("MCI_DISABLE_FUSED")) return MCI_OK;
   const int64_t N = d.N, M = d.M, n1 = d.n1, mu = M * N;
-  if (N % 2 || N < 4 || N > (1 << 15) || d.n_out > (1 << 20)) return MCI_OK;
-  const int64_t H = N / 2;
+  if (N < 4 || N > (1 << 15) || d.n_out > (1 << 20)) return MCI_OK;
+  // even N: the channel DFT through the half-length transform of sample pairs; odd N: the
+  // length-N transform of the real samples (Bluestein forms 3 and 4 only)
+  const bool odd = N % 2 != 0;
+  const int64_t H = odd ? N : N / 2;
   const int64_t K = std::max<int64_t>(std::llabs(n1), std::llabs(n1 + mu - 1));
   const Variant* pick = nullptr;
   for (const Variant& v : kVariants) {
     // (a power-of-two H also takes Bluestein where no plain form fits: the smallest PF wins,
     // and the plain form, PF = H, is always smaller than a chirp convolution's)
-    const bool fwd_ok = v.blue == 0 ? H == v.PF
-                : v.blue == 1 ? 2 * H - 1 <= v.PF
-                              : H + (H + 1) / 2 - 1 <= v.PF;
+    if ((v.blue >= 3) != odd) continue;
+    const int bl = v.blue >= 3 ? v.blue - 2 : v.blue;
+    const bool fwd_ok = bl == 0 ? H == v.PF
+                : bl == 1 ? 2 * H - 1 <= v.PF
+                          : H + (H + 1) / 2 - 1 <= v.PF;
     if (!fwd_ok || (int64_t)v.P * v.Q != d.n_out) continue;
     if (!pick || v.PF < pick->PF) pick = &v;
   }
@@ -822,7 +855,8 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   // tables (FP64 on the host, stored FP32)
   const int PF = pick->PF, P = pick->P;
   const int Q = pick->Q;
-  std::vector<std::complex<double>> twF(PF), chirp(H), bhat((size_t)(pick->blue == 2 ? 2 : 1) * PF, 0.0), wN(H + 1),
+  const int blue = pick->blue >= 3 ? pick->blue - 2 : pick->blue;   // the Bluestein form, odd N or not
+  std::vector<std::complex<double>> twF(PF), chirp(H), bhat((size_t)(blue == 2 ? 2 : 1) * PF, 0.0), wN(H + 1),
       twI(P), U((size_t)(Q / 2) * (2 * K + 1)), Ub((size_t)(Q / 2) * P, 0.0);
   for (int k = 0; k < PF; ++k) twF[k] = root_of_unity(k, PF);
   for (int64_t k = 0; k <= H; ++k) wN[k] = root_of_unity(k, N);
@@ -840,11 +874,11 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
       const int64_t k = b <= K ? b : (b >= P - K ? b - P : INT64_MIN);
       if (k != INT64_MIN) Ub[(size_t)pc * P + b] = U[(size_t)pc * (2 * K + 1) + (k + K)];
     }
-  if (pick->blue) {
+  if (blue) {
     for (int64_t k = 0; k < H; ++k) chirp[k] = chirp_value(k, H, -1);
     std::vector<int> rad;
     for (int64_t r = PF; r > 1; r /= 8) rad.push_back(r >= 8 ? 8 : (int)r);
-    if (pick->blue == 1) {
+    if (blue == 1) {
       // the kernel b[n] = conj c[|n|], |n| < H, placed circularly
       for (int64_t m = 0; m < H; ++m) {
         bhat[m] = std::conj(chirp[m]);
@@ -907,7 +941,8 @@ mci_status fused_select(const mci_plan_desc& d, int prec, int store, const void*
   const int per_cu = std::max<int>(1, (int)((160 * 1024) / std::max<int64_t>(lds, 1)));
   fp.grid_cap = std::max(1, cus) * std::min(per_cu, 8);
   std::snprintf(fp.name, sizeof fp.name, "k_mci1d_fused: forward %s %d-point, output %d x %d-point, M=%d",
-                pick->blue == 2 ? "split-Bluestein" : pick->blue == 1 ? "Bluestein" : "direct", PF, Q / 2, P, (int)M);
+                blue == 2 ? "split-Bluestein" : blue == 1 ? "Bluestein" : "direct", PF, Q / 2, P, (int)M);
+  if (odd) std::snprintf(fp.name + std::strlen(fp.name), sizeof fp.name - std::strlen(fp.name), ", odd N");
   fp.kind = 1;
   return MCI_OK;
 }

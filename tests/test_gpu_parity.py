@@ -180,6 +180,19 @@ def test_strided_batch_matches_dense(torch_cuda, N, n_out, M, real):
                                          ws.data_ptr(), ws.numel(), 0)
 
 
+@pytest.mark.parametrize("N,n_out,M,n1", [(171, 2048, 3, None), (683, 8192, 3, None), (683, 16384, 3, None),
+                                          (601, 8192, 2, None), (171, 2048, 2, -100), (255, 8192, 4, None)])
+def test_fused_odd_n_parity(torch_cuda, N, n_out, M, n1):
+    """Odd N on the single-pass kernel: the channel DFT is the length-N transform of the real
+    samples (Bluestein at 512 or split Bluestein at 1024), with no even/odd recovery; against
+    the oracle element by element at 1e-5, and against the multi-kernel path."""
+    from paper_1802_10291_amd import Plan1D
+    chans = [("deriv", m) for m in range(M)]
+    y, want, plan = run_case(torch_cuda, N, n_out, chans, n1=n1, seed=N + M)
+    assert plan.info.path == 1 and "odd N" in plan.kernel_name(), plan.kernel_name()
+    assert_parity(y, want, TOL["f32"])
+
+
 def test_parity_f16_storage(torch_cuda):
     y, want, _ = run_case(torch_cuda, 64, 256, [("deriv", 0), ("deriv", 1)], storage="f16", batch=4, seed=3)
     assert_parity(y, want, TOL["f16"])
